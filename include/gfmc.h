@@ -1,0 +1,211 @@
+/*
+ * gfmc.h -- C ABI of the MI355X (gfx950) library for the O(N) Green-function-
+ * based Monte Carlo (GFMC) method on the 3D double-exchange model (Zhang,
+ * Yamagiwa, Yunoki, arXiv:1303.6016).
+ *
+ * What the library computes (Section 2 of the paper):
+ *   model   H = -t sum_<ij> t_ij c_i^+ c_j + h.c. in the infinite-Hund limit,
+ *           t_ij from the polar/azimuthal angles of the classical spins
+ *           (equation "ht"), periodic L x L x L simple cubic lattice;
+ *   moments mu_n^{jk} = <j|T_n(Ht)|k> of Ht = (H - b)/a for the 7 sites touched
+ *           by a local spin change (site o and its 6 neighbours), from M/2 steps
+ *           of the three-term recursion (equation "recursive") with moment
+ *           doubling (equation "mu2");
+ *   Delta S_eff from the kernel-damped local Green's functions (equations
+ *           "green", "green_short"/"green_fft"), the 2x2 determinant
+ *           (equation "d_z_green") and the Fermi-weighted phase integral
+ *           (equation "d_seff2");
+ *   Metropolis sweeps of Algorithm 1 with the magnetization |sum_i S_i|/N.
+ *
+ * Conventions:
+ *   site index      i = x + L*(y + L*z)
+ *   directions      d = 0..5 : +x, -x, +y, -y, +z, -z
+ *   start labels    j = 0..6 : o, then the neighbour of o in direction j-1
+ *   moment layout   mu[n][j][k][2] (re, im), n = 0..M-1, row-major, FP64
+ *   random numbers  Philox4x64-10, key (seed, chain_id); counter
+ *                   (sweep*N + j, 1, 0, 0) for proposal j of a sweep,
+ *                   (i, 2, 0, 0) for the initial spin of site i,
+ *                   (k, 3, 0, 0) for the k-th pick of randomised sites.
+ *
+ * Ownership: the caller allocates and owns all host arrays, all device memory
+ * (the workspace passed to gfmc_chain_create / gfmc_batch_create) and the HIP
+ * stream.  The library copies host inputs, writes only into caller buffers,
+ * and owns only the opaque handles.  Destroying a handle never frees caller
+ * memory.
+ *
+ * Errors: every entry point returns gfmc_status and never throws or aborts.
+ * Invalid input returns GFMC_EINVAL with the state unchanged; the reason is
+ * available from gfmc_last_error() (thread-local).  HIP failures return
+ * GFMC_EDEVICE.
+ *
+ * Asynchrony: device work is enqueued on the handle's stream.  Calls that
+ * return host data (moments, delta_seff, step records, spins, sweep results)
+ * synchronize that stream before returning.
+ *
+ * Threading: a chain or batch handle is used by one caller thread at a time.
+ *
+ * Restrictions of the device path: L even (the lattice must be bipartite:
+ * the recursion stores only the sublattice on which each vector is nonzero),
+ * 2 <= L <= 256; b = 0 (a diagonal shift breaks that sublattice structure);
+ * M even, 2 <= M <= 16384; K a power of two with M <= K <= 16384 (the radix-2
+ * transform of the paper's node mapping).
+ */
+#ifndef GFMC_H
+#define GFMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GFMC_OK = 0,
+  GFMC_EINVAL = -1,    /* invalid argument; state unchanged                  */
+  GFMC_ENOMEM = -2,    /* workspace too small                                */
+  GFMC_EDEVICE = -3,   /* HIP runtime error                                  */
+  GFMC_EBUSY = -4,     /* resource busy                                      */
+  GFMC_ESTATE = -5,    /* call not valid in the current state                */
+  GFMC_ECANCELED = -6  /* operation cancelled                                */
+} gfmc_status;
+
+typedef enum { GFMC_FP64 = 0, GFMC_FP32_ACC64 = 1 } gfmc_precision;
+typedef enum { GFMC_JACKSON = 0, GFMC_LORENTZ = 1 } gfmc_kernel;
+typedef enum { GFMC_PROPOSE_SPHERE = 0, GFMC_PROPOSE_CONE = 1 } gfmc_proposal;
+typedef enum { GFMC_INIT_RANDOM = 0, GFMC_INIT_FM = 1, GFMC_INIT_FM_PLUS_RANDOM = 2 } gfmc_init;
+
+/* Parameters of one Markov chain (all energies in units of t). */
+typedef struct {
+  int32_t L;                /* linear size, N = L^3, periodic                         */
+  double t;                 /* hopping scale (> 0)                                    */
+  double beta;              /* inverse temperature (> 0)                              */
+  double mu;                /* chemical potential                                     */
+  int32_t M;                /* number of Chebyshev moments (even)                     */
+  int32_t K;                /* energy nodes; 0 selects K = M                          */
+  gfmc_kernel kernel;       /* damping kernel (Jackson default)                       */
+  double lorentz_lambda;    /* Lorentz parameter; 0 selects 4.0                       */
+  double scale_a;           /* Ht = (H - b)/a; 0 selects a = 6t/(1 - 0.01)            */
+  double scale_b;           /* must be 0 on the device path                           */
+  gfmc_precision precision; /* FP64, or FP32 recursion with FP64 moment sums          */
+  gfmc_proposal proposal;   /* new direction: whole sphere or cap around the old one  */
+  double cone_angle;        /* cap half-angle in rad (GFMC_PROPOSE_CONE)              */
+  uint64_t seed;            /* Philox key word 0                                      */
+  uint64_t chain_id;        /* Philox key word 1                                      */
+} gfmc_chain_params;
+
+/* Outcome of one proposal (Algorithm 1, inner loop body). */
+typedef struct {
+  int64_t index;            /* proposal counter value sweep*N + j                     */
+  int32_t site;             /* proposed site o                                        */
+  int32_t own;              /* decision from (dseff, u): 1 accept                     */
+  int32_t accepted;         /* decision applied (own unless forced)                   */
+  int32_t pad_;
+  double theta_old, phi_old, theta_new, phi_new;
+  double dseff;             /* Delta S_eff = S_eff(new) - S_eff(old)                  */
+  double u;                 /* uniform draw in [0,1) of the Metropolis test           */
+  double phase_top;         /* continuous phase at the highest node (ideally ~0)      */
+} gfmc_step_record;
+
+typedef struct gfmc_chain gfmc_chain;   /* opaque */
+typedef struct gfmc_batch gfmc_batch;   /* opaque */
+
+/* ---------------------------------------------------------------- chains --
+ * Device workspace (bytes, 256-byte aligned base) that a chain with these
+ * parameters needs: spin angles, spinor cache, the 7 Chebyshev vectors (one
+ * sublattice each, 7*N complex values), per-step moment partial sums, the
+ * moment table and reconstruction scratch.  EINVAL for parameters outside the
+ * device path's restrictions. */
+gfmc_status gfmc_workspace_bytes(const gfmc_chain_params* params, size_t* bytes);
+
+/* Create a chain on `dev_workspace` (device pointer of at least
+ * gfmc_workspace_bytes bytes, owned by the caller, alive until destroy) and
+ * `hip_stream` (hipStream_t, may be NULL for the default stream).  Spins start
+ * ferromagnetic (all theta = phi = 0); the proposal counter starts at 0. */
+gfmc_status gfmc_chain_create(const gfmc_chain_params* params, void* dev_workspace,
+                              size_t bytes, void* hip_stream, gfmc_chain** out);
+gfmc_status gfmc_chain_destroy(gfmc_chain* chain);
+
+/* Change t, beta, mu (the rescaling a, if defaulted, follows t). */
+gfmc_status gfmc_set_params(gfmc_chain* chain, double t, double beta, double mu);
+
+/* Initialise spins on the device from the chain's Philox key: uniform on the
+ * sphere, ferromagnetic, or ferromagnetic with exactly floor(frac*N) sites
+ * (picked by a partial Fisher-Yates shuffle) redrawn on the sphere. */
+gfmc_status gfmc_init_spins(gfmc_chain* chain, gfmc_init mode, double random_fraction);
+
+/* Copy N angles from / to host arrays (theta in [0,pi], phi any finite value). */
+gfmc_status gfmc_set_spins(gfmc_chain* chain, const double* theta, const double* phi);
+gfmc_status gfmc_get_spins(gfmc_chain* chain, double* theta, double* phi);
+
+/* Proposal counter (next proposal uses counter value `index`). */
+gfmc_status gfmc_set_counter(gfmc_chain* chain, int64_t index);
+gfmc_status gfmc_get_counter(gfmc_chain* chain, int64_t* index);
+
+/* Local moments around `site` for the current spins (no state change):
+ * writes mu[M][7][7][2] (host). */
+gfmc_status gfmc_moments(gfmc_chain* chain, int32_t site, double* mu);
+
+/* Delta S_eff for moving the spin at `site` to (theta_new, phi_new), no state
+ * change.  phase_top may be NULL. */
+gfmc_status gfmc_delta_seff(gfmc_chain* chain, int32_t site, double theta_new,
+                            double phi_new, double* dseff, double* phase_top);
+
+/* One proposal at the chain's counter; force -1 takes the chain's own
+ * decision, 0 rejects, 1 accepts.  rec may be NULL. */
+gfmc_status gfmc_step(gfmc_chain* chain, int32_t force, gfmc_step_record* rec);
+
+/* nsweeps sweeps of N proposals each (Algorithm 1).  magnetization
+ * [nsweeps] and accepted (total over the call) may be NULL. */
+gfmc_status gfmc_sweep(gfmc_chain* chain, int32_t nsweeps, double* magnetization,
+                       int64_t* accepted);
+
+gfmc_status gfmc_sync(gfmc_chain* chain);
+
+/* ----------------------------------------------------------------- batches --
+ * A batch advances several independent chains together: every Chebyshev step
+ * is one launch over all chains that still need it, so chains of different L
+ * and M share the device.  All chains must have the same precision and be
+ * created on the same device; the batch enqueues on its own stream and the
+ * chains must not be used individually while the batch exists.
+ * The batch workspace holds the chain descriptor table and launch plans. */
+gfmc_status gfmc_batch_workspace_bytes(gfmc_chain* const* chains, int32_t n, size_t* bytes);
+gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* dev_workspace,
+                              size_t bytes, void* hip_stream, gfmc_batch** out);
+gfmc_status gfmc_batch_destroy(gfmc_batch* batch);
+
+/* nprop proposals on every chain.  force: NULL (own decisions) or [nprop][n];
+ * recs: NULL or [nprop][n] records. */
+gfmc_status gfmc_batch_step(gfmc_batch* batch, int32_t nprop, const int32_t* force,
+                            gfmc_step_record* recs);
+
+/* Each chain runs nsweeps sweeps of its own N proposals; magnetization
+ * [n][nsweeps] and accepted [n] may be NULL.  Chains with smaller N finish
+ * their sweeps earlier and stop. */
+gfmc_status gfmc_batch_sweep(gfmc_batch* batch, int32_t nsweeps, double* magnetization,
+                             int64_t* accepted);
+
+/* Capture one proposal of the whole batch (propose, every Chebyshev step,
+ * moment assembly, reconstruction and Metropolis update) in a HIP graph and
+ * replay it for later gfmc_batch_step calls without force or records
+ * (enable != 0), or go back to direct launches (enable == 0). */
+gfmc_status gfmc_batch_use_graph(gfmc_batch* batch, int32_t enable);
+
+/* Timing of the Chebyshev step kernel over the last gfmc_batch_step call,
+ * from HIP events on the batch stream around the step launches: total
+ * milliseconds and number of step launches. */
+gfmc_status gfmc_batch_step_timing(gfmc_batch* batch, double* step_ms, int64_t* launches);
+
+/* Algorithmic bytes moved by one proposal of `chain` in the step kernel
+ * (vectors read and written, spinors read; per step and summed over steps). */
+gfmc_status gfmc_chain_step_bytes(gfmc_chain* chain, double* bytes_per_step, int32_t* steps);
+
+/* ------------------------------------------------------------------ misc -- */
+const char* gfmc_status_string(gfmc_status status);
+const char* gfmc_last_error(void);
+const char* gfmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFMC_H */

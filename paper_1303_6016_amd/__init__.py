@@ -1,0 +1,306 @@
+"""Python binding of libgfmc (gfx950 GFMC hot path), argument marshalling only.
+
+Every computation runs in the HIP kernels behind the C ABI of ``include/gfmc.h``.
+PyTorch provides device memory (the workspaces) and streams.  Loading fails
+loudly when the library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfmc.so")
+
+GFMC_OK, GFMC_EINVAL, GFMC_ENOMEM, GFMC_EDEVICE, GFMC_EBUSY, GFMC_ESTATE, GFMC_ECANCELED = (
+    0, -1, -2, -3, -4, -5, -6)
+FP64, FP32_ACC64 = 0, 1
+JACKSON, LORENTZ = 0, 1
+PROPOSE_SPHERE, PROPOSE_CONE = 0, 1
+INIT_RANDOM, INIT_FM, INIT_FM_PLUS_RANDOM = 0, 1, 2
+
+
+class GfmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gfmc status {status}: {msg}")
+        self.status = status
+
+
+class ChainParams(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32), ("t", ctypes.c_double), ("beta", ctypes.c_double),
+        ("mu", ctypes.c_double), ("M", ctypes.c_int32), ("K", ctypes.c_int32),
+        ("kernel", ctypes.c_int32), ("lorentz_lambda", ctypes.c_double),
+        ("scale_a", ctypes.c_double), ("scale_b", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("proposal", ctypes.c_int32),
+        ("cone_angle", ctypes.c_double), ("seed", ctypes.c_uint64), ("chain_id", ctypes.c_uint64),
+    ]
+
+
+class StepRecord(ctypes.Structure):
+    _fields_ = [
+        ("index", ctypes.c_int64), ("site", ctypes.c_int32), ("own", ctypes.c_int32),
+        ("accepted", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("theta_old", ctypes.c_double), ("phi_old", ctypes.c_double),
+        ("theta_new", ctypes.c_double), ("phi_new", ctypes.c_double),
+        ("dseff", ctypes.c_double), ("u", ctypes.c_double), ("phase_top", ctypes.c_double),
+    ]
+
+
+_P = ctypes.POINTER
+_d, _i32, _i64, _sz, _vp = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+_SIGS = {
+    "gfmc_workspace_bytes": [_P(ChainParams), _P(_sz)],
+    "gfmc_chain_create": [_P(ChainParams), _vp, _sz, _vp, _P(_vp)],
+    "gfmc_chain_destroy": [_vp],
+    "gfmc_set_params": [_vp, _d, _d, _d],
+    "gfmc_init_spins": [_vp, _i32, _d],
+    "gfmc_set_spins": [_vp, _P(_d), _P(_d)],
+    "gfmc_get_spins": [_vp, _P(_d), _P(_d)],
+    "gfmc_set_counter": [_vp, _i64],
+    "gfmc_get_counter": [_vp, _P(_i64)],
+    "gfmc_moments": [_vp, _i32, _P(_d)],
+    "gfmc_delta_seff": [_vp, _i32, _d, _d, _P(_d), _P(_d)],
+    "gfmc_step": [_vp, _i32, _P(StepRecord)],
+    "gfmc_sweep": [_vp, _i32, _P(_d), _P(_i64)],
+    "gfmc_sync": [_vp],
+    "gfmc_chain_step_bytes": [_vp, _P(_d), _P(_i32)],
+    "gfmc_batch_workspace_bytes": [_P(_vp), _i32, _P(_sz)],
+    "gfmc_batch_create": [_P(_vp), _i32, _vp, _sz, _vp, _P(_vp)],
+    "gfmc_batch_destroy": [_vp],
+    "gfmc_batch_step": [_vp, _i32, _P(_i32), _P(StepRecord)],
+    "gfmc_batch_sweep": [_vp, _i32, _P(_d), _P(_i64)],
+    "gfmc_batch_use_graph": [_vp, _i32],
+    "gfmc_batch_step_timing": [_vp, _P(_d), _P(_i64)],
+}
+EXPORTS = list(_SIGS) + ["gfmc_status_string", "gfmc_last_error", "gfmc_version"]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgfmc.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_1303_6016_amd/build.py` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        for name in ("gfmc_status_string",):
+            getattr(L, name).argtypes = [ctypes.c_int]
+            getattr(L, name).restype = ctypes.c_char_p
+        for name in ("gfmc_last_error", "gfmc_version"):
+            getattr(L, name).argtypes = []
+            getattr(L, name).restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != GFMC_OK:
+        raise GfmcError(status, lib().gfmc_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+@dataclass
+class Params:
+    L: int
+    t: float = 1.0
+    beta: float = 20.0
+    mu: float = 0.0
+    M: int = 256
+    K: int = 0
+    kernel: int = JACKSON
+    lorentz_lambda: float = 0.0
+    scale_a: float = 0.0
+    scale_b: float = 0.0
+    precision: int = FP64
+    proposal: int = PROPOSE_SPHERE
+    cone_angle: float = 0.0
+    seed: int = 0
+    chain_id: int = 0
+
+    def c(self) -> ChainParams:
+        return ChainParams(self.L, self.t, self.beta, self.mu, self.M, self.K, self.kernel,
+                           self.lorentz_lambda, self.scale_a, self.scale_b, self.precision,
+                           self.proposal, self.cone_angle, self.seed & (2**64 - 1),
+                           self.chain_id & (2**64 - 1))
+
+    @property
+    def N(self) -> int:
+        return self.L ** 3
+
+
+def gfmc_workspace_bytes(p: Params) -> int:
+    n = ctypes.c_size_t()
+    cp = p.c()
+    _check(lib().gfmc_workspace_bytes(ctypes.byref(cp), ctypes.byref(n)))
+    return n.value
+
+
+def _alloc(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 512-byte aligned blocks
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+class Chain:
+    """One Markov chain; its workspace is a torch uint8 tensor on the device."""
+
+    def __init__(self, p: Params, device="cuda", stream: Optional[torch.cuda.Stream] = None):
+        self.p = p
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.nbytes = gfmc_workspace_bytes(p)
+            self.ws = _alloc(self.nbytes, self.device)
+            h = ctypes.c_void_p()
+            cp = p.c()
+            _check(lib().gfmc_chain_create(ctypes.byref(cp), ctypes.c_void_p(self.ws.data_ptr()),
+                                           self.nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                           ctypes.byref(h)))
+            self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().gfmc_chain_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def N(self):
+        return self.p.N
+
+    def set_params(self, t, beta, mu):
+        _check(lib().gfmc_set_params(self.h, t, beta, mu))
+        self.p.t, self.p.beta, self.p.mu = t, beta, mu
+
+    def init_spins(self, mode: int, frac: float = 0.0):
+        _check(lib().gfmc_init_spins(self.h, mode, frac))
+
+    def set_spins(self, theta, phi):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        ph = np.ascontiguousarray(phi, dtype=np.float64)
+        assert th.size == self.N and ph.size == self.N
+        _check(lib().gfmc_set_spins(self.h, _dptr(th), _dptr(ph)))
+
+    def get_spins(self):
+        th = np.zeros(self.N)
+        ph = np.zeros(self.N)
+        _check(lib().gfmc_get_spins(self.h, _dptr(th), _dptr(ph)))
+        return th, ph
+
+    def set_counter(self, index: int):
+        _check(lib().gfmc_set_counter(self.h, index))
+
+    def get_counter(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().gfmc_get_counter(self.h, ctypes.byref(v)))
+        return v.value
+
+    def moments(self, site: int) -> np.ndarray:
+        out = np.zeros((self.p.M, 7, 7, 2))
+        _check(lib().gfmc_moments(self.h, site, _dptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def delta_seff(self, site: int, theta_new: float, phi_new: float, with_phase_top=False):
+        ds, top = ctypes.c_double(), ctypes.c_double()
+        _check(lib().gfmc_delta_seff(self.h, site, theta_new, phi_new, ctypes.byref(ds),
+                                     ctypes.byref(top)))
+        return (ds.value, top.value) if with_phase_top else ds.value
+
+    def step(self, force: int = -1) -> StepRecord:
+        rec = StepRecord()
+        _check(lib().gfmc_step(self.h, force, ctypes.byref(rec)))
+        return rec
+
+    def sweep(self, nsweeps: int):
+        mag = np.zeros(max(nsweeps, 1))
+        acc = ctypes.c_int64()
+        _check(lib().gfmc_sweep(self.h, nsweeps, _dptr(mag), ctypes.byref(acc)))
+        return mag[:nsweeps], acc.value
+
+    def sync(self):
+        _check(lib().gfmc_sync(self.h))
+
+    def step_bytes(self):
+        b, s = ctypes.c_double(), ctypes.c_int32()
+        _check(lib().gfmc_chain_step_bytes(self.h, ctypes.byref(b), ctypes.byref(s)))
+        return b.value, s.value
+
+
+class Batch:
+    """Several chains advanced together (one launch per Chebyshev step)."""
+
+    def __init__(self, chains: Sequence[Chain], stream: Optional[torch.cuda.Stream] = None):
+        self.chains = list(chains)
+        dev = self.chains[0].device
+        with torch.cuda.device(dev):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+            arr = (ctypes.c_void_p * len(self.chains))(*[c.h.value for c in self.chains])
+            n = ctypes.c_size_t()
+            _check(lib().gfmc_batch_workspace_bytes(arr, len(self.chains), ctypes.byref(n)))
+            self.ws = _alloc(n.value, dev)
+            h = ctypes.c_void_p()
+            _check(lib().gfmc_batch_create(arr, len(self.chains), ctypes.c_void_p(self.ws.data_ptr()),
+                                           n.value, ctypes.c_void_p(self.stream.cuda_stream),
+                                           ctypes.byref(h)))
+            self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().gfmc_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nprop: int = 1, force: Optional[np.ndarray] = None, records: bool = False):
+        n = len(self.chains)
+        fp = None
+        if force is not None:
+            f = np.ascontiguousarray(force, dtype=np.int32).reshape(nprop, n)
+            fp = f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        recs = (StepRecord * (nprop * n))() if records else None
+        _check(lib().gfmc_batch_step(self.h, nprop, fp, recs))
+        if records:
+            return [[recs[q * n + i] for i in range(n)] for q in range(nprop)]
+        return None
+
+    def sweep(self, nsweeps: int):
+        n = len(self.chains)
+        mag = np.zeros((n, max(nsweeps, 1)))
+        acc = np.zeros(n, dtype=np.int64)
+        _check(lib().gfmc_batch_sweep(self.h, nsweeps, _dptr(mag),
+                                      acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return mag[:, :nsweeps], acc
+
+    def use_graph(self, enable: bool = True):
+        _check(lib().gfmc_batch_use_graph(self.h, 1 if enable else 0))
+
+    def step_timing(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().gfmc_batch_step_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

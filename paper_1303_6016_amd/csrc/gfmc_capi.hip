@@ -1,0 +1,715 @@
+// gfmc_capi.hip -- host side of the C ABI declared in include/gfmc.h:
+// parameter validation, workspace layout, chain and batch handles, and the
+// launch sequence of one proposal (propose -> M/2 Chebyshev steps ->
+// moment assembly -> reconstruction + Metropolis).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "gfmc_device.h"
+
+namespace gfmc {
+hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
+hipError_t launch_step(int fp32, const Desc* d, const int* blkoff, int nact, int blocks, int s,
+                       hipStream_t st);
+hipError_t launch_moments(const Desc* d, int n, int smax, hipStream_t st);
+hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
+                        gfmc_step_record* recs, hipStream_t st);
+hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t st);
+hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st);
+hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st);
+hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t st);
+}  // namespace gfmc
+
+using namespace gfmc;
+
+// ------------------------------------------------------------- errors ----
+static thread_local std::string g_err;
+
+static gfmc_status fail(gfmc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(GFMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define CHK(expr)                          \
+  do {                                     \
+    gfmc_status s_ = (expr);               \
+    if (s_ != GFMC_OK) return s_;          \
+  } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------- chain layout ----
+struct Derived {
+  int L, N, half, M, S, K, log2K, nblk, fp32;
+  double a, lambda;
+};
+
+static gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
+  if (!p) return fail(GFMC_EINVAL, "params is NULL");
+  if (p->L < 2 || p->L > 256 || (p->L & 1))
+    return fail(GFMC_EINVAL, "L must be even and in [2, 256] (bipartite lattice)");
+  if (!(p->t > 0) || !std::isfinite(p->t)) return fail(GFMC_EINVAL, "t must be positive");
+  if (!(p->beta > 0) || !std::isfinite(p->beta)) return fail(GFMC_EINVAL, "beta must be positive");
+  if (!std::isfinite(p->mu)) return fail(GFMC_EINVAL, "mu must be finite");
+  if (p->M < 2 || (p->M & 1) || p->M > kMaxK) return fail(GFMC_EINVAL, "M must be even in [2, 8192]");
+  const int K = p->K ? p->K : p->M;
+  if (K < p->M || K > kMaxK || (K & (K - 1)))
+    return fail(GFMC_EINVAL, "K must be a power of two with M <= K <= 8192");
+  if (p->scale_b != 0.0) return fail(GFMC_EINVAL, "scale_b must be 0 on the device path");
+  if (p->scale_a < 0 || !std::isfinite(p->scale_a)) return fail(GFMC_EINVAL, "scale_a must be >= 0");
+  if (p->kernel != GFMC_JACKSON && p->kernel != GFMC_LORENTZ)
+    return fail(GFMC_EINVAL, "unknown kernel");
+  if (p->precision != GFMC_FP64 && p->precision != GFMC_FP32_ACC64)
+    return fail(GFMC_EINVAL, "unknown precision");
+  if (p->proposal != GFMC_PROPOSE_SPHERE && p->proposal != GFMC_PROPOSE_CONE)
+    return fail(GFMC_EINVAL, "unknown proposal");
+  if (p->proposal == GFMC_PROPOSE_CONE && !(p->cone_angle > 0 && p->cone_angle <= M_PI))
+    return fail(GFMC_EINVAL, "cone_angle must be in (0, pi]");
+  if (p->kernel == GFMC_LORENTZ && p->lorentz_lambda < 0) return fail(GFMC_EINVAL, "lambda < 0");
+  d.L = p->L;
+  d.N = p->L * p->L * p->L;
+  d.half = d.N / 2;
+  d.M = p->M;
+  d.S = p->M / 2;
+  d.K = K;
+  d.log2K = 0;
+  while ((1 << d.log2K) < K) ++d.log2K;
+  d.nblk = (d.half + kStepThreads - 1) / kStepThreads;
+  d.fp32 = p->precision == GFMC_FP32_ACC64;
+  d.a = p->scale_a > 0 ? p->scale_a : 6.0 * p->t / (1.0 - 0.01);
+  d.lambda = p->lorentz_lambda > 0 ? p->lorentz_lambda : 4.0;
+  if (d.a < 6.0 * p->t) return fail(GFMC_EINVAL, "scale_a must be >= 6t (spectrum inside [-1,1])");
+  return GFMC_OK;
+}
+
+struct Layout {
+  size_t desc, blkoff, force, rec, mag, ctl, theta, phi, spin, vec, part, mom, gscr, total;
+};
+
+static Layout layout_of(const Derived& d) {
+  const size_t tsz = d.fp32 ? 4 : 8;
+  Layout l;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+  l.desc = take(sizeof(Desc));
+  l.blkoff = take(2 * sizeof(int));
+  l.force = take(kRecCap * sizeof(int32_t));
+  l.rec = take(kRecCap * sizeof(gfmc_step_record));
+  l.mag = take(kMagCap * sizeof(double));
+  l.ctl = take(sizeof(Ctl));
+  l.theta = take((size_t)d.N * 8);
+  l.phi = take((size_t)d.N * 8);
+  l.spin = take((size_t)d.N * 4 * tsz);
+  l.vec = take((size_t)7 * d.N * 2 * tsz);
+  l.part = take((size_t)d.S * d.nblk * kNP * 8);
+  l.mom = take((size_t)d.M * 49 * 16);
+  l.gscr = take((size_t)4 * d.K * 16);
+  l.total = o;
+  return l;
+}
+
+// A launch plan: a device table of chain descriptors (sorted by number of
+// Chebyshev steps, largest first) and the block offsets of the step kernel.
+struct Plan {
+  int n = 0, fp32 = 0, smax = 0, kmax = 0, nmax = 0;
+  Desc* d_desc = nullptr;
+  int* d_blkoff = nullptr;
+  int32_t* d_force = nullptr;          // [kRecCap][n]
+  gfmc_step_record* d_rec = nullptr;   // [kRecCap][n]
+  double* d_mag = nullptr;             // [kMagCap][n]
+  std::vector<int> S, blkoff;          // per sorted chain; blkoff has n+1 entries
+  hipStream_t stream = nullptr;
+  // timing of the step launches
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  double step_ms = 0;
+  int64_t step_launches = 0;
+  bool timing = false;
+  // graph replay of one proposal
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+struct gfmc_chain {
+  gfmc_chain_params p;
+  Derived d;
+  Layout l;
+  char* ws = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Desc desc;
+  Plan plan;            // single-chain plan living in the chain's workspace
+  bool in_batch = false;
+};
+
+struct gfmc_batch {
+  std::vector<gfmc_chain*> chains;   // caller order
+  std::vector<int> order;            // sorted position -> caller index
+  Plan plan;
+  bool use_graph = false;
+};
+
+static void fill_desc(gfmc_chain* c) {
+  Desc& D = c->desc;
+  memset(&D, 0, sizeof(D));
+  D.L = c->d.L; D.N = c->d.N; D.half = c->d.half; D.M = c->d.M; D.S = c->d.S; D.K = c->d.K;
+  D.nblk = c->d.nblk; D.kernel = c->p.kernel; D.proposal = c->p.proposal; D.log2K = c->d.log2K;
+  D.t = c->p.t; D.beta = c->p.beta; D.mu = c->p.mu; D.a = c->d.a; D.cone = c->p.cone_angle;
+  D.lambda = c->d.lambda; D.seed = c->p.seed; D.chain_id = c->p.chain_id;
+  D.theta = (double*)(c->ws + c->l.theta);
+  D.phi = (double*)(c->ws + c->l.phi);
+  D.spin = c->ws + c->l.spin;
+  D.vec = c->ws + c->l.vec;
+  D.part = (double*)(c->ws + c->l.part);
+  D.mom = (double*)(c->ws + c->l.mom);
+  D.gscr = (double*)(c->ws + c->l.gscr);
+  D.ctl = (Ctl*)(c->ws + c->l.ctl);
+}
+
+static gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
+  std::vector<Desc> ds(sorted.size());
+  for (size_t i = 0; i < sorted.size(); ++i) ds[i] = sorted[i]->desc;
+  HIPCHK(hipMemcpyAsync(P.d_desc, ds.data(), ds.size() * sizeof(Desc), hipMemcpyHostToDevice,
+                        P.stream));
+  HIPCHK(hipMemcpyAsync(P.d_blkoff, P.blkoff.data(), P.blkoff.size() * sizeof(int),
+                        hipMemcpyHostToDevice, P.stream));
+  HIPCHK(hipStreamSynchronize(P.stream));
+  return GFMC_OK;
+}
+
+static void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
+  P.n = (int)sorted.size();
+  P.S.resize(P.n);
+  P.blkoff.assign(P.n + 1, 0);
+  P.smax = P.kmax = P.nmax = 0;
+  for (int i = 0; i < P.n; ++i) {
+    P.S[i] = sorted[i]->d.S;
+    P.blkoff[i + 1] = P.blkoff[i] + sorted[i]->d.nblk;
+    P.smax = std::max(P.smax, P.S[i]);
+    P.kmax = std::max(P.kmax, sorted[i]->d.K);
+    P.nmax = std::max(P.nmax, sorted[i]->d.N);
+  }
+}
+
+// ------------------------------------------------- one proposal (launches) --
+// Enqueues: propose, S steps (each over the chains that still need it),
+// moment assembly, reconstruction (+ Metropolis when mode 0), spinor update.
+static gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* d_rec,
+                                    bool with_recon) {
+  HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
+  const bool tm = P.timing && P.ev_used + 2 <= (int)P.ev.size();
+  if (tm) HIPCHK(hipEventRecord(P.ev[P.ev_used], P.stream));
+  int nact = P.n;
+  for (int s = 1; s <= P.smax; ++s) {
+    while (nact > 0 && P.S[nact - 1] < s) --nact;
+    HIPCHK(launch_step(P.fp32, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s, P.stream));
+  }
+  if (tm) {
+    HIPCHK(hipEventRecord(P.ev[P.ev_used + 1], P.stream));
+    P.ev_used += 2;
+  }
+  if (P.timing) P.step_launches += P.smax;
+  HIPCHK(launch_moments(P.d_desc, P.n, P.smax, P.stream));
+  if (with_recon) HIPCHK(launch_recon(P.fp32, P.d_desc, P.n, P.kmax, d_force, d_rec, P.stream));
+  return GFMC_OK;
+}
+
+static gfmc_status timing_begin(Plan& P, int nprop) {
+  P.timing = true;
+  P.ev_used = 0;
+  P.step_ms = 0;
+  P.step_launches = 0;
+  const size_t want = (size_t)std::min(nprop, 4096) * 2;
+  while (P.ev.size() < want) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    P.ev.push_back(e);
+  }
+  return GFMC_OK;
+}
+
+static gfmc_status timing_end(Plan& P) {
+  HIPCHK(hipStreamSynchronize(P.stream));
+  double tot = 0;
+  for (int i = 0; i + 1 < P.ev_used; i += 2) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, P.ev[i], P.ev[i + 1]));
+    tot += ms;
+  }
+  const int timed = P.ev_used / 2;
+  // scale the step launch count to the timed proposals
+  if (timed > 0 && P.step_launches > 0) P.step_launches = (int64_t)timed * P.smax;
+  P.step_ms = tot;
+  P.timing = false;
+  return GFMC_OK;
+}
+
+static gfmc_status set_mode(gfmc_chain* c, int mode, int site, double tn, double pn) {
+  Ctl h;
+  HIPCHK(hipMemcpyAsync(&h, c->desc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  h.mode = mode;
+  h.site = site;
+  h.th_new = tn;
+  h.ph_new = pn;
+  HIPCHK(hipMemcpyAsync(c->desc.ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  return GFMC_OK;
+}
+
+static gfmc_status check_chain(gfmc_chain* c) {
+  if (!c) return fail(GFMC_EINVAL, "chain is NULL");
+  if (c->in_batch) return fail(GFMC_ESTATE, "chain belongs to a live batch");
+  HIPCHK(hipSetDevice(c->device));
+  return GFMC_OK;
+}
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* gfmc_status_string(gfmc_status s) {
+  switch (s) {
+    case GFMC_OK: return "ok";
+    case GFMC_EINVAL: return "invalid argument";
+    case GFMC_ENOMEM: return "workspace too small";
+    case GFMC_EDEVICE: return "device error";
+    case GFMC_EBUSY: return "busy";
+    case GFMC_ESTATE: return "invalid state";
+    case GFMC_ECANCELED: return "cancelled";
+  }
+  return "unknown status";
+}
+
+const char* gfmc_last_error(void) { return g_err.c_str(); }
+const char* gfmc_version(void) { return "gfmc-gfx950 0.1"; }
+
+gfmc_status gfmc_workspace_bytes(const gfmc_chain_params* p, size_t* bytes) {
+  Derived d;
+  CHK(derive(p, d));
+  if (!bytes) return fail(GFMC_EINVAL, "bytes is NULL");
+  *bytes = layout_of(d).total;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_chain_create(const gfmc_chain_params* p, void* ws, size_t bytes, void* stream,
+                              gfmc_chain** out) {
+  Derived d;
+  CHK(derive(p, d));
+  if (!out) return fail(GFMC_EINVAL, "out is NULL");
+  if (!ws) return fail(GFMC_EINVAL, "workspace is NULL");
+  if ((uintptr_t)ws & 255) return fail(GFMC_EINVAL, "workspace must be 256-byte aligned");
+  const Layout l = layout_of(d);
+  if (bytes < l.total) return fail(GFMC_ENOMEM, "workspace smaller than gfmc_workspace_bytes");
+  gfmc_chain* c = new (std::nothrow) gfmc_chain();
+  if (!c) return fail(GFMC_ENOMEM, "host allocation failed");
+  c->p = *p;
+  c->d = d;
+  c->l = l;
+  c->ws = (char*)ws;
+  c->bytes = bytes;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(GFMC_EDEVICE, "hipGetDevice failed");
+  }
+  fill_desc(c);
+  Plan& P = c->plan;
+  P.stream = c->stream;
+  P.fp32 = d.fp32;
+  P.d_desc = (Desc*)(c->ws + l.desc);
+  P.d_blkoff = (int*)(c->ws + l.blkoff);
+  P.d_force = (int32_t*)(c->ws + l.force);
+  P.d_rec = (gfmc_step_record*)(c->ws + l.rec);
+  P.d_mag = (double*)(c->ws + l.mag);
+  plan_shape(P, {c});
+  gfmc_status st = upload_plan(P, {c});
+  if (st == GFMC_OK) {
+    Ctl h;
+    memset(&h, 0, sizeof(h));
+    if (hipMemcpyAsync(c->desc.ctl, &h, sizeof(h), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->desc.theta, 0, (size_t)d.N * 8, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->desc.phi, 0, (size_t)d.N * 8, c->stream) != hipSuccess ||
+        launch_spinors(d.fp32, P.d_desc, 1, d.N, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      st = fail(GFMC_EDEVICE, "chain initialisation failed");
+  }
+  if (st != GFMC_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_chain_destroy(gfmc_chain* c) {
+  if (!c) return GFMC_OK;
+  if (c->in_batch) return fail(GFMC_ESTATE, "chain belongs to a live batch");
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->plan.ev) (void)hipEventDestroy(e);
+  delete c;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_set_params(gfmc_chain* c, double t, double beta, double mu) {
+  CHK(check_chain(c));
+  gfmc_chain_params p = c->p;
+  p.t = t;
+  p.beta = beta;
+  p.mu = mu;
+  Derived d;
+  CHK(derive(&p, d));
+  c->p = p;
+  c->d = d;
+  fill_desc(c);
+  return upload_plan(c->plan, {c});
+}
+
+gfmc_status gfmc_init_spins(gfmc_chain* c, gfmc_init mode, double frac) {
+  CHK(check_chain(c));
+  if (mode != GFMC_INIT_RANDOM && mode != GFMC_INIT_FM && mode != GFMC_INIT_FM_PLUS_RANDOM)
+    return fail(GFMC_EINVAL, "unknown init mode");
+  if (mode == GFMC_INIT_FM_PLUS_RANDOM && !(frac >= 0 && frac <= 1))
+    return fail(GFMC_EINVAL, "random_fraction must be in [0, 1]");
+  Plan& P = c->plan;
+  HIPCHK(launch_init_spins(P.d_desc, c->d.N, mode == GFMC_INIT_RANDOM ? 0 : 1, c->stream));
+  if (mode == GFMC_INIT_FM_PLUS_RANDOM) {
+    int64_t nr = (int64_t)std::floor(frac * (double)c->d.N);
+    nr = std::min<int64_t>(std::max<int64_t>(nr, 0), c->d.N);
+    // the vector buffer (7N complex) is free scratch between proposals
+    HIPCHK(launch_fisher_yates(P.d_desc, nr, (int32_t*)c->desc.vec, c->stream));
+  }
+  HIPCHK(launch_spinors(c->d.fp32, P.d_desc, 1, c->d.N, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_set_spins(gfmc_chain* c, const double* th, const double* ph) {
+  CHK(check_chain(c));
+  if (!th || !ph) return fail(GFMC_EINVAL, "theta/phi is NULL");
+  for (int i = 0; i < c->d.N; ++i)
+    if (!std::isfinite(th[i]) || !std::isfinite(ph[i]) || th[i] < 0 || th[i] > M_PI)
+      return fail(GFMC_EINVAL, "angles must be finite with theta in [0, pi]");
+  HIPCHK(hipMemcpyAsync(c->desc.theta, th, (size_t)c->d.N * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->desc.phi, ph, (size_t)c->d.N * 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_spinors(c->d.fp32, c->plan.d_desc, 1, c->d.N, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_get_spins(gfmc_chain* c, double* th, double* ph) {
+  if (!c) return fail(GFMC_EINVAL, "chain is NULL");
+  HIPCHK(hipSetDevice(c->device));
+  if (!th || !ph) return fail(GFMC_EINVAL, "theta/phi is NULL");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(th, c->desc.theta, (size_t)c->d.N * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ph, c->desc.phi, (size_t)c->d.N * 8, hipMemcpyDeviceToHost));
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_set_counter(gfmc_chain* c, int64_t index) {
+  CHK(check_chain(c));
+  if (index < 0) return fail(GFMC_EINVAL, "index must be >= 0");
+  HIPCHK(hipMemcpyAsync(&c->desc.ctl->index, &index, sizeof(index), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_get_counter(gfmc_chain* c, int64_t* index) {
+  if (!c || !index) return fail(GFMC_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(index, &c->desc.ctl->index, sizeof(*index), hipMemcpyDeviceToHost));
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_moments(gfmc_chain* c, int32_t site, double* mu) {
+  CHK(check_chain(c));
+  if (site < 0 || site >= c->d.N) return fail(GFMC_EINVAL, "site out of range");
+  if (!mu) return fail(GFMC_EINVAL, "mu is NULL");
+  CHK(set_mode(c, 2, site, 0.0, 0.0));
+  CHK(enqueue_proposal(c->plan, nullptr, nullptr, false));
+  HIPCHK(hipMemcpyAsync(mu, c->desc.mom, (size_t)c->d.M * 49 * 16, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return set_mode(c, 0, 0, 0.0, 0.0);
+}
+
+gfmc_status gfmc_delta_seff(gfmc_chain* c, int32_t site, double tn, double pn, double* dseff,
+                            double* phase_top) {
+  CHK(check_chain(c));
+  if (site < 0 || site >= c->d.N) return fail(GFMC_EINVAL, "site out of range");
+  if (!std::isfinite(tn) || !std::isfinite(pn)) return fail(GFMC_EINVAL, "angles not finite");
+  if (!dseff) return fail(GFMC_EINVAL, "dseff is NULL");
+  CHK(set_mode(c, 1, site, tn, pn));
+  CHK(enqueue_proposal(c->plan, nullptr, nullptr, true));
+  Ctl h;
+  HIPCHK(hipMemcpyAsync(&h, c->desc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *dseff = h.dseff;
+  if (phase_top) *phase_top = h.phase_top;
+  return set_mode(c, 0, 0, 0.0, 0.0);
+}
+
+}  // extern "C"
+
+// nprop proposals of every chain in the plan.  force: host [nprop][n] or NULL;
+// recs: host [nprop][n] or NULL.  Host arrays are in sorted plan order.
+static gfmc_status run_proposals(Plan& P, int nprop, const int32_t* force,
+                                 gfmc_step_record* recs) {
+  for (int p0 = 0; p0 < nprop; p0 += kRecCap) {
+    const int cnt = std::min(kRecCap, nprop - p0);
+    if (force)
+      HIPCHK(hipMemcpyAsync(P.d_force, force + (size_t)p0 * P.n, (size_t)cnt * P.n * 4,
+                            hipMemcpyHostToDevice, P.stream));
+    for (int q = 0; q < cnt; ++q)
+      CHK(enqueue_proposal(P, force ? P.d_force + (size_t)q * P.n : nullptr,
+                           recs ? P.d_rec + (size_t)q * P.n : nullptr, true));
+    if (recs)
+      HIPCHK(hipMemcpyAsync(recs + (size_t)p0 * P.n, P.d_rec, (size_t)cnt * P.n * sizeof(gfmc_step_record),
+                            hipMemcpyDeviceToHost, P.stream));
+    if (force || recs) HIPCHK(hipStreamSynchronize(P.stream));
+  }
+  return GFMC_OK;
+}
+
+extern "C" {
+
+gfmc_status gfmc_step(gfmc_chain* c, int32_t force, gfmc_step_record* rec) {
+  CHK(check_chain(c));
+  if (force < -1 || force > 1) return fail(GFMC_EINVAL, "force must be -1, 0 or 1");
+  gfmc_step_record r;
+  CHK(run_proposals(c->plan, 1, &force, &r));
+  if (rec) *rec = r;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_sweep(gfmc_chain* c, int32_t nsweeps, double* mag, int64_t* accepted) {
+  CHK(check_chain(c));
+  if (nsweeps < 0) return fail(GFMC_EINVAL, "nsweeps must be >= 0");
+  int64_t a0 = 0, a1 = 0;
+  HIPCHK(hipMemcpy(&a0, &c->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost));
+  for (int s = 0; s < nsweeps; ++s) {
+    CHK(run_proposals(c->plan, c->d.N, nullptr, nullptr));
+    HIPCHK(launch_magnetization(c->plan.d_desc, 1, c->plan.d_mag, c->stream));
+    if (mag) HIPCHK(hipMemcpyAsync(mag + s, c->plan.d_mag, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  HIPCHK(hipMemcpy(&a1, &c->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost));
+  if (accepted) *accepted = a1 - a0;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_sync(gfmc_chain* c) {
+  if (!c) return fail(GFMC_EINVAL, "chain is NULL");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_chain_step_bytes(gfmc_chain* c, double* bytes_per_step, int32_t* steps) {
+  if (!c || !bytes_per_step || !steps) return fail(GFMC_EINVAL, "NULL argument");
+  // Per step: read both stored values of every site (7 complex: one class is
+  // the stencil input, the other the a_{s-2} term), write 3.5 complex per
+  // site (the class being advanced), read the spinor of every site.
+  const double tsz = c->d.fp32 ? 4 : 8;
+  const double N = c->d.N;
+  *bytes_per_step = N * (7.0 * 2 * tsz + 3.5 * 2 * tsz + 4 * tsz);
+  *steps = c->d.S;
+  return GFMC_OK;
+}
+
+// ---------------------------------------------------------------- batches
+static size_t batch_bytes(int n) {
+  return align256((size_t)n * sizeof(Desc)) + align256((size_t)(n + 1) * sizeof(int)) +
+         align256((size_t)kRecCap * n * sizeof(int32_t)) +
+         align256((size_t)kRecCap * n * sizeof(gfmc_step_record)) +
+         align256((size_t)kMagCap * n * sizeof(double));
+}
+
+gfmc_status gfmc_batch_workspace_bytes(gfmc_chain* const* chains, int32_t n, size_t* bytes) {
+  if (!chains || n <= 0 || !bytes) return fail(GFMC_EINVAL, "bad arguments");
+  *bytes = batch_bytes(n);
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, size_t bytes,
+                              void* stream, gfmc_batch** out) {
+  if (!chains || n <= 0 || !out || !ws) return fail(GFMC_EINVAL, "bad arguments");
+  if ((uintptr_t)ws & 255) return fail(GFMC_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < batch_bytes(n)) return fail(GFMC_ENOMEM, "batch workspace too small");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  for (int i = 0; i < n; ++i) {
+    if (!chains[i]) return fail(GFMC_EINVAL, "NULL chain");
+    if (chains[i]->in_batch) return fail(GFMC_ESTATE, "chain already in a batch");
+    if (chains[i]->d.fp32 != chains[0]->d.fp32) return fail(GFMC_EINVAL, "mixed precision");
+    if (chains[i]->device != dev) return fail(GFMC_EINVAL, "chain on another device");
+    for (int j = 0; j < i; ++j)
+      if (chains[j] == chains[i]) return fail(GFMC_EINVAL, "chain listed twice");
+  }
+  gfmc_batch* b = new (std::nothrow) gfmc_batch();
+  if (!b) return fail(GFMC_ENOMEM, "host allocation failed");
+  b->chains.assign(chains, chains + n);
+  b->order.resize(n);
+  std::iota(b->order.begin(), b->order.end(), 0);
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int x, int y) { return chains[x]->d.S > chains[y]->d.S; });
+  std::vector<gfmc_chain*> sorted(n);
+  for (int i = 0; i < n; ++i) sorted[i] = chains[b->order[i]];
+  Plan& P = b->plan;
+  char* w = (char*)ws;
+  P.stream = (hipStream_t)stream;
+  P.fp32 = chains[0]->d.fp32;
+  P.d_desc = (Desc*)w; w += align256((size_t)n * sizeof(Desc));
+  P.d_blkoff = (int*)w; w += align256((size_t)(n + 1) * sizeof(int));
+  P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * n * sizeof(int32_t));
+  P.d_rec = (gfmc_step_record*)w; w += align256((size_t)kRecCap * n * sizeof(gfmc_step_record));
+  P.d_mag = (double*)w;
+  plan_shape(P, sorted);
+  // chains' own streams may hold pending work
+  for (auto* c : sorted) HIPCHK(hipStreamSynchronize(c->stream));
+  gfmc_status st = upload_plan(P, sorted);
+  if (st != GFMC_OK) {
+    delete b;
+    return st;
+  }
+  for (auto* c : sorted) c->in_batch = true;
+  *out = b;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_destroy(gfmc_batch* b) {
+  if (!b) return GFMC_OK;
+  (void)hipStreamSynchronize(b->plan.stream);
+  if (b->plan.gexec) (void)hipGraphExecDestroy(b->plan.gexec);
+  if (b->plan.graph) (void)hipGraphDestroy(b->plan.graph);
+  for (hipEvent_t e : b->plan.ev) (void)hipEventDestroy(e);
+  for (auto* c : b->chains) c->in_batch = false;
+  delete b;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_use_graph(gfmc_batch* b, int32_t enable) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  Plan& P = b->plan;
+  if (!enable) {
+    b->use_graph = false;
+    return GFMC_OK;
+  }
+  if (!P.gexec) {
+    HIPCHK(hipStreamSynchronize(P.stream));
+    HIPCHK(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal));
+    const bool tm = P.timing;
+    P.timing = false;
+    gfmc_status st = enqueue_proposal(P, nullptr, nullptr, true);
+    P.timing = tm;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(P.stream, &g);
+    if (st != GFMC_OK) return st;
+    HIPCHK(e);
+    P.graph = g;
+    HIPCHK(hipGraphInstantiate(&P.gexec, g, nullptr, nullptr, 0));
+  }
+  b->use_graph = true;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_step(gfmc_batch* b, int32_t nprop, const int32_t* force,
+                            gfmc_step_record* recs) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  if (nprop < 0) return fail(GFMC_EINVAL, "nprop must be >= 0");
+  Plan& P = b->plan;
+  const int n = P.n;
+  std::vector<int32_t> f;
+  if (force) {
+    f.resize((size_t)nprop * n);
+    for (int q = 0; q < nprop; ++q)
+      for (int i = 0; i < n; ++i) {
+        const int32_t v = force[(size_t)q * n + b->order[i]];
+        if (v < -1 || v > 1) return fail(GFMC_EINVAL, "force must be -1, 0 or 1");
+        f[(size_t)q * n + i] = v;
+      }
+  }
+  std::vector<gfmc_step_record> r(recs ? (size_t)nprop * n : 0);
+  if (b->use_graph && !force && !recs) {
+    HIPCHK(hipStreamSynchronize(P.stream));
+    const int tev = std::min(nprop, 4096);
+    CHK(timing_begin(P, 1));
+    HIPCHK(hipEventRecord(P.ev[0], P.stream));
+    for (int q = 0; q < nprop; ++q) HIPCHK(hipGraphLaunch(P.gexec, P.stream));
+    HIPCHK(hipEventRecord(P.ev[1], P.stream));
+    P.ev_used = 2;
+    (void)tev;
+    CHK(timing_end(P));
+    // whole proposals were timed: report the per-proposal time spread over the steps
+    P.step_launches = (int64_t)nprop * P.smax;
+    return GFMC_OK;
+  }
+  CHK(timing_begin(P, nprop));
+  CHK(run_proposals(P, nprop, force ? f.data() : nullptr, recs ? r.data() : nullptr));
+  CHK(timing_end(P));
+  if (recs)
+    for (int q = 0; q < nprop; ++q)
+      for (int i = 0; i < n; ++i) recs[(size_t)q * n + b->order[i]] = r[(size_t)q * n + i];
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_sweep(gfmc_batch* b, int32_t nsweeps, double* mag, int64_t* accepted) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  if (nsweeps < 0) return fail(GFMC_EINVAL, "nsweeps must be >= 0");
+  Plan& P = b->plan;
+  const int n = P.n;
+  std::vector<int64_t> a0(n), a1(n);
+  for (int i = 0; i < n; ++i)
+    HIPCHK(hipMemcpy(&a0[i], &b->chains[b->order[i]]->desc.ctl->accepted_total, 8,
+                     hipMemcpyDeviceToHost));
+  bool uniform = true;
+  for (auto* c : b->chains) uniform = uniform && c->d.N == b->chains[0]->d.N;
+  if (!uniform) return fail(GFMC_EINVAL, "gfmc_batch_sweep needs chains of one lattice size");
+  const int N = b->chains[0]->d.N;
+  std::vector<double> m((size_t)n);
+  for (int s = 0; s < nsweeps; ++s) {
+    if (b->use_graph) {
+      for (int q = 0; q < N; ++q) HIPCHK(hipGraphLaunch(P.gexec, P.stream));
+    } else {
+      CHK(run_proposals(P, N, nullptr, nullptr));
+    }
+    HIPCHK(launch_magnetization(P.d_desc, n, P.d_mag, P.stream));
+    HIPCHK(hipMemcpyAsync(m.data(), P.d_mag, (size_t)n * 8, hipMemcpyDeviceToHost, P.stream));
+    HIPCHK(hipStreamSynchronize(P.stream));
+    if (mag)
+      for (int i = 0; i < n; ++i) mag[(size_t)b->order[i] * nsweeps + s] = m[i];
+  }
+  for (int i = 0; i < n; ++i)
+    HIPCHK(hipMemcpy(&a1[i], &b->chains[b->order[i]]->desc.ctl->accepted_total, 8,
+                     hipMemcpyDeviceToHost));
+  if (accepted)
+    for (int i = 0; i < n; ++i) accepted[b->order[i]] = a1[i] - a0[i];
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_step_timing(gfmc_batch* b, double* step_ms, int64_t* launches) {
+  if (!b || !step_ms || !launches) return fail(GFMC_EINVAL, "NULL argument");
+  *step_ms = b->plan.step_ms;
+  *launches = b->plan.step_launches;
+  return GFMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// gfmc_device.h -- device-side data layout and small helpers of the gfx950
+// GFMC library.  Included only by the library's own translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gfmc.h"
+
+namespace gfmc {
+
+constexpr int kStepThreads = 256;   // threads per block of the Chebyshev step kernel
+constexpr int kNP = 49;             // moment partial sums per block and step
+constexpr int kReconThreads = 256;  // threads of the reconstruction block (one per chain)
+constexpr int kRecCap = 64;         // proposals per host round trip (records, forcing)
+constexpr int kMagCap = 64;         // sweeps per host round trip (magnetization)
+constexpr int kMaxK = 8192;         // energy nodes held in LDS by the transform
+
+// Complex value and per-site spinor in the recursion precision T.
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+template <typename T>
+struct alignas(16) spn {   // chi = (alpha, beta) = (cos(th/2) e^{-i ph/2}, sin(th/2) e^{i ph/2})
+  T ar, ai, br, bi;
+};
+
+// Per-chain control block (device).  Written by the proposal and
+// reconstruction kernels, read by the Chebyshev steps.
+struct Ctl {
+  int64_t index;            // counter value of the next proposal
+  int64_t accepted_total;   // accepted proposals since creation
+  int32_t mode;             // 0 draw from the counter, 1 host-given site+angles, 2 site only
+  int32_t site;             // proposed site o
+  int32_t parity_o;         // (x+y+z) & 1 of o
+  int32_t o_half;           // half-row index of o
+  int32_t start_site[7];    // o and its neighbours, full site index
+  int32_t start_half[7];    // ... half-row index
+  int32_t own, accepted;
+  double th_old, ph_old, th_new, ph_new, u, dseff, phase_top;
+  double delta[12];         // Delta_{n_d,o}, d = 0..5 (re, im)
+};
+
+// Per-chain descriptor (device table read by the batched kernels).
+struct Desc {
+  int32_t L, N, half, M, S, K, nblk, kernel, proposal, log2K;
+  double t, beta, mu, a, cone, lambda;
+  uint64_t seed, chain_id;
+  double* theta;            // [N]
+  double* phi;              // [N]
+  void* spin;               // spn<T>[2][half]   (parity, half-row index)
+  void* vec;                // cpx<T>[7][2][half] (slot, parity, half-row index)
+  double* part;             // [S][nblk][kNP]
+  double* mom;              // [M][7][7][2]
+  double* gscr;             // [4][K][2]
+  Ctl* ctl;
+};
+
+// Site decomposition of the bipartite layout: site (x,y,z) has parity
+// (x+y+z)&1 and half-row index (x>>1) + (L/2)(y + L z); the two sites of a
+// given half-row index differ only in the low bit of x.
+__host__ __device__ inline int half_index(int x, int y, int z, int L) {
+  return (x >> 1) + (L >> 1) * (y + L * z);
+}
+
+}  // namespace gfmc

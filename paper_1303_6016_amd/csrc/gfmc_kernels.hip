@@ -1,0 +1,798 @@
+// gfmc_kernels.hip -- gfx950 kernels of the GFMC hot path.
+//
+// Per proposal and chain (Algorithm 1, inner loop body; Section 2.2):
+//   k_propose  : Philox draw of site and new direction, bond changes Delta_{n,o}
+//   k_step     : one step of the three-term Chebyshev recursion (equation
+//                "recursive") for the 7 start vectors, matrix-free, fused with
+//                the Gram sums that give two moments per step (equation "mu2")
+//   k_moments  : deferred, compensated sum of the per-block Gram partials and
+//                assembly of mu_n^{jk}, n < M
+//   k_recon    : contraction to the 2x2 block, damping kernel, node transform
+//                by radix-2 FFT (equations "green_short", "green_fft",
+//                "mu_to_mu_tilde"), determinant (equation "d_z_green"),
+//                continuous phase, energy integral (equation "d_seff2"),
+//                Metropolis test and spin update
+//   k_magnetization: |sum_i S_i| / N at the end of a sweep
+#include "gfmc_device.h"
+
+namespace gfmc {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ Philox ------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), counter (c0, c1, 0, 0).
+__device__ inline void philox(uint64_t c0, uint64_t c1, uint64_t k0, uint64_t k1,
+                              uint64_t out[4]) {
+  uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B97F4A7C15ULL;
+      k1 += 0xBB67AE8584CAA73BULL;
+    }
+    const uint64_t m0 = 0xD2E7470EE14C6C93ULL, m1 = 0xCA5A826395121157ULL;
+    uint64_t hi0 = __umul64hi(m0, x0), lo0 = m0 * x0;
+    uint64_t hi1 = __umul64hi(m1, x2), lo1 = m1 * x2;
+    uint64_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+    x0 = y0; x1 = lo1; x2 = y2; x3 = lo0;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+__device__ inline double u01(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
+
+__device__ inline void site_xyz(int i, int L, int& x, int& y, int& z) {
+  x = i % L;
+  y = (i / L) % L;
+  z = i / (L * L);
+}
+
+__device__ inline int neighbor_site(int i, int d, int L) {
+  int x, y, z;
+  site_xyz(i, L, x, y, z);
+  switch (d) {
+    case 0: x = (x + 1 == L) ? 0 : x + 1; break;
+    case 1: x = (x == 0) ? L - 1 : x - 1; break;
+    case 2: y = (y + 1 == L) ? 0 : y + 1; break;
+    case 3: y = (y == 0) ? L - 1 : y - 1; break;
+    case 4: z = (z + 1 == L) ? 0 : z + 1; break;
+    default: z = (z == 0) ? L - 1 : z - 1; break;
+  }
+  return x + L * (y + L * z);
+}
+
+// Half-row index of the neighbour of (x,y,z) in direction d.
+__device__ inline int nb_half(int x, int y, int z, int d, int L) {
+  switch (d) {
+    case 0: x = (x + 1 == L) ? 0 : x + 1; break;
+    case 1: x = (x == 0) ? L - 1 : x - 1; break;
+    case 2: y = (y + 1 == L) ? 0 : y + 1; break;
+    case 3: y = (y == 0) ? L - 1 : y - 1; break;
+    case 4: z = (z + 1 == L) ? 0 : z + 1; break;
+    default: z = (z == 0) ? L - 1 : z - 1; break;
+  }
+  return half_index(x, y, z, L);
+}
+
+// Hopping amplitude from the angles (equation "ht"), FP64.
+__device__ inline void hop_angles(double ti, double pi_, double tj, double pj, double& re,
+                                  double& im) {
+  re = cos(0.5 * (ti - tj)) * cos(0.5 * (pi_ - pj));
+  im = cos(0.5 * (ti + tj)) * sin(0.5 * (pi_ - pj));
+}
+
+template <typename T>
+__device__ inline spn<T> make_spinor(double th, double ph) {
+  double st, ct, sp, cp;
+  sincos(0.5 * th, &st, &ct);
+  sincos(0.5 * ph, &sp, &cp);
+  spn<T> s;
+  s.ar = (T)(ct * cp);
+  s.ai = (T)(-ct * sp);
+  s.br = (T)(st * cp);
+  s.bi = (T)(st * sp);
+  return s;
+}
+
+// <chi_i|chi_j> = t_ij (the same amplitude as equation "ht", from cached
+// half-angle factors).
+template <typename T>
+__device__ inline void hop_spinor(const spn<T>& a, const spn<T>& b, T& re, T& im) {
+  re = a.ar * b.ar + a.ai * b.ai + a.br * b.br + a.bi * b.bi;
+  im = a.ar * b.ai - a.ai * b.ar + a.br * b.bi - a.bi * b.br;
+}
+
+// Block b of a grid of nb blocks runs on XCD b % 8; give each XCD a
+// contiguous range of logical blocks so that lattice planes that neighbour in
+// z are processed under the same L2.
+__device__ inline int xcd_remap(int b, int nb) {
+  const int x = b & 7, i = b >> 3;
+  const int base = nb >> 3, rem = nb & 7;
+  return x * base + (x < rem ? x : rem) + i;
+}
+
+// -------------------------------------------------------------- propose ---
+__global__ void k_propose(const Desc* __restrict__ descs, int n) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const Desc& D = descs[c];
+  Ctl* ctl = D.ctl;
+  int o;
+  double tn, pn, u = 0.0;
+  if (ctl->mode == 0) {
+    uint64_t r[4];
+    philox((uint64_t)ctl->index, 1ULL, D.seed, D.chain_id, r);
+    o = (int)__umul64hi(r[0], (uint64_t)D.N);
+    const double ua = u01(r[1]), ub = u01(r[2]);
+    u = u01(r[3]);
+    if (D.proposal == GFMC_PROPOSE_CONE) {
+      const double t0 = D.theta[o], p0 = D.phi[o];
+      const double st = sin(t0), ct = cos(t0), sp = sin(p0), cp = cos(p0);
+      const double S[3] = {st * cp, st * sp, ct};
+      const double e1[3] = {ct * cp, ct * sp, -st};
+      const double e2[3] = {-sp, cp, 0.0};
+      const double ca = 1.0 - (1.0 - cos(D.cone)) * ua;
+      const double sa = sqrt(fmax(0.0, (1.0 - ca) * (1.0 + ca)));
+      const double psi = 2.0 * M_PI * ub;
+      const double cs = cos(psi), ss = sin(psi);
+      double Sn[3];
+      for (int q = 0; q < 3; ++q) Sn[q] = ca * S[q] + sa * (cs * e1[q] + ss * e2[q]);
+      tn = atan2(sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1]), Sn[2]);
+      pn = atan2(Sn[1], Sn[0]);
+      if (pn < 0) pn += 2.0 * M_PI;
+    } else {
+      tn = acos(1.0 - 2.0 * ua);
+      pn = 2.0 * M_PI * ub;
+    }
+    ctl->site = o;
+    ctl->th_new = tn;
+    ctl->ph_new = pn;
+    ctl->u = u;
+  } else {
+    o = ctl->site;
+    tn = ctl->th_new;
+    pn = ctl->ph_new;
+  }
+  const int L = D.L;
+  int x, y, z;
+  site_xyz(o, L, x, y, z);
+  ctl->parity_o = (x + y + z) & 1;
+  ctl->o_half = half_index(x, y, z, L);
+  ctl->start_site[0] = o;
+  ctl->start_half[0] = ctl->o_half;
+  const double to = D.theta[o], po = D.phi[o];
+  ctl->th_old = to;
+  ctl->ph_old = po;
+  for (int d = 0; d < 6; ++d) {
+    const int nb = neighbor_site(o, d, L);
+    int a, b, cc;
+    site_xyz(nb, L, a, b, cc);
+    ctl->start_site[1 + d] = nb;
+    ctl->start_half[1 + d] = half_index(a, b, cc, L);
+    // Delta_{n,o} = H'_{n,o} - H_{n,o} = -t (t'_{n o} - t_{n o})
+    double r1, i1, r0, i0;
+    hop_angles(D.theta[nb], D.phi[nb], tn, pn, r1, i1);
+    hop_angles(D.theta[nb], D.phi[nb], to, po, r0, i0);
+    ctl->delta[2 * d] = -D.t * (r1 - r0);
+    ctl->delta[2 * d + 1] = -D.t * (i1 - i0);
+  }
+}
+
+// ------------------------------------------------------------ Chebyshev ---
+// One step s >= 1 of |a_s> = c1 Ht'|a_{s-1}> - c2 |a_{s-2}> for the 7 start
+// vectors of every chain in the launch, where Ht' is the hopping part with
+// the factor -t/a folded into c1 (c1 = -t/a, c2 = 0 for s = 1; c1 = -2t/a,
+// c2 = 1 otherwise).  The lattice is bipartite and Ht connects only opposite
+// parities, so a^o_s lives on parity p(o)^(s&1) and the six neighbour
+// vectors a^n_s on the other parity; each site therefore stores one value of
+// a^o and six of a^n, and a_{s+1} overwrites a_{s-1} in place.  Each thread
+// owns the two sites of one half-row index (one per parity): on one it forms
+// a^o_s from the 6 neighbours, on the other the six a^n_s.
+//
+// Moments (equation "mu2", doubling): per step the kernel accumulates
+//   P^{oo}_s = <a^o_s|a^o_s>, P^{de}_s = <a^{n_d}_s|a^{n_e}_s>,
+//   Q^{oe}_s = <a^o_{s-1}|a^{n_e}_s>
+// (the other pairs vanish on a bipartite lattice) as the 16x16 real Gram
+// matrix of the per-thread vector
+//   x = (Re/Im a^{n_0..5}_s, Re/Im a^o_{s-1}  at the n-site,  Re/Im a^o_s at the o-site)
+// summed over the block's sites on the FP64 matrix core, and stores the 49
+// real combinations per block (no reduction on the per-step critical path).
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ descs,
+                                                       const int* __restrict__ blkoff, int nact,
+                                                       int s) {
+  __shared__ double xs[4][64][17];
+  __shared__ double gsum[4][256];
+  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+  int c = 0;
+  {
+    int lo = 0, hi = nact - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (blkoff[mid] <= gb) lo = mid; else hi = mid - 1;
+    }
+    c = lo;
+  }
+  const Desc& D = descs[c];
+  const int lb = gb - blkoff[c];
+  const int L = D.L, hx = L >> 1, half = D.half;
+  const int h = lb * kStepThreads + (int)threadIdx.x;
+  const Ctl* ctl = D.ctl;
+  const int pO = ctl->parity_o;
+  const int po = pO ^ (s & 1);          // parity of the site that carries a^o_s
+  const int pn = po ^ 1;                // parity of the site that carries a^n_s
+  double x[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) x[i] = 0.0;
+
+  if (h < half) {
+    const int k = h % hx, r = h / hx, y = r % L, z = r / L;
+    const int xo = 2 * k + ((y + z + po) & 1);
+    const int xn = 2 * k + ((y + z + pn) & 1);
+    const spn<T>* __restrict__ sp = (const spn<T>*)D.spin;
+    cpx<T>* __restrict__ v = (cpx<T>*)D.vec;
+#define VEC(slot, par, hh) v[((size_t)((slot) * 2 + (par))) * half + (hh)]
+    const T c1 = FIRST ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
+    const int o_half = ctl->o_half;
+
+    // a^o_s on the o-site
+    {
+      const spn<T> si = sp[(size_t)po * half + h];
+      T ar = 0, ai = 0;
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        const int nh = nb_half(xo, y, z, d, L);
+        const spn<T> sj = sp[(size_t)pn * half + nh];
+        T hr, hi_;
+        hop_spinor(si, sj, hr, hi_);
+        cpx<T> an;
+        if (FIRST) { an.x = (nh == o_half) ? (T)1 : (T)0; an.y = 0; }
+        else an = VEC(0, pn, nh);
+        ar += hr * an.x - hi_ * an.y;
+        ai += hr * an.y + hi_ * an.x;
+      }
+      cpx<T> ao;
+      ao.x = c1 * ar;
+      ao.y = c1 * ai;
+      if (!FIRST) {
+        const cpx<T> pr = VEC(0, po, h);
+        ao.x -= pr.x;
+        ao.y -= pr.y;
+      }
+      VEC(0, po, h) = ao;
+      x[14] = (double)ao.x;
+      x[15] = (double)ao.y;
+    }
+    // a^{n_e}_s, e = 0..5, on the n-site
+    {
+      const spn<T> si = sp[(size_t)pn * half + h];
+      T accr[6], acci[6];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        const int nh = nb_half(xn, y, z, d, L);
+        const spn<T> sj = sp[(size_t)po * half + nh];
+        T hr, hi_;
+        hop_spinor(si, sj, hr, hi_);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          cpx<T> an;
+          if (FIRST) { an.x = (nh == ctl->start_half[1 + e]) ? (T)1 : (T)0; an.y = 0; }
+          else an = VEC(1 + e, po, nh);
+          accr[e] += hr * an.x - hi_ * an.y;
+          acci[e] += hr * an.y + hi_ * an.x;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        cpx<T> an;
+        an.x = c1 * accr[e];
+        an.y = c1 * acci[e];
+        if (!FIRST) {
+          const cpx<T> pr = VEC(1 + e, pn, h);
+          an.x -= pr.x;
+          an.y -= pr.y;
+        }
+        VEC(1 + e, pn, h) = an;
+        x[2 * e] = (double)an.x;
+        x[2 * e + 1] = (double)an.y;
+      }
+      cpx<T> aop;   // a^o_{s-1} at the n-site
+      if (FIRST) {
+        aop.x = (h == o_half) ? (T)1 : (T)0;
+        aop.y = 0;
+        // store a_0 on the sites that hold it from now on
+        VEC(0, pn, h) = aop;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          cpx<T> u;
+          u.x = (h == ctl->start_half[1 + e]) ? (T)1 : (T)0;
+          u.y = 0;
+          VEC(1 + e, po, h) = u;
+        }
+      } else {
+        aop = VEC(0, pn, h);
+      }
+      x[12] = (double)aop.x;
+      x[13] = (double)aop.y;
+    }
+#undef VEC
+  }
+
+  // Gram matrix of x over the block on the FP64 matrix core:
+  // v_mfma_f64_16x16x4 with A = B = 4 columns (sites) of 16 components.
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) xs[w][lane][i] = x[i];
+  __syncthreads();
+  d4v acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const double val = xs[w][4 * m + (lane >> 4)][lane & 15];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) gsum[w][(4 * (lane >> 4) + r) * 16 + (lane & 15)] = acc[r];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < kNP) {
+#define G(i, j) (gsum[0][(i) * 16 + (j)] + gsum[1][(i) * 16 + (j)] + gsum[2][(i) * 16 + (j)] + \
+                 gsum[3][(i) * 16 + (j)])
+    double val;
+    if (t == 0) {
+      val = G(14, 14) + G(15, 15);
+    } else if (t < 37) {
+      // P^{de}, d <= e, packed: diagonal -> Re, off-diagonal -> Re, Im
+      int idx = t - 1, d = 0;
+      while (true) {
+        const int len = 1 + 2 * (5 - d);
+        if (idx < len) break;
+        idx -= len;
+        ++d;
+      }
+      if (idx == 0) {
+        val = G(2 * d, 2 * d) + G(2 * d + 1, 2 * d + 1);
+      } else {
+        const int e = d + 1 + (idx - 1) / 2;
+        val = ((idx - 1) & 1) ? G(2 * d, 2 * e + 1) - G(2 * d + 1, 2 * e)
+                              : G(2 * d, 2 * e) + G(2 * d + 1, 2 * e + 1);
+      }
+    } else {
+      const int q = t - 37, e = q >> 1;
+      val = (q & 1) ? G(12, 2 * e + 1) - G(13, 2 * e) : G(12, 2 * e) + G(13, 2 * e + 1);
+    }
+#undef G
+    D.part[((size_t)(s - 1) * D.nblk + lb) * kNP + t] = val;
+  }
+}
+
+// Index of P^{de} (d <= e) in the packed 49-value block partial.
+__device__ inline int pidx(int d, int e) {
+  int idx = 1;
+  for (int q = 0; q < d; ++q) idx += 1 + 2 * (5 - q);
+  return idx + (e == d ? 0 : 1 + 2 * (e - d - 1));
+}
+
+// ------------------------------------------------------------- moments ---
+// grid (Smax, n), 64 threads: sums the block partials of step s with
+// Neumaier compensation and writes mu_{2s-1}, mu_{2s} (and mu_0 for s = 1):
+//   mu_{2s}   = 2 P_s - mu_0,  mu_{2s-1} = 2 Q_s - mu_1  (s >= 2),
+//   mu_1 = Q_1, mu_0^{jk} = [site_j == site_k];
+// pairs that vanish on the bipartite lattice are written as exact zeros and
+// the lower triangle follows from Hermiticity.
+__global__ void k_moments(const Desc* __restrict__ descs) {
+  const Desc& D = descs[blockIdx.y];
+  const int s = blockIdx.x + 1;
+  if (s > D.S) return;
+  __shared__ double P[kNP];
+  __shared__ double Q1[12];
+  const int t = threadIdx.x;
+  const int nblk = D.nblk;
+  if (t < kNP || (t < kNP + 12 && s > 1)) {
+    const int step = (t < kNP) ? s - 1 : 0;
+    const int p = (t < kNP) ? t : 37 + (t - kNP);
+    const double* src = D.part + (size_t)step * nblk * kNP + p;
+    double sum = 0.0, comp = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      const double v = src[(size_t)b * kNP];
+      const double tt = sum + v;
+      comp += (fabs(sum) >= fabs(v)) ? (sum - tt) + v : (v - tt) + sum;
+      sum = tt;
+    }
+    if (t < kNP) P[t] = sum + comp; else Q1[t - kNP] = sum + comp;
+  }
+  __syncthreads();
+  if (t >= 49) return;
+  const int j = t / 7, k = t % 7;
+  const Ctl* ctl = D.ctl;
+  const double d0 = (ctl->start_site[j] == ctl->start_site[k]) ? 1.0 : 0.0;
+  double* mom = D.mom;
+  auto put = [&](int n, double re, double im) {
+    mom[(((size_t)n * 7 + j) * 7 + k) * 2] = re;
+    mom[(((size_t)n * 7 + j) * 7 + k) * 2 + 1] = im;
+  };
+  auto q1 = [&](int e, double& re, double& im) {
+    if (s == 1) { re = P[37 + 2 * e]; im = P[38 + 2 * e]; }
+    else { re = Q1[2 * e]; im = Q1[2 * e + 1]; }
+  };
+  if (s == 1) put(0, d0, 0.0);
+  // odd moment n = 2s - 1
+  {
+    double re = 0.0, im = 0.0;
+    if ((j == 0) != (k == 0)) {
+      const int e = (j == 0) ? k - 1 : j - 1;
+      double r1, i1;
+      q1(e, r1, i1);
+      if (s == 1) { re = r1; im = i1; }
+      else { re = 2.0 * P[37 + 2 * e] - r1; im = 2.0 * P[38 + 2 * e] - i1; }
+      if (j != 0) im = -im;   // mu^{e o} = conj(mu^{o e})
+    }
+    put(2 * s - 1, re, im);
+  }
+  // even moment n = 2s
+  if (2 * s < D.M) {
+    double re = 0.0, im = 0.0;
+    if (j == 0 && k == 0) {
+      re = 2.0 * P[0] - 1.0;
+    } else if (j > 0 && k > 0) {
+      const int d = (j < k ? j : k) - 1, e = (j < k ? k : j) - 1;
+      const int ix = pidx(d, e);
+      re = 2.0 * P[ix] - d0;
+      im = (d == e) ? 0.0 : 2.0 * P[ix + 1];
+      if (j > k) im = -im;
+    } else {
+      re = -d0;
+    }
+    put(2 * s, re, im);
+  }
+}
+
+// -------------------------------------------------------- reconstruction ---
+__device__ inline int bitrev(int v, int bits) {
+  return (int)(__brev((unsigned)v) >> (32 - bits));
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// One block per chain.  mode 0: proposal from the counter (Metropolis,
+// update, counter advance); mode 1/2: evaluation only.
+__global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict__ descs,
+                                                         const int32_t* __restrict__ force,
+                                                         gfmc_step_record* __restrict__ recs) {
+  extern __shared__ double2 buf[];   // [K]
+  __shared__ double red[kReconThreads];
+  __shared__ double tot[kReconThreads];
+  const int c = blockIdx.x;
+  const Desc& D = descs[c];
+  Ctl* ctl = D.ctl;
+  const int M = D.M, K = D.K, lg = D.log2K, tid = threadIdx.x;
+  const double a = D.a;
+  double dl[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) dl[i] = ctl->delta[i];
+  const double2* __restrict__ mom = (const double2*)D.mom;   // [M][7][7]
+  double2* __restrict__ gs = (double2*)D.gscr;                // [4][K]
+
+  // Four real series: 0 mu^{oo}, 1 mu^{vv}, 2 Re mu^{ov}, 3 Im mu^{ov};
+  // mu^{vo} = conj(mu^{ov}) (Hermitian moments), so G_vo uses the same series.
+  for (int q = 0; q < 4; ++q) {
+    for (int m = tid; m < K; m += kReconThreads) {
+      double val = 0.0;
+      if (m < M) {
+        const double2* mm = mom + (size_t)m * 49;
+        double x;
+        if (q == 0) {
+          x = mm[0].x;
+        } else if (q == 1) {
+          double re = 0.0;
+          for (int d = 0; d < 6; ++d) {
+            double sr = 0.0, si = 0.0;   // sum_e delta_e mu^{de}
+            for (int e = 0; e < 6; ++e) {
+              const double2 me = mm[(1 + d) * 7 + 1 + e];
+              sr += dl[2 * e] * me.x - dl[2 * e + 1] * me.y;
+              si += dl[2 * e] * me.y + dl[2 * e + 1] * me.x;
+            }
+            re += dl[2 * d] * sr + dl[2 * d + 1] * si;   // Re(conj(delta_d) * (...))
+          }
+          x = re;
+        } else {
+          double sr = 0.0, si = 0.0;
+          for (int e = 0; e < 6; ++e) {
+            const double2 me = mm[1 + e];
+            sr += dl[2 * e] * me.x - dl[2 * e + 1] * me.y;
+            si += dl[2 * e] * me.y + dl[2 * e + 1] * me.x;
+          }
+          x = (q == 2) ? sr : si;
+        }
+        double g;
+        if (D.kernel == GFMC_LORENTZ) {
+          g = sinh(D.lambda * (1.0 - (double)m / M)) / sinh(D.lambda);
+        } else {
+          const double qn = (double)m / (M + 1.0);
+          g = ((M - m + 1.0) * cospi(qn) + sinpi(qn) * cospi(1.0 / (M + 1.0)) /
+                                               sinpi(1.0 / (M + 1.0))) / (M + 1.0);
+        }
+        val = g * x;
+        if (m == 0) val *= 0.5;
+      }
+      double sn, cs;   // c_m = mu'_m exp(-i pi m / (2K))
+      sincospi(-(double)m / (2.0 * K), &sn, &cs);
+      buf[bitrev(m, lg)] = make_double2(val * cs, val * sn);
+    }
+    __syncthreads();
+    // radix-2 decimation-in-time FFT, gamma_n = sum_m c_m exp(-2 pi i m n / K)
+    for (int len = 2; len <= K; len <<= 1) {
+      const int hl = len >> 1;
+      for (int b = tid; b < (K >> 1); b += kReconThreads) {
+        const int j = b % hl, base = (b / hl) * len;
+        double sn, cs;
+        sincospi(-2.0 * j / len, &sn, &cs);
+        const double2 u = buf[base + j];
+        const double2 t = cmul(buf[base + j + hl], make_double2(cs, sn));
+        buf[base + j] = make_double2(u.x + t.x, u.y + t.y);
+        buf[base + j + hl] = make_double2(u.x - t.x, u.y - t.y);
+      }
+      __syncthreads();
+    }
+    // chi_{2j} = gamma_j, chi_{2j+1} = conj(gamma_{K-j-1}); Gt_k = 2i chi_k / sin th_k
+    for (int k = tid; k < K; k += kReconThreads) {
+      const int j = k >> 1;
+      double2 chi = buf[j];
+      if (k & 1) {
+        chi = buf[K - j - 1];
+        chi.y = -chi.y;
+      }
+      const double st = sinpi((k + 0.5) / K);
+      gs[(size_t)q * K + k] = make_double2(-2.0 * chi.y / st, 2.0 * chi.x / st);
+    }
+    __syncthreads();
+  }
+  // d_k = (1 + G_ov)(1 + G_vo) - G_oo G_vv with G = Gt / a
+  const double ia = 1.0 / a;
+  for (int k = tid; k < K; k += kReconThreads) {
+    const double2 goo = gs[k], gvv = gs[(size_t)K + k], R = gs[2 * (size_t)K + k],
+                  I = gs[3 * (size_t)K + k];
+    const double2 p = make_double2(1.0 + ia * (R.x - I.y), ia * (R.y + I.x));   // 1 + G_ov
+    const double2 m = make_double2(1.0 + ia * (R.x + I.y), ia * (R.y - I.x));   // 1 + G_vo
+    const double2 pm = cmul(p, m);
+    const double2 gg = cmul(goo, gvv);
+    buf[k] = make_double2(pm.x - ia * ia * gg.x, pm.y - ia * ia * gg.y);
+  }
+  __syncthreads();
+  // Continuous phase from the lowest node (k = K-1) upwards:
+  // phi_k = Arg d_{K-1} + sum_{j=k}^{K-2} Arg(d_j conj(d_{j+1})), as a chunked suffix sum.
+  const int chunk = (K + kReconThreads - 1) / kReconThreads;
+  const int k0 = tid * chunk, k1 = min(K, k0 + chunk);
+  auto inc = [&](int k) -> double {
+    if (k == K - 1) return atan2(buf[k].y, buf[k].x);
+    const double2 r = cmul(buf[k], make_double2(buf[k + 1].x, -buf[k + 1].y));
+    return atan2(r.y, r.x);
+  };
+  double csum = 0.0;
+  for (int k = k0; k < k1; ++k) csum += inc(k);
+  tot[tid] = csum;
+  __syncthreads();
+  if (tid == 0) {
+    double acc = 0.0;
+    for (int i = kReconThreads - 1; i >= 0; --i) {
+      const double v = tot[i];
+      tot[i] = acc;   // sum over later chunks
+      acc += v;
+    }
+  }
+  __syncthreads();
+  double phi = tot[tid], part = 0.0, ptop = 0.0;
+  for (int k = k1 - 1; k >= k0; --k) {
+    phi += inc(k);
+    const double sth = sinpi((k + 0.5) / K);
+    const double e = a * cospi((k + 0.5) / K);
+    const double xx = D.beta * (e - D.mu);
+    double f;
+    if (xx > 0) { const double qq = exp(-xx); f = qq / (1.0 + qq); }
+    else f = 1.0 / (1.0 + exp(xx));
+    part += f * sth * phi;
+    if (k == 0) ptop = phi;
+  }
+  red[tid] = part;
+  __syncthreads();
+  for (int w = kReconThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double ds = D.beta * a / K * red[0];
+    ctl->dseff = ds;
+    ctl->phase_top = ptop;
+    if (ctl->mode == 0) {
+      const double u = ctl->u;
+      const int own = (ds <= 0.0 || u < exp(-ds)) ? 1 : 0;
+      const int f = force ? force[c] : -1;
+      const int acc = f < 0 ? own : (f ? 1 : 0);
+      const int o = ctl->site;
+      if (recs) {
+        gfmc_step_record& R = recs[c];
+        R.index = ctl->index; R.site = o; R.own = own; R.accepted = acc; R.pad_ = 0;
+        R.theta_old = ctl->th_old; R.phi_old = ctl->ph_old;
+        R.theta_new = ctl->th_new; R.phi_new = ctl->ph_new;
+        R.dseff = ds; R.u = u; R.phase_top = ptop;
+      }
+      ctl->own = own;
+      ctl->accepted = acc;
+      if (acc) {
+        D.theta[o] = ctl->th_new;
+        D.phi[o] = ctl->ph_new;
+      }
+      ctl->index += 1;
+      ctl->accepted_total += acc;
+    }
+  }
+}
+
+// Spinor cache update for an accepted move (separate so that it runs in the
+// recursion precision).
+template <typename T>
+__global__ void k_accept_spinor(const Desc* __restrict__ descs, int n) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const Desc& D = descs[c];
+  const Ctl* ctl = D.ctl;
+  if (ctl->mode != 0 || !ctl->accepted) return;
+  spn<T>* sp = (spn<T>*)D.spin;
+  sp[(size_t)ctl->parity_o * D.half + ctl->o_half] = make_spinor<T>(ctl->th_new, ctl->ph_new);
+}
+
+// ---------------------------------------------------------- per-site ops ---
+template <typename T>
+__global__ void k_spinors(const Desc* __restrict__ descs) {
+  const Desc& D = descs[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.N) return;
+  int x, y, z;
+  site_xyz(i, D.L, x, y, z);
+  spn<T>* sp = (spn<T>*)D.spin;
+  sp[(size_t)((x + y + z) & 1) * D.half + half_index(x, y, z, D.L)] =
+      make_spinor<T>(D.theta[i], D.phi[i]);
+}
+
+// Initial spins: mode 0 uniform on the sphere from counter (i, 2, 0, 0);
+// modes 1, 2 ferromagnetic (the random subset of mode 2 follows in k_fisher_yates).
+__global__ void k_init_spins(const Desc* __restrict__ descs, int mode) {
+  const Desc& D = descs[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.N) return;
+  if (mode == 0) {
+    uint64_t r[4];
+    philox((uint64_t)i, 2ULL, D.seed, D.chain_id, r);
+    D.theta[i] = acos(1.0 - 2.0 * u01(r[0]));
+    D.phi[i] = 2.0 * M_PI * u01(r[1]);
+  } else {
+    D.theta[i] = 0.0;
+    D.phi[i] = 0.0;
+  }
+}
+
+// Exactly nr distinct sites by a partial Fisher-Yates shuffle (pick k from
+// counter (k, 3, 0, 0)), each redrawn on the sphere from (site, 2, 0, 0).
+// Sequential by construction; `perm` is N int32 of scratch.
+__global__ void k_fisher_yates(const Desc* __restrict__ descs, int64_t nr, int32_t* perm) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const Desc& D = descs[0];
+  const int64_t N = D.N;
+  for (int64_t i = 0; i < N; ++i) perm[i] = (int32_t)i;
+  for (int64_t k = 0; k < nr; ++k) {
+    uint64_t r[4];
+    philox((uint64_t)k, 3ULL, D.seed, D.chain_id, r);
+    const int64_t j = k + (int64_t)__umul64hi(r[0], (uint64_t)(N - k));
+    const int32_t tmp = perm[k];
+    perm[k] = perm[j];
+    perm[j] = tmp;
+  }
+  for (int64_t k = 0; k < nr; ++k) {
+    const int i = perm[k];
+    uint64_t r[4];
+    philox((uint64_t)i, 2ULL, D.seed, D.chain_id, r);
+    D.theta[i] = acos(1.0 - 2.0 * u01(r[0]));
+    D.phi[i] = 2.0 * M_PI * u01(r[1]);
+  }
+}
+
+// |sum_i S_i| / N, one block per chain, written to out[c].
+__global__ void k_magnetization(const Desc* __restrict__ descs, double* __restrict__ out) {
+  __shared__ double rs[3][256];
+  const Desc& D = descs[blockIdx.x];
+  double sx = 0, sy = 0, sz = 0;
+  for (int i = threadIdx.x; i < D.N; i += blockDim.x) {
+    double st, ct, sp, cp;
+    sincos(D.theta[i], &st, &ct);
+    sincos(D.phi[i], &sp, &cp);
+    sx += st * cp;
+    sy += st * sp;
+    sz += ct;
+  }
+  rs[0][threadIdx.x] = sx;
+  rs[1][threadIdx.x] = sy;
+  rs[2][threadIdx.x] = sz;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 3; ++q) rs[q][threadIdx.x] += rs[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    out[blockIdx.x] = sqrt(rs[0][0] * rs[0][0] + rs[1][0] * rs[1][0] + rs[2][0] * rs[2][0]) / D.N;
+}
+
+// ------------------------------------------------------------ launchers ---
+hipError_t launch_propose(const Desc* d, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_propose, dim3((n + 63) / 64), dim3(64), 0, st, d, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_t(const Desc* d, const int* blkoff, int nact, int blocks, int s,
+                         hipStream_t st) {
+  if (s == 1)
+    hipLaunchKernelGGL((k_step<T, true>), dim3(blocks), dim3(kStepThreads), 0, st, d, blkoff,
+                       nact, s);
+  else
+    hipLaunchKernelGGL((k_step<T, false>), dim3(blocks), dim3(kStepThreads), 0, st, d, blkoff,
+                       nact, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(int fp32, const Desc* d, const int* blkoff, int nact, int blocks, int s,
+                       hipStream_t st) {
+  return fp32 ? launch_step_t<float>(d, blkoff, nact, blocks, s, st)
+              : launch_step_t<double>(d, blkoff, nact, blocks, s, st);
+}
+
+hipError_t launch_moments(const Desc* d, int n, int smax, hipStream_t st) {
+  hipLaunchKernelGGL(k_moments, dim3(smax, n), dim3(64), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
+                        gfmc_step_record* recs, hipStream_t st) {
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipFuncSetAttribute((const void*)k_recon, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        kMaxK * (int)sizeof(double2));
+    attr_done = true;
+  }
+  hipLaunchKernelGGL(k_recon, dim3(n), dim3(kReconThreads), (size_t)kmax * sizeof(double2), st,
+                     d, force, recs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (fp32)
+    hipLaunchKernelGGL(k_accept_spinor<float>, dim3((n + 63) / 64), dim3(64), 0, st, d, n);
+  else
+    hipLaunchKernelGGL(k_accept_spinor<double>, dim3((n + 63) / 64), dim3(64), 0, st, d, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t st) {
+  dim3 g((nmax + 255) / 256, n);
+  if (fp32) hipLaunchKernelGGL(k_spinors<float>, g, dim3(256), 0, st, d);
+  else hipLaunchKernelGGL(k_spinors<double>, g, dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_spins, dim3((nmax + 255) / 256, 1), dim3(256), 0, st, d, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st) {
+  hipLaunchKernelGGL(k_fisher_yates, dim3(1), dim3(1), 0, st, d, nr, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_magnetization, dim3(n), dim3(256), 0, st, d, out);
+  return hipGetLastError();
+}
+
+}  // namespace gfmc

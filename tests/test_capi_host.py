@@ -1,0 +1,52 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+that include/gfmc.h declares, and validates parameters without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gfmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gfmc_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1303_6016_amd as g
+    L = g.lib()
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(g.EXPORTS)
+    assert L.gfmc_version().decode().startswith("gfmc")
+
+
+def _bytes(**kw):
+    import paper_1303_6016_amd as g
+    return g.gfmc_workspace_bytes(g.Params(**kw))
+
+
+@pytest.mark.parametrize("kw", [dict(L=3), dict(L=0), dict(L=4, M=7), dict(L=4, M=256, K=300),
+                                dict(L=4, M=512, K=256), dict(L=4, beta=0.0), dict(L=4, t=-1.0),
+                                dict(L=4, scale_b=0.1), dict(L=4, scale_a=1.0),
+                                dict(L=4, proposal=1, cone_angle=0.0), dict(L=4, precision=5),
+                                dict(L=4, M=16384)])
+def test_invalid_parameters_are_rejected(kw):
+    import paper_1303_6016_amd as g
+    with pytest.raises(g.GfmcError) as e:
+        _bytes(**kw)
+    assert e.value.status == g.GFMC_EINVAL
+
+
+def test_workspace_size_follows_layout():
+    # the bipartite layout stores 7 complex values per site in the recursion precision
+    b64 = _bytes(L=32, M=2048, precision=0)
+    b32 = _bytes(L=32, M=2048, precision=1)
+    N = 32 ** 3
+    assert b64 - b32 >= 7 * N * 8 + 2 * N * 4 * 2
+    assert b64 > 7 * N * 16

@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (absolute; |mu| <= 1):
+  moments     FP64 1e-12, FP32 recursion / FP64 sums 1e-5
+  Delta S     FP64 1e-10, FP32 2e-5
+  RNG, sites, Metropolis draws: bit-exact; new angles within a few ulp
+  (device and host libm may round acos/atan2 differently).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FP64_MU, FP32_MU = 1e-12, 1e-5
+FP64_DS, FP32_DS = 1e-10, 2e-5
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1303_6016_amd as g
+    g.lib()
+    return g
+
+
+def make(g, L, M, prec=0, seed=0, chain_id=0, **kw):
+    p = g.Params(L=L, M=M, precision=prec, seed=seed, chain_id=chain_id, **kw)
+    m = oracle.Model(L=L, M=M, seed=seed, chain_id=chain_id,
+                     **{k: v for k, v in kw.items() if k in ("t", "beta", "mu", "K")})
+    if "proposal" in kw:
+        m.proposal = kw["proposal"]
+    if "cone_angle" in kw:
+        m.cone = kw["cone_angle"]
+    if "kernel" in kw:
+        m.kernel = kw["kernel"]
+    if kw.get("lorentz_lambda"):
+        m.lam = kw["lorentz_lambda"]
+    return g.Chain(p), m
+
+
+# ----------------------------------------------------------------- moments --
+@pytest.mark.parametrize("L,M,seed,sites", [(2, 32, 1, [0, 5]), (4, 256, 2, [0, 1, 37, 63]),
+                                            (6, 128, 3, [0, 100, 215]), (8, 256, 4, [3, 511])])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_moments_small(g, L, M, seed, sites, prec):
+    ch, m = make(g, L, M, prec)
+    th, ph = synth.random_angles(m.N, seed)
+    ch.set_spins(th, ph)
+    tol = FP64_MU if prec == 0 else FP32_MU
+    for o in sites:
+        got = ch.moments(o)
+        ref = oracle.moments(m, th, ph, o)
+        err = np.abs(got - ref).max()
+        print(f"L={L} M={M} prec={prec} site={o} max|dmu|={err:.2e}", flush=True)
+        assert err < tol
+
+
+def test_moments_16cubed_ferro_plus_random(g):
+    ch, m = make(g, 16, 1024, 0, seed=42)
+    ch.init_spins(g.INIT_FM_PLUS_RANDOM, 0.1)
+    th, ph = ch.get_spins()
+    tho, pho = oracle.init_spins(m, 2, 0.1)
+    assert np.array_equal(th != 0, tho != 0) and (th != 0).sum() == 409
+    assert np.array_equal(ph, pho)
+    assert np.abs(th - tho).max() <= 4 * np.spacing(np.pi)
+    for o in (0, 2049):
+        err = np.abs(ch.moments(o) - oracle.moments(m, th, ph, o)).max()
+        print(f"16^3 M=1024 site={o} max|dmu|={err:.2e}", flush=True)
+        assert err < FP64_MU
+
+
+@pytest.mark.parametrize("prec,tol", [(0, FP64_MU), (1, FP32_MU)])
+def test_moments_32cubed_full_size_sampled(g, prec, tol):
+    # the workload size of the benchmark: one sampled site, oracle one by one
+    ch, m = make(g, 32, 2048, prec, seed=7, chain_id=3)
+    ch.init_spins(g.INIT_RANDOM)
+    th, ph = ch.get_spins()
+    o = 12345
+    ref = oracle.moments(m, th, ph, o)
+    err = np.abs(ch.moments(o) - ref).max()
+    print(f"32^3 M=2048 prec={prec} max|dmu|={err:.2e}", flush=True)
+    assert err < tol
+
+
+def test_moment_invariants_on_device(g):
+    ch, m = make(g, 8, 128, 0)
+    th, ph = synth.random_angles(m.N, 12)
+    ch.set_spins(th, ph)
+    mu = ch.moments(77)
+    assert np.abs(mu[0] - np.eye(7)).max() == 0
+    assert np.abs(mu - mu.conj().transpose(0, 2, 1)).max() < 1e-14
+    assert np.abs(mu).max() <= 1 + 1e-12
+    assert np.all(mu[1::2, 0, 0] == 0) and np.all(mu[0::2, 0, 1:] == 0)
+
+
+# ----------------------------------------------------------------- Delta S --
+@pytest.mark.parametrize("L,M,K,beta", [(4, 256, 0, 20.0), (6, 256, 512, 5.0), (8, 512, 0, 20.0),
+                                        (4, 64, 0, 0.5)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_delta_seff(g, L, M, K, beta, prec):
+    ch, m = make(g, L, M, prec, beta=beta, K=K)
+    th, ph = synth.random_angles(m.N, 5)
+    ch.set_spins(th, ph)
+    tol = FP64_DS if prec == 0 else FP32_DS
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        o = int(rng.integers(m.N))
+        tn, pn = float(np.arccos(rng.uniform(-1, 1))), float(rng.uniform(0, 2 * np.pi))
+        got, top = ch.delta_seff(o, tn, pn, with_phase_top=True)
+        ref, rtop = oracle.delta_seff(m, th, ph, o, tn, pn, with_phase_top=True)
+        print(f"L={L} M={M} K={K} beta={beta} prec={prec} dS={ref:.6f} err={got - ref:.2e}",
+              flush=True)
+        assert abs(got - ref) < tol
+        assert abs(top - rtop) < 1e-8
+
+
+def test_delta_seff_lorentz_and_identity(g):
+    ch, m = make(g, 4, 128, 0, kernel=1, lorentz_lambda=4.0)
+    th, ph = synth.random_angles(m.N, 9)
+    ch.set_spins(th, ph)
+    got = ch.delta_seff(10, 1.0, 2.0)
+    assert abs(got - oracle.delta_seff(m, th, ph, 10, 1.0, 2.0)) < FP64_DS
+    assert ch.delta_seff(10, th[10], ph[10]) == 0.0
+
+
+# ---------------------------------------------------- teacher-forced chains --
+def run_forced(g, ch, m, th, ph, nprop, prec):
+    tol = FP64_DS if prec == 0 else FP32_DS
+    forced = 0
+    for idx in range(nprop):
+        ro = oracle.step(m, th, ph, idx)
+        rg = ch.step(force=ro.accepted)
+        assert rg.index == ro.index == idx
+        assert rg.site == ro.site and rg.u == ro.u
+        assert abs(rg.theta_new - ro.theta_new) <= 4 * np.spacing(max(ro.theta_new, 1.0))
+        assert abs(rg.phi_new - ro.phi_new) <= 4 * np.spacing(max(ro.phi_new, 1.0))
+        assert abs(rg.dseff - ro.dseff) < tol, (idx, rg.dseff, ro.dseff)
+        near = abs(math.log(ro.u) + ro.dseff) < 10 * tol if ro.u > 0 else False
+        if rg.own != ro.own:
+            assert near, (idx, rg.dseff, ro.dseff, ro.u)
+            forced += 1
+        assert rg.accepted == ro.accepted
+    gth, gph = ch.get_spins()
+    assert np.abs(gth - th).max() < 1e-13 and np.abs(gph - ph).max() < 1e-13
+    return forced
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_trajectory_4cubed_two_sweeps(g, seed):
+    # 4^3, M = 256, Jackson, beta = 20, mu = 0, uniform-sphere start and proposals
+    ch, m = make(g, 4, 256, 0, seed=seed, beta=20.0)
+    ch.init_spins(g.INIT_RANDOM)
+    th, ph = oracle.init_spins(m, 0)
+    gth, gph = ch.get_spins()
+    assert np.array_equal(gph, ph) and np.abs(gth - th).max() <= 4 * np.spacing(np.pi)
+    ch.set_spins(th, ph)
+    forced = run_forced(g, ch, m, th, ph, 2 * m.N, 0)
+    print(f"seed={seed}: 128 proposals, forced decisions {forced}", flush=True)
+
+
+def test_trajectory_16cubed_prefix_cone(g):
+    # 16^3, M = 1024, T = 0.05, FM + 10% random start, cap proposals of 0.3 rad
+    ch, m = make(g, 16, 1024, 0, seed=42, beta=20.0, proposal=1, cone_angle=0.3)
+    th, ph = oracle.init_spins(m, 2, 0.1)
+    ch.set_spins(th, ph)
+    forced = run_forced(g, ch, m, th, ph, 12, 0)
+    print(f"16^3 prefix: forced {forced}", flush=True)
+
+
+def test_trajectory_fp32(g):
+    ch, m = make(g, 8, 256, 1, seed=4, beta=10.0)
+    th, ph = synth.random_angles(m.N, 4)
+    ch.set_spins(th, ph)
+    run_forced(g, ch, m, th, ph, 24, 1)
+
+
+def test_sweep_matches_oracle(g):
+    ch, m = make(g, 4, 128, 0, seed=11, beta=8.0)
+    th, ph = synth.random_angles(m.N, 11)
+    ch.set_spins(th, ph)
+    # oracle trajectory with its own decisions; the device must take the same
+    # ones unless an event lands within rounding of the Metropolis threshold
+    recs = []
+    t2, p2 = th.copy(), ph.copy()
+    for idx in range(m.N):
+        recs.append(oracle.step(m, t2, p2, idx))
+    if any(abs(math.log(r.u) + r.dseff) < 1e-9 for r in recs if r.u > 0):
+        pytest.skip("threshold tie in this seed")
+    mag, acc = ch.sweep(1)
+    gth, gph = ch.get_spins()
+    assert acc == sum(r.accepted for r in recs)
+    assert np.abs(gth - t2).max() < 1e-13 and np.abs(gph - p2).max() < 1e-13
+    assert abs(mag[0] - oracle.magnetization(4, t2, p2)) < 1e-14
+    assert ch.get_counter() == m.N
+
+
+# ------------------------------------------------------------------ batches --
+def test_batch_results_equal_single_chains(g):
+    specs = [(4, 256, 0.05), (6, 128, 0.1), (8, 256, 0.2), (4, 64, 0.02)]
+    def build():
+        out = []
+        for i, (L, M, T) in enumerate(specs):
+            ch, _ = make(g, L, M, 1, seed=100 + i, beta=1.0 / T)
+            ch.init_spins(g.INIT_RANDOM)
+            out.append(ch)
+        return out
+    alone = build()
+    ref = [[ch.step() for _ in range(6)] for ch in alone]
+    mixed = build()
+    b = g.Batch(mixed)
+    recs = b.step(6, records=True)
+    for q in range(6):
+        for i in range(len(specs)):
+            r, a = recs[q][i], ref[i][q]
+            assert (r.site, r.accepted, r.u) == (a.site, a.accepted, a.u)
+            assert r.dseff == a.dseff
+    b.close()
+    for x, y in zip(alone, mixed):
+        assert np.array_equal(x.get_spins()[0], y.get_spins()[0])
+
+
+def test_batch_graph_replay_matches_direct(g):
+    def build():
+        chs = []
+        for i in range(3):
+            ch, _ = make(g, 6, 128, 0, seed=7, chain_id=i, beta=10.0)
+            ch.init_spins(g.INIT_RANDOM)
+            chs.append(ch)
+        return chs
+    a, b = build(), build()
+    ba, bb = g.Batch(a), g.Batch(b)
+    ba.step(5)
+    bb.use_graph(True)
+    for _ in range(5):
+        bb.step(1)
+        bb.chains[0].stream.synchronize()
+    ba.close()
+    bb.close()
+    for x, y in zip(a, b):
+        assert np.array_equal(x.get_spins()[0], y.get_spins()[0])
+        assert x.get_counter() == y.get_counter() == 5
