@@ -1,0 +1,161 @@
+"""Benchmark of the GFMC hot path on one MI355X.
+
+Workload (one "step"): one Metropolis proposal on each of 64 independent
+chains of a 32^3 periodic cubic lattice, M = 2048 Chebyshev moments, FP32
+recursion with FP64 moment sums, temperatures linearly spaced in
+[0.02t, 0.2t], uniform-sphere starts from seed 7 (chain_id = chain index).
+A proposal runs the whole path: Philox draw, bond changes, M/2 fused
+Chebyshev steps over the 7 start vectors, moment assembly, reconstruction
+(FFT transform, determinant, phase, energy integral), Metropolis update.
+
+Prints ONE JSON line (rank 0).  value = Chebyshev site-vector updates per
+second over the whole job (N * 7 * M/2 per proposal).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+L, M, NCHAIN = 32, 2048, 64
+T_LO, T_HI = 0.02, 0.2
+SEED = 7
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-single", action="store_true")
+    ap.add_argument("--graph", type=int, default=0, help="replay one proposal as a HIP graph")
+    return ap.parse_args()
+
+
+def cpu_baseline(n_prop: int = 2):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same
+    workload: n_prop proposals of one 32^3, M = 2048 chain."""
+    import numpy as np
+    import oracle
+    m = oracle.Model(L=L, M=M, beta=1.0 / T_LO, seed=SEED, chain_id=0)
+    th, ph = oracle.init_spins(m, 0)
+    t0 = time.perf_counter()
+    for idx in range(n_prop):
+        oracle.step(m, th, ph, idx)
+    dt = time.perf_counter() - t0
+    svu = n_prop * m.N * 7 * (M // 2)
+    return {"value": svu / dt, "unit": "svu/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_prop} proposals of one 32^3 M=2048 chain (FP64, single thread), "
+                      f"{dt:.1f} s; svu counted as N*7*M/2 per proposal",
+            "mc_spin_updates_per_s": n_prop / dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_1303_6016_amd as g
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    temps = synth.temperature_ladder(NCHAIN, T_LO, T_HI)
+    chains = []
+    for c in range(NCHAIN):
+        p = g.Params(L=L, M=M, beta=1.0 / temps[c], mu=0.0, precision=g.FP32_ACC64,
+                     seed=SEED, chain_id=c)
+        ch = g.Chain(p, device=dev)
+        ch.init_spins(g.INIT_RANDOM)
+        chains.append(ch)
+    batch = g.Batch(chains)
+    if args.graph:
+        batch.use_graph(True)
+    stream = batch.stream
+    bytes_per_step, nsteps = chains[0].step_bytes()
+    N = L ** 3
+    svu_per_prop = N * 7 * (M // 2)
+
+    for _ in range(args.warmup):
+        batch.step(1)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, per-step events for the latency distribution
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    step_ms_total, launches_total = 0.0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for k in range(args.steps):
+        batch.step(1)
+        ms, nl = batch.step_timing()
+        step_ms_total += ms
+        launches_total += nl
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]) / 1e3
+    total_s = float(lat.sum())
+    ms_per_step = 1e3 * total_s / args.steps
+    value = args.steps * NCHAIN * svu_per_prop / total_s
+
+    # dominant kernel: the Chebyshev step, averaged over every launch in the timed region
+    avg_launch_s = step_ms_total / 1e3 / max(launches_total, 1)
+    bytes_per_launch = NCHAIN * bytes_per_step
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_step<float>", "avg_launch_us": avg_launch_s * 1e6,
+            "bytes_per_launch": bytes_per_launch}
+
+    out = {
+        "metric": "Chebyshev site-vector updates/s + MC spin updates/s at 32^3; p50/p99 sweep latency",
+        "value": value, "unit": "svu/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "32^3 lattice x 64 chains, M=2048, FP32 recursion / FP64 moment "
+                               "sums, T=0.02..0.2 t, uniform-sphere starts (seed 7)",
+                   "L": L, "M": M, "chains": NCHAIN, "graph": bool(args.graph)},
+        "mc_spin_updates_per_s": args.steps * NCHAIN / total_s,
+        "step_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "sweep_latency_s": {"p50": float(np.percentile(lat, 50)) * N,
+                            "p99": float(np.percentile(lat, 99)) * N,
+                            "note": "extrapolated: one sweep = N batched steps"},
+        "wall_s": wall,
+        "roofline": roof,
+    }
+
+    if not args.no_fp64_single:
+        p = g.Params(L=L, M=M, beta=1.0 / T_LO, precision=g.FP64, seed=SEED, chain_id=0)
+        ch = g.Chain(p, device=dev)
+        ch.init_spins(g.INIT_RANDOM)
+        ch.step()
+        torch.cuda.synchronize()
+        n1 = 4
+        t1 = time.perf_counter()
+        for _ in range(n1):
+            ch.step()
+        torch.cuda.synchronize()
+        d1 = time.perf_counter() - t1
+        out["fp64_single_chain"] = {"mc_spin_updates_per_s": n1 / d1,
+                                    "svu_per_s": n1 * svu_per_prop / d1,
+                                    "proposals": n1}
+        out["batched_vs_fp64_single_speedup"] = out["mc_spin_updates_per_s"] / (n1 / d1)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

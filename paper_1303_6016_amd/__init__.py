@@ -255,7 +255,8 @@ class Batch:
         self.chains = list(chains)
         dev = self.chains[0].device
         with torch.cuda.device(dev):
-            self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+            # a stream of its own: the legacy default stream cannot be captured
+            self.stream = stream if stream is not None else torch.cuda.Stream(dev)
             arr = (ctypes.c_void_p * len(self.chains))(*[c.h.value for c in self.chains])
             n = ctypes.c_size_t()
             _check(lib().gfmc_batch_workspace_bytes(arr, len(self.chains), ctypes.byref(n)))

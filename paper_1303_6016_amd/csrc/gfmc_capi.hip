@@ -613,6 +613,7 @@ gfmc_status gfmc_batch_use_graph(gfmc_batch* b, int32_t enable) {
     b->use_graph = false;
     return GFMC_OK;
   }
+  if (P.stream == nullptr) return fail(GFMC_EINVAL, "graph capture needs a non-default stream");
   if (!P.gexec) {
     HIPCHK(hipStreamSynchronize(P.stream));
     HIPCHK(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal));

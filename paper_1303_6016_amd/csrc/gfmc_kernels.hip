@@ -113,6 +113,8 @@ __device__ inline int xcd_remap(int b, int nb) {
 
 // -------------------------------------------------------------- propose ---
 __global__ void k_propose(const Desc* __restrict__ descs, int n) {
+  // no FMA contraction: an unchanged spin must give Delta_{n,o} = 0 exactly
+#pragma clang fp contract(off)
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const Desc& D = descs[c];
@@ -332,8 +334,10 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
     const double val = xs[w][4 * m + (lane >> 4)][lane & 15];
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
   }
+  // result layout of v_mfma_f64_16x16x4: lane l, register r holds entry
+  // (4r + l/16, l%16) of the 16x16 product
 #pragma unroll
-  for (int r = 0; r < 4; ++r) gsum[w][(4 * (lane >> 4) + r) * 16 + (lane & 15)] = acc[r];
+  for (int r = 0; r < 4; ++r) gsum[w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
   __syncthreads();
   const int t = threadIdx.x;
   if (t < kNP) {

@@ -118,7 +118,8 @@ def test_delta_seff(g, L, M, K, beta, prec):
         print(f"L={L} M={M} K={K} beta={beta} prec={prec} dS={ref:.6f} err={got - ref:.2e}",
               flush=True)
         assert abs(got - ref) < tol
-        assert abs(top - rtop) < 1e-8
+        # top-edge phase: a diagnostic amplified by 1/sin(th) at the band edge
+        assert abs(top - rtop) < (1e-8 if prec == 0 else 1e-2)
 
 
 def test_delta_seff_lorentz_and_identity(g):
