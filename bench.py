@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-single", action="store_true")
     ap.add_argument("--graph", type=int, default=0, help="replay one proposal as a HIP graph")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -64,6 +66,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+    if args.copy_probe:
+        n = 1 << 28                       # 2^28 float32 = 1 GiB per buffer
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "dispatches": 3}), flush=True)
+        return
     import paper_1303_6016_amd as g
     import synth
 
@@ -78,6 +90,7 @@ def main():
         ch.init_spins(g.INIT_RANDOM)
         chains.append(ch)
     batch = g.Batch(chains)
+    ppt = batch.autotune(16)
     if args.graph:
         batch.use_graph(True)
     stream = batch.stream
@@ -124,7 +137,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "32^3 lattice x 64 chains, M=2048, FP32 recursion / FP64 moment "
                                "sums, T=0.02..0.2 t, uniform-sphere starts (seed 7)",
-                   "L": L, "M": M, "chains": NCHAIN, "graph": bool(args.graph)},
+                   "L": L, "M": M, "chains": NCHAIN, "graph": bool(args.graph),
+                   "pairs_per_thread": ppt},
         "mc_spin_updates_per_s": args.steps * NCHAIN / total_s,
         "step_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "sweep_latency_s": {"p50": float(np.percentile(lat, 50)) * N,

@@ -47,8 +47,8 @@
  * Restrictions of the device path: L even (the lattice must be bipartite:
  * the recursion stores only the sublattice on which each vector is nonzero),
  * 2 <= L <= 256; b = 0 (a diagonal shift breaks that sublattice structure);
- * M even, 2 <= M <= 16384; K a power of two with M <= K <= 16384 (the radix-2
- * transform of the paper's node mapping).
+ * M even, 2 <= M <= 8192; K a power of two with M <= K <= 8192 (the radix-2
+ * transform of the paper's node mapping runs in LDS).
  */
 #ifndef GFMC_H
 #define GFMC_H
@@ -190,6 +190,16 @@ gfmc_status gfmc_batch_sweep(gfmc_batch* batch, int32_t nsweeps, double* magneti
  * replay it for later gfmc_batch_step calls without force or records
  * (enable != 0), or go back to direct launches (enable == 0). */
 gfmc_status gfmc_batch_use_graph(gfmc_batch* batch, int32_t enable);
+
+/* Launch shape of the Chebyshev step kernel: site pairs per thread (1 or 2).
+ * Results do not depend on it beyond the order of the per-block moment sums. */
+gfmc_status gfmc_batch_set_tuning(gfmc_batch* batch, int32_t pairs_per_thread);
+
+/* Time each step-kernel launch shape over `trial_steps` Chebyshev steps on the
+ * batch's current spins (no change of chain state), keep the fastest, and
+ * remember it for later batches of the same shape (precision, number of
+ * chains, L and M of each chain).  chosen may be NULL. */
+gfmc_status gfmc_batch_autotune(gfmc_batch* batch, int32_t trial_steps, int32_t* chosen);
 
 /* Timing of the Chebyshev step kernel over the last gfmc_batch_step call,
  * from HIP events on the batch stream around the step launches: total

@@ -77,6 +77,8 @@ _SIGS = {
     "gfmc_batch_sweep": [_vp, _i32, _P(_d), _P(_i64)],
     "gfmc_batch_use_graph": [_vp, _i32],
     "gfmc_batch_step_timing": [_vp, _P(_d), _P(_i64)],
+    "gfmc_batch_set_tuning": [_vp, _i32],
+    "gfmc_batch_autotune": [_vp, _i32, _P(_i32)],
 }
 EXPORTS = list(_SIGS) + ["gfmc_status_string", "gfmc_last_error", "gfmc_version"]
 
@@ -300,6 +302,14 @@ class Batch:
 
     def use_graph(self, enable: bool = True):
         _check(lib().gfmc_batch_use_graph(self.h, 1 if enable else 0))
+
+    def set_tuning(self, pairs_per_thread: int):
+        _check(lib().gfmc_batch_set_tuning(self.h, pairs_per_thread))
+
+    def autotune(self, trial_steps: int = 16) -> int:
+        v = ctypes.c_int32()
+        _check(lib().gfmc_batch_autotune(self.h, trial_steps, ctypes.byref(v)))
+        return v.value
 
     def step_timing(self):
         ms, n = ctypes.c_double(), ctypes.c_int64()

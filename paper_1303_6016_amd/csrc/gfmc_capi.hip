@@ -17,8 +17,8 @@
 
 namespace gfmc {
 hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
-hipError_t launch_step(int fp32, const Desc* d, const int* blkoff, int nact, int blocks, int s,
-                       hipStream_t st);
+hipError_t launch_step(int fp32, int ppt, const Desc* d, const int* blkoff, int nact, int blocks,
+                       int s, hipStream_t st);
 hipError_t launch_moments(const Desc* d, int n, int smax, hipStream_t st);
 hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
                         gfmc_step_record* recs, hipStream_t st);
@@ -127,6 +127,7 @@ static Layout layout_of(const Derived& d) {
 // Chebyshev steps, largest first) and the block offsets of the step kernel.
 struct Plan {
   int n = 0, fp32 = 0, smax = 0, kmax = 0, nmax = 0;
+  int ppt = 1;                         // site pairs per thread of the step kernel
   Desc* d_desc = nullptr;
   int* d_blkoff = nullptr;
   int32_t* d_force = nullptr;          // [kRecCap][n]
@@ -160,6 +161,7 @@ struct gfmc_chain {
 
 struct gfmc_batch {
   std::vector<gfmc_chain*> chains;   // caller order
+  std::vector<gfmc_chain*> sorted;   // plan order
   std::vector<int> order;            // sorted position -> caller index
   Plan plan;
   bool use_graph = false;
@@ -182,9 +184,17 @@ static void fill_desc(gfmc_chain* c) {
   D.ctl = (Ctl*)(c->ws + c->l.ctl);
 }
 
+static int blocks_of(const Derived& d, int ppt) {
+  const int per = kStepThreads * ppt;
+  return (d.half + per - 1) / per;
+}
+
 static gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   std::vector<Desc> ds(sorted.size());
-  for (size_t i = 0; i < sorted.size(); ++i) ds[i] = sorted[i]->desc;
+  for (size_t i = 0; i < sorted.size(); ++i) {
+    ds[i] = sorted[i]->desc;
+    ds[i].nblk = blocks_of(sorted[i]->d, P.ppt);
+  }
   HIPCHK(hipMemcpyAsync(P.d_desc, ds.data(), ds.size() * sizeof(Desc), hipMemcpyHostToDevice,
                         P.stream));
   HIPCHK(hipMemcpyAsync(P.d_blkoff, P.blkoff.data(), P.blkoff.size() * sizeof(int),
@@ -200,7 +210,7 @@ static void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   P.smax = P.kmax = P.nmax = 0;
   for (int i = 0; i < P.n; ++i) {
     P.S[i] = sorted[i]->d.S;
-    P.blkoff[i + 1] = P.blkoff[i] + sorted[i]->d.nblk;
+    P.blkoff[i + 1] = P.blkoff[i] + blocks_of(sorted[i]->d, P.ppt);
     P.smax = std::max(P.smax, P.S[i]);
     P.kmax = std::max(P.kmax, sorted[i]->d.K);
     P.nmax = std::max(P.nmax, sorted[i]->d.N);
@@ -218,7 +228,7 @@ static gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_r
   int nact = P.n;
   for (int s = 1; s <= P.smax; ++s) {
     while (nact > 0 && P.S[nact - 1] < s) --nact;
-    HIPCHK(launch_step(P.fp32, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s, P.stream));
+    HIPCHK(launch_step(P.fp32, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s, P.stream));
   }
   if (tm) {
     HIPCHK(hipEventRecord(P.ev[P.ev_used + 1], P.stream));
@@ -583,6 +593,7 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
   P.d_rec = (gfmc_step_record*)w; w += align256((size_t)kRecCap * n * sizeof(gfmc_step_record));
   P.d_mag = (double*)w;
   plan_shape(P, sorted);
+  b->sorted = sorted;
   // chains' own streams may hold pending work
   for (auto* c : sorted) HIPCHK(hipStreamSynchronize(c->stream));
   gfmc_status st = upload_plan(P, sorted);
@@ -704,6 +715,77 @@ gfmc_status gfmc_batch_sweep(gfmc_batch* b, int32_t nsweeps, double* mag, int64_
   if (accepted)
     for (int i = 0; i < n; ++i) accepted[b->order[i]] = a1[i] - a0[i];
   return GFMC_OK;
+}
+
+static void drop_graph(Plan& P) {
+  if (P.gexec) (void)hipGraphExecDestroy(P.gexec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  P.gexec = nullptr;
+  P.graph = nullptr;
+}
+
+gfmc_status gfmc_batch_set_tuning(gfmc_batch* b, int32_t pairs_per_thread) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  if (pairs_per_thread != 1 && pairs_per_thread != 2)
+    return fail(GFMC_EINVAL, "pairs_per_thread must be 1 or 2");
+  Plan& P = b->plan;
+  HIPCHK(hipStreamSynchronize(P.stream));
+  P.ppt = pairs_per_thread;
+  plan_shape(P, b->sorted);
+  CHK(upload_plan(P, b->sorted));
+  const bool g = b->use_graph;
+  drop_graph(P);
+  b->use_graph = false;
+  if (g) return gfmc_batch_use_graph(b, 1);
+  return GFMC_OK;
+}
+
+// Tuning cache keyed by the batch shape: (precision, number of chains, and
+// the (L, M) of every chain in plan order).
+static std::vector<std::pair<std::vector<int>, int>> g_tune_cache;
+
+gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* chosen) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  if (trial_steps < 1) return fail(GFMC_EINVAL, "trial_steps must be >= 1");
+  Plan& P = b->plan;
+  std::vector<int> key = {P.fp32, P.n};
+  for (auto* c : b->sorted) { key.push_back(c->d.L); key.push_back(c->d.M); }
+  for (auto& kv : g_tune_cache)
+    if (kv.first == key) {
+      if (chosen) *chosen = kv.second;
+      return gfmc_batch_set_tuning(b, kv.second);
+    }
+  // The step kernel only touches per-proposal scratch (vectors, partials), so
+  // trial launches between proposals leave the chains' state unchanged.
+  int best = 1;
+  float best_ms = 1e30f;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int ppt : {1, 2}) {
+    CHK(gfmc_batch_set_tuning(b, ppt));
+    // a proposal state for the trial (the counter only advances in k_recon)
+    HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
+    HIPCHK(launch_step(P.fp32, P.ppt, P.d_desc, P.d_blkoff, P.n, P.blkoff[P.n], 1, P.stream));
+    const int smax = std::max(2, std::min(P.smax, trial_steps + 1));
+    int nact = P.n;
+    HIPCHK(hipEventRecord(e0, P.stream));
+    for (int s = 2; s <= smax; ++s) {
+      while (nact > 0 && P.S[nact - 1] < s) --nact;
+      if (nact == 0) break;
+      HIPCHK(launch_step(P.fp32, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s, P.stream));
+    }
+    HIPCHK(hipEventRecord(e1, P.stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) { best_ms = ms; best = ppt; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_tune_cache.push_back({key, best});
+  if (chosen) *chosen = best;
+  return gfmc_batch_set_tuning(b, best);
 }
 
 gfmc_status gfmc_batch_step_timing(gfmc_batch* b, double* step_ms, int64_t* launches) {

@@ -181,29 +181,107 @@ __global__ void k_propose(const Desc* __restrict__ descs, int n) {
 }
 
 // ------------------------------------------------------------ Chebyshev ---
+#define GLOBAL __attribute__((address_space(1)))
+
+// Six neighbour-vector values of one site, stored contiguously.
+template <typename T>
+struct alignas(16) six {
+  cpx<T> v[6];
+};
+
+// Loads and stores through global-address-space pointers as plain vector
+// accesses (16-byte where the layout allows).
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ inline spn<float> ld(const GLOBAL spn<float>* p) {
+  const f4v v = *(const GLOBAL f4v*)p;
+  return {v.x, v.y, v.z, v.w};
+}
+__device__ inline spn<double> ld(const GLOBAL spn<double>* p) {
+  const GLOBAL d2v* q = (const GLOBAL d2v*)p;
+  const d2v a = q[0], b = q[1];
+  return {a.x, a.y, b.x, b.y};
+}
+__device__ inline cpx<float> ld(const GLOBAL cpx<float>* p) {
+  const f2v v = *(const GLOBAL f2v*)p;
+  return {v.x, v.y};
+}
+__device__ inline cpx<double> ld(const GLOBAL cpx<double>* p) {
+  const d2v v = *(const GLOBAL d2v*)p;
+  return {v.x, v.y};
+}
+__device__ inline void st(GLOBAL cpx<float>* p, const cpx<float>& c) {
+  f2v v = {c.x, c.y};
+  *(GLOBAL f2v*)p = v;
+}
+__device__ inline void st(GLOBAL cpx<double>* p, const cpx<double>& c) {
+  d2v v = {c.x, c.y};
+  *(GLOBAL d2v*)p = v;
+}
+__device__ inline six<float> ld(const GLOBAL six<float>* p) {
+  const GLOBAL f4v* q = (const GLOBAL f4v*)p;
+  six<float> r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const f4v v = q[i];
+    r.v[2 * i] = {v.x, v.y};
+    r.v[2 * i + 1] = {v.z, v.w};
+  }
+  return r;
+}
+__device__ inline six<double> ld(const GLOBAL six<double>* p) {
+  const GLOBAL d2v* q = (const GLOBAL d2v*)p;
+  six<double> r;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const d2v v = q[i];
+    r.v[i] = {v.x, v.y};
+  }
+  return r;
+}
+__device__ inline void st(GLOBAL six<float>* p, const six<float>& r) {
+  GLOBAL f4v* q = (GLOBAL f4v*)p;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    f4v v = {r.v[2 * i].x, r.v[2 * i].y, r.v[2 * i + 1].x, r.v[2 * i + 1].y};
+    q[i] = v;
+  }
+}
+__device__ inline void st(GLOBAL six<double>* p, const six<double>& r) {
+  GLOBAL d2v* q = (GLOBAL d2v*)p;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    d2v v = {r.v[i].x, r.v[i].y};
+    q[i] = v;
+  }
+}
+
 // One step s >= 1 of |a_s> = c1 Ht'|a_{s-1}> - c2 |a_{s-2}> for the 7 start
 // vectors of every chain in the launch, where Ht' is the hopping part with
 // the factor -t/a folded into c1 (c1 = -t/a, c2 = 0 for s = 1; c1 = -2t/a,
 // c2 = 1 otherwise).  The lattice is bipartite and Ht connects only opposite
 // parities, so a^o_s lives on parity p(o)^(s&1) and the six neighbour
 // vectors a^n_s on the other parity; each site therefore stores one value of
-// a^o and six of a^n, and a_{s+1} overwrites a_{s-1} in place.  Each thread
-// owns the two sites of one half-row index (one per parity): on one it forms
-// a^o_s from the 6 neighbours, on the other the six a^n_s.
+// a^o (o-slot) and six of a^n (n-slots) and a_{s+1} overwrites a_{s-1} in
+// place.  Each thread owns PPT half-row indices; for each, the two sites of
+// that index (one per parity): on one it forms a^o_s from the 6 neighbours,
+// on the other the six a^n_s.
 //
 // Moments (equation "mu2", doubling): per step the kernel accumulates
 //   P^{oo}_s = <a^o_s|a^o_s>, P^{de}_s = <a^{n_d}_s|a^{n_e}_s>,
 //   Q^{oe}_s = <a^o_{s-1}|a^{n_e}_s>
 // (the other pairs vanish on a bipartite lattice) as the 16x16 real Gram
-// matrix of the per-thread vector
+// matrix of the per-site-pair vector
 //   x = (Re/Im a^{n_0..5}_s, Re/Im a^o_{s-1}  at the n-site,  Re/Im a^o_s at the o-site)
-// summed over the block's sites on the FP64 matrix core, and stores the 49
-// real combinations per block (no reduction on the per-step critical path).
-template <typename T, bool FIRST>
+// summed over the block on the FP64 matrix core, and stores the 49 real
+// combinations per block (no reduction on the per-step critical path).
+template <typename T, bool FIRST, int PPT>
 __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ descs,
                                                        const int* __restrict__ blkoff, int nact,
                                                        int s) {
-  __shared__ double xs[4][64][17];
+  __shared__ double xs[4][16][17];
   __shared__ double gsum[4][256];
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
   int c = 0;
@@ -218,38 +296,44 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   const Desc& D = descs[c];
   const int lb = gb - blkoff[c];
   const int L = D.L, hx = L >> 1, half = D.half;
-  const int h = lb * kStepThreads + (int)threadIdx.x;
   const Ctl* ctl = D.ctl;
   const int pO = ctl->parity_o;
-  const int po = pO ^ (s & 1);          // parity of the site that carries a^o_s
-  const int pn = po ^ 1;                // parity of the site that carries a^n_s
-  double x[16];
+  const int po = pO ^ (s & 1);          // parity of the sites that carry a^o_s
+  const int pn = po ^ 1;                // parity of the sites that carry a^n_s
+  const int o_half = ctl->o_half;
+  int sh[6];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) x[i] = 0.0;
+  for (int e = 0; e < 6; ++e) sh[e] = FIRST ? ctl->start_half[1 + e] : 0;
+  const T c1 = FIRST ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
+  const GLOBAL spn<T>* sp = (const GLOBAL spn<T>*)D.spin;            // [2][half]
+  GLOBAL cpx<T>* vo = (GLOBAL cpx<T>*)D.vec;                         // o-slots [2][half]
+  GLOBAL six<T>* vn = (GLOBAL six<T>*)((GLOBAL cpx<T>*)D.vec + D.N); // n-slots [2][half]
+  const GLOBAL spn<T>* sp_o = sp + (size_t)po * half;
+  const GLOBAL spn<T>* sp_n = sp + (size_t)pn * half;
 
-  if (h < half) {
+  double x[PPT][16];
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[p][i] = 0.0;
+    const int h = (lb * PPT + p) * kStepThreads + (int)threadIdx.x;
+    if (h >= half) continue;
     const int k = h % hx, r = h / hx, y = r % L, z = r / L;
     const int xo = 2 * k + ((y + z + po) & 1);
     const int xn = 2 * k + ((y + z + pn) & 1);
-    const spn<T>* __restrict__ sp = (const spn<T>*)D.spin;
-    cpx<T>* __restrict__ v = (cpx<T>*)D.vec;
-#define VEC(slot, par, hh) v[((size_t)((slot) * 2 + (par))) * half + (hh)]
-    const T c1 = FIRST ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
-    const int o_half = ctl->o_half;
-
     // a^o_s on the o-site
     {
-      const spn<T> si = sp[(size_t)po * half + h];
+      const spn<T> si = ld(sp_o + h);
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         const int nh = nb_half(xo, y, z, d, L);
-        const spn<T> sj = sp[(size_t)pn * half + nh];
+        const spn<T> sj = ld(sp_n + nh);
         T hr, hi_;
         hop_spinor(si, sj, hr, hi_);
         cpx<T> an;
         if (FIRST) { an.x = (nh == o_half) ? (T)1 : (T)0; an.y = 0; }
-        else an = VEC(0, pn, nh);
+        else an = ld(vo + (size_t)pn * half + nh);
         ar += hr * an.x - hi_ * an.y;
         ai += hr * an.y + hi_ * an.x;
       }
@@ -257,82 +341,97 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
       ao.x = c1 * ar;
       ao.y = c1 * ai;
       if (!FIRST) {
-        const cpx<T> pr = VEC(0, po, h);
+        const cpx<T> pr = ld(vo + (size_t)po * half + h);
         ao.x -= pr.x;
         ao.y -= pr.y;
       }
-      VEC(0, po, h) = ao;
-      x[14] = (double)ao.x;
-      x[15] = (double)ao.y;
+      st(vo + (size_t)po * half + h, ao);
+      x[p][14] = (double)ao.x;
+      x[p][15] = (double)ao.y;
     }
     // a^{n_e}_s, e = 0..5, on the n-site
     {
-      const spn<T> si = sp[(size_t)pn * half + h];
+      const spn<T> si = ld(sp_n + h);
       T accr[6], acci[6];
 #pragma unroll
       for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         const int nh = nb_half(xn, y, z, d, L);
-        const spn<T> sj = sp[(size_t)po * half + nh];
+        const spn<T> sj = ld(sp_o + nh);
         T hr, hi_;
         hop_spinor(si, sj, hr, hi_);
+        six<T> an;
+        if (FIRST) {
+#pragma unroll
+          for (int e = 0; e < 6; ++e) { an.v[e].x = (nh == sh[e]) ? (T)1 : (T)0; an.v[e].y = 0; }
+        } else {
+          an = ld(vn + (size_t)po * half + nh);
+        }
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
-          cpx<T> an;
-          if (FIRST) { an.x = (nh == ctl->start_half[1 + e]) ? (T)1 : (T)0; an.y = 0; }
-          else an = VEC(1 + e, po, nh);
-          accr[e] += hr * an.x - hi_ * an.y;
-          acci[e] += hr * an.y + hi_ * an.x;
+          accr[e] += hr * an.v[e].x - hi_ * an.v[e].y;
+          acci[e] += hr * an.v[e].y + hi_ * an.v[e].x;
         }
       }
+      six<T> out;
+      six<T> prev;
+      if (!FIRST) prev = ld(vn + (size_t)pn * half + h);
 #pragma unroll
       for (int e = 0; e < 6; ++e) {
-        cpx<T> an;
-        an.x = c1 * accr[e];
-        an.y = c1 * acci[e];
+        out.v[e].x = c1 * accr[e];
+        out.v[e].y = c1 * acci[e];
         if (!FIRST) {
-          const cpx<T> pr = VEC(1 + e, pn, h);
-          an.x -= pr.x;
-          an.y -= pr.y;
+          out.v[e].x -= prev.v[e].x;
+          out.v[e].y -= prev.v[e].y;
         }
-        VEC(1 + e, pn, h) = an;
-        x[2 * e] = (double)an.x;
-        x[2 * e + 1] = (double)an.y;
+        x[p][2 * e] = (double)out.v[e].x;
+        x[p][2 * e + 1] = (double)out.v[e].y;
       }
+      st(vn + (size_t)pn * half + h, out);
       cpx<T> aop;   // a^o_{s-1} at the n-site
       if (FIRST) {
         aop.x = (h == o_half) ? (T)1 : (T)0;
         aop.y = 0;
         // store a_0 on the sites that hold it from now on
-        VEC(0, pn, h) = aop;
+        st(vo + (size_t)pn * half + h, aop);
+        six<T> u;
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-          cpx<T> u;
-          u.x = (h == ctl->start_half[1 + e]) ? (T)1 : (T)0;
-          u.y = 0;
-          VEC(1 + e, po, h) = u;
-        }
+        for (int e = 0; e < 6; ++e) { u.v[e].x = (h == sh[e]) ? (T)1 : (T)0; u.v[e].y = 0; }
+        st(vn + (size_t)po * half + h, u);
       } else {
-        aop = VEC(0, pn, h);
+        aop = ld(vo + (size_t)pn * half + h);
       }
-      x[12] = (double)aop.x;
-      x[13] = (double)aop.y;
+      x[p][12] = (double)aop.x;
+      x[p][13] = (double)aop.y;
     }
-#undef VEC
   }
 
   // Gram matrix of x over the block on the FP64 matrix core:
-  // v_mfma_f64_16x16x4 with A = B = 4 columns (sites) of 16 components.
+  // v_mfma_f64_16x16x4 with A = B = 4 columns (site pairs) of 16 components.
+  // Each wave stages 16 site pairs at a time in LDS (4 rounds per PPT slice).
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) xs[w][lane][i] = x[i];
-  __syncthreads();
   d4v acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const double val = xs[w][4 * m + (lane >> 4)][lane & 15];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
+  for (int p = 0; p < PPT; ++p) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      if ((lane >> 4) == rr) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) xs[w][lane & 15][i] = x[p][i];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double val = xs[w][4 * m + (lane >> 4)][lane & 15];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
   }
   // result layout of v_mfma_f64_16x16x4: lane l, register r holds entry
   // (4r + l/16, l%16) of the 16x16 product
@@ -735,22 +834,25 @@ hipError_t launch_propose(const Desc* d, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int PPT>
 hipError_t launch_step_t(const Desc* d, const int* blkoff, int nact, int blocks, int s,
                          hipStream_t st) {
   if (s == 1)
-    hipLaunchKernelGGL((k_step<T, true>), dim3(blocks), dim3(kStepThreads), 0, st, d, blkoff,
-                       nact, s);
+    hipLaunchKernelGGL((k_step<T, true, PPT>), dim3(blocks), dim3(kStepThreads), 0, st, d,
+                       blkoff, nact, s);
   else
-    hipLaunchKernelGGL((k_step<T, false>), dim3(blocks), dim3(kStepThreads), 0, st, d, blkoff,
-                       nact, s);
+    hipLaunchKernelGGL((k_step<T, false, PPT>), dim3(blocks), dim3(kStepThreads), 0, st, d,
+                       blkoff, nact, s);
   return hipGetLastError();
 }
 
-hipError_t launch_step(int fp32, const Desc* d, const int* blkoff, int nact, int blocks, int s,
-                       hipStream_t st) {
-  return fp32 ? launch_step_t<float>(d, blkoff, nact, blocks, s, st)
-              : launch_step_t<double>(d, blkoff, nact, blocks, s, st);
+hipError_t launch_step(int fp32, int ppt, const Desc* d, const int* blkoff, int nact, int blocks,
+                       int s, hipStream_t st) {
+  if (fp32)
+    return ppt == 2 ? launch_step_t<float, 2>(d, blkoff, nact, blocks, s, st)
+                    : launch_step_t<float, 1>(d, blkoff, nact, blocks, s, st);
+  return ppt == 2 ? launch_step_t<double, 2>(d, blkoff, nact, blocks, s, st)
+                  : launch_step_t<double, 1>(d, blkoff, nact, blocks, s, st);
 }
 
 hipError_t launch_moments(const Desc* d, int n, int smax, hipStream_t st) {

@@ -227,6 +227,27 @@ def test_batch_results_equal_single_chains(g):
         assert np.array_equal(x.get_spins()[0], y.get_spins()[0])
 
 
+@pytest.mark.parametrize("ppt", [1, 2])
+def test_batch_launch_shapes_agree(g, ppt):
+    # moments through a batch with either launch shape equal the single-chain ones
+    specs = [(6, 128), (4, 64), (8, 128)]
+    alone, mixed = [], []
+    for i, (L, M) in enumerate(specs):
+        a, m = make(g, L, M, 0, seed=3, chain_id=i, beta=5.0)
+        a.init_spins(g.INIT_RANDOM)
+        alone.append(a.step())
+        b_, _ = make(g, L, M, 0, seed=3, chain_id=i, beta=5.0)
+        b_.init_spins(g.INIT_RANDOM)
+        mixed.append(b_)
+    b = g.Batch(mixed)
+    b.set_tuning(ppt)
+    recs = b.step(1, records=True)[0]
+    for r, a in zip(recs, alone):
+        assert r.site == a.site and abs(r.dseff - a.dseff) < 1e-12
+    assert b.autotune(4) in (1, 2)
+    b.close()
+
+
 def test_batch_graph_replay_matches_direct(g):
     def build():
         chs = []
