@@ -210,6 +210,55 @@ gfmc_status gfmc_batch_step_timing(gfmc_batch* batch, double* step_ms, int64_t* 
  * (vectors read and written, spinors read; per step and summed over steps). */
 gfmc_status gfmc_chain_step_bytes(gfmc_chain* chain, double* bytes_per_step, int32_t* steps);
 
+/* ----------------------------------------------------------------- serving --
+ * An engine runs independent chain requests on one device with continuous
+ * batching: a host worker thread admits queued requests whenever a slot and
+ * enough of the HBM budget are free, and every iteration advances all
+ * admitted chains by one proposal in one batched launch sequence, so chains
+ * of different L, M and temperature share the device and requests that
+ * arrive while others run join at the next iteration.  Each request runs
+ * `nsweeps` sweeps (N proposals each, Algorithm 1) from its own Philox key
+ * and start configuration; per-chain results do not depend on which other
+ * chains share the device.  The engine owns one device allocation of
+ * `hbm_budget_bytes` (chain workspaces are carved from it) and one stream. */
+typedef struct gfmc_engine gfmc_engine;   /* opaque */
+
+typedef struct {
+  uint64_t request_id;
+  gfmc_status status;       /* GFMC_OK, GFMC_ECANCELED, or the error that stopped it  */
+  int32_t L, M;
+  int32_t sweeps;           /* completed sweeps                                       */
+  int32_t pad_;
+  int64_t proposals, accepted;
+  double magnetization;     /* |m| after the last completed sweep                     */
+  double magnetization_mean;/* mean of |m| over completed sweeps                      */
+  double t_submit, t_admit, t_first_sweep, t_done;   /* seconds since engine creation */
+} gfmc_result;
+
+gfmc_status gfmc_engine_create(int device, size_t hbm_budget_bytes, int32_t max_slots,
+                               gfmc_engine** out);
+/* Queue a request.  EBUSY if its workspace alone exceeds the engine's budget
+ * (it could never be admitted); EINVAL for invalid parameters or nsweeps < 1. */
+gfmc_status gfmc_engine_submit(gfmc_engine* engine, const gfmc_chain_params* params,
+                               gfmc_init init, double random_fraction, int32_t nsweeps,
+                               uint64_t* request_id);
+/* Move up to `cap` finished results into `out`; *n receives how many. */
+gfmc_status gfmc_engine_poll(gfmc_engine* engine, gfmc_result* out, int32_t cap, int32_t* n);
+/* Cancel a queued or running request (its result reports GFMC_ECANCELED);
+ * EINVAL if the id is unknown or already finished. */
+gfmc_status gfmc_engine_cancel(gfmc_engine* engine, uint64_t request_id);
+/* Drain the recorded wall-clock durations (seconds) of completed sweeps, in
+ * completion order, and the matching request ids (ids may be NULL). */
+gfmc_status gfmc_engine_sweep_latencies(gfmc_engine* engine, double* seconds, uint64_t* ids,
+                                        int32_t cap, int32_t* n);
+/* Counts: queued, running, finished-but-unpolled requests; bytes in use. */
+gfmc_status gfmc_engine_status(gfmc_engine* engine, int32_t* queued, int32_t* running,
+                               int32_t* finished, size_t* bytes_in_use);
+/* Block until no request is queued or running (or timeout_s elapses: EBUSY). */
+gfmc_status gfmc_engine_drain(gfmc_engine* engine, double timeout_s);
+/* Stop the worker (running requests are cancelled) and free the device memory. */
+gfmc_status gfmc_engine_destroy(gfmc_engine* engine);
+
 /* ------------------------------------------------------------------ misc -- */
 const char* gfmc_status_string(gfmc_status status);
 const char* gfmc_last_error(void);

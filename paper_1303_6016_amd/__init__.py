@@ -42,6 +42,17 @@ class ChainParams(ctypes.Structure):
     ]
 
 
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("request_id", ctypes.c_uint64), ("status", ctypes.c_int32), ("L", ctypes.c_int32),
+        ("M", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("proposals", ctypes.c_int64), ("accepted", ctypes.c_int64),
+        ("magnetization", ctypes.c_double), ("magnetization_mean", ctypes.c_double),
+        ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+        ("t_first_sweep", ctypes.c_double), ("t_done", ctypes.c_double),
+    ]
+
+
 class StepRecord(ctypes.Structure):
     _fields_ = [
         ("index", ctypes.c_int64), ("site", ctypes.c_int32), ("own", ctypes.c_int32),
@@ -79,6 +90,14 @@ _SIGS = {
     "gfmc_batch_step_timing": [_vp, _P(_d), _P(_i64)],
     "gfmc_batch_set_tuning": [_vp, _i32],
     "gfmc_batch_autotune": [_vp, _i32, _P(_i32)],
+    "gfmc_engine_create": [ctypes.c_int, _sz, _i32, _P(_vp)],
+    "gfmc_engine_submit": [_vp, _P(ChainParams), _i32, _d, _i32, _P(ctypes.c_uint64)],
+    "gfmc_engine_poll": [_vp, _vp, _i32, _P(_i32)],
+    "gfmc_engine_cancel": [_vp, ctypes.c_uint64],
+    "gfmc_engine_sweep_latencies": [_vp, _P(_d), _P(ctypes.c_uint64), _i32, _P(_i32)],
+    "gfmc_engine_status": [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_sz)],
+    "gfmc_engine_drain": [_vp, _d],
+    "gfmc_engine_destroy": [_vp],
 }
 EXPORTS = list(_SIGS) + ["gfmc_status_string", "gfmc_last_error", "gfmc_version"]
 
@@ -315,3 +334,57 @@ class Batch:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(lib().gfmc_batch_step_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Engine:
+    """Serving engine: continuous batching of chain requests on one device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 1 << 30, max_slots: int = 64):
+        h = ctypes.c_void_p()
+        _check(lib().gfmc_engine_create(device, hbm_budget_bytes, max_slots, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().gfmc_engine_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, p: Params, init: int = INIT_RANDOM, frac: float = 0.0, nsweeps: int = 1) -> int:
+        rid = ctypes.c_uint64()
+        cp = p.c()
+        _check(lib().gfmc_engine_submit(self.h, ctypes.byref(cp), init, frac, nsweeps,
+                                        ctypes.byref(rid)))
+        return rid.value
+
+    def poll(self, cap: int = 256):
+        out = (Result * cap)()
+        n = ctypes.c_int32()
+        _check(lib().gfmc_engine_poll(self.h, out, cap, ctypes.byref(n)))
+        return [out[i] for i in range(n.value)]
+
+    def cancel(self, request_id: int):
+        _check(lib().gfmc_engine_cancel(self.h, request_id))
+
+    def sweep_latencies(self, cap: int = 1 << 16):
+        sec = np.zeros(cap)
+        ids = np.zeros(cap, dtype=np.uint64)
+        n = ctypes.c_int32()
+        _check(lib().gfmc_engine_sweep_latencies(
+            self.h, _dptr(sec), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), cap,
+            ctypes.byref(n)))
+        return sec[:n.value], ids[:n.value]
+
+    def status(self):
+        q, r, f, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check(lib().gfmc_engine_status(self.h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f),
+                                        ctypes.byref(b)))
+        return {"queued": q.value, "running": r.value, "finished": f.value, "bytes": b.value}
+
+    def drain(self, timeout_s: float = 600.0):
+        _check(lib().gfmc_engine_drain(self.h, timeout_s))

@@ -13,53 +13,18 @@
 #include <string>
 #include <vector>
 
-#include "gfmc_device.h"
+#include "gfmc_host.h"
 
-namespace gfmc {
-hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
-hipError_t launch_step(int fp32, int ppt, const Desc* d, const int* blkoff, int nact, int blocks,
-                       int s, hipStream_t st);
-hipError_t launch_moments(const Desc* d, int n, int smax, hipStream_t st);
-hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
-                        gfmc_step_record* recs, hipStream_t st);
-hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t st);
-hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st);
-hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st);
-hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t st);
-}  // namespace gfmc
-
-using namespace gfmc;
-
-// ------------------------------------------------------------- errors ----
 static thread_local std::string g_err;
 
-static gfmc_status fail(gfmc_status s, const std::string& msg) {
+gfmc_status gfmc_fail(gfmc_status s, const std::string& msg) {
   g_err = msg;
   return s;
 }
 
-#define HIPCHK(expr)                                                                      \
-  do {                                                                                    \
-    hipError_t e_ = (expr);                                                               \
-    if (e_ != hipSuccess)                                                                 \
-      return fail(GFMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
-  } while (0)
+static gfmc_status fail(gfmc_status s, const std::string& msg) { return gfmc_fail(s, msg); }
 
-#define CHK(expr)                          \
-  do {                                     \
-    gfmc_status s_ = (expr);               \
-    if (s_ != GFMC_OK) return s_;          \
-  } while (0)
-
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// ------------------------------------------------------- chain layout ----
-struct Derived {
-  int L, N, half, M, S, K, log2K, nblk, fp32;
-  double a, lambda;
-};
-
-static gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
+gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   if (!p) return fail(GFMC_EINVAL, "params is NULL");
   if (p->L < 2 || p->L > 256 || (p->L & 1))
     return fail(GFMC_EINVAL, "L must be even and in [2, 256] (bipartite lattice)");
@@ -97,11 +62,7 @@ static gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   return GFMC_OK;
 }
 
-struct Layout {
-  size_t desc, blkoff, force, rec, mag, ctl, theta, phi, spin, vec, part, mom, gscr, total;
-};
-
-static Layout layout_of(const Derived& d) {
+Layout layout_of(const Derived& d) {
   const size_t tsz = d.fp32 ? 4 : 8;
   Layout l;
   size_t o = 0;
@@ -123,51 +84,7 @@ static Layout layout_of(const Derived& d) {
   return l;
 }
 
-// A launch plan: a device table of chain descriptors (sorted by number of
-// Chebyshev steps, largest first) and the block offsets of the step kernel.
-struct Plan {
-  int n = 0, fp32 = 0, smax = 0, kmax = 0, nmax = 0;
-  int ppt = 1;                         // site pairs per thread of the step kernel
-  Desc* d_desc = nullptr;
-  int* d_blkoff = nullptr;
-  int32_t* d_force = nullptr;          // [kRecCap][n]
-  gfmc_step_record* d_rec = nullptr;   // [kRecCap][n]
-  double* d_mag = nullptr;             // [kMagCap][n]
-  std::vector<int> S, blkoff;          // per sorted chain; blkoff has n+1 entries
-  hipStream_t stream = nullptr;
-  // timing of the step launches
-  std::vector<hipEvent_t> ev;
-  int ev_used = 0;
-  double step_ms = 0;
-  int64_t step_launches = 0;
-  bool timing = false;
-  // graph replay of one proposal
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-};
-
-struct gfmc_chain {
-  gfmc_chain_params p;
-  Derived d;
-  Layout l;
-  char* ws = nullptr;
-  size_t bytes = 0;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  Desc desc;
-  Plan plan;            // single-chain plan living in the chain's workspace
-  bool in_batch = false;
-};
-
-struct gfmc_batch {
-  std::vector<gfmc_chain*> chains;   // caller order
-  std::vector<gfmc_chain*> sorted;   // plan order
-  std::vector<int> order;            // sorted position -> caller index
-  Plan plan;
-  bool use_graph = false;
-};
-
-static void fill_desc(gfmc_chain* c) {
+void fill_desc(gfmc_chain* c) {
   Desc& D = c->desc;
   memset(&D, 0, sizeof(D));
   D.L = c->d.L; D.N = c->d.N; D.half = c->d.half; D.M = c->d.M; D.S = c->d.S; D.K = c->d.K;
@@ -189,7 +106,7 @@ static int blocks_of(const Derived& d, int ppt) {
   return (d.half + per - 1) / per;
 }
 
-static gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
+gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   std::vector<Desc> ds(sorted.size());
   for (size_t i = 0; i < sorted.size(); ++i) {
     ds[i] = sorted[i]->desc;
@@ -203,7 +120,7 @@ static gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) 
   return GFMC_OK;
 }
 
-static void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
+void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   P.n = (int)sorted.size();
   P.S.resize(P.n);
   P.blkoff.assign(P.n + 1, 0);
@@ -220,7 +137,7 @@ static void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
 // ------------------------------------------------- one proposal (launches) --
 // Enqueues: propose, S steps (each over the chains that still need it),
 // moment assembly, reconstruction (+ Metropolis when mode 0), spinor update.
-static gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* d_rec,
+gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* d_rec,
                                     bool with_recon) {
   HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
   const bool tm = P.timing && P.ev_used + 2 <= (int)P.ev.size();
@@ -289,6 +206,54 @@ static gfmc_status check_chain(gfmc_chain* c) {
   return GFMC_OK;
 }
 
+// Workspace carve-up, descriptor, single-chain plan and a ferromagnetic start.
+gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived& d, void* ws,
+                        size_t bytes, hipStream_t stream) {
+  if (!ws) return fail(GFMC_EINVAL, "workspace is NULL");
+  if ((uintptr_t)ws & 255) return fail(GFMC_EINVAL, "workspace must be 256-byte aligned");
+  const Layout l = layout_of(d);
+  if (bytes < l.total) return fail(GFMC_ENOMEM, "workspace smaller than gfmc_workspace_bytes");
+  c->p = *p;
+  c->d = d;
+  c->l = l;
+  c->ws = (char*)ws;
+  c->bytes = bytes;
+  c->stream = stream;
+  HIPCHK(hipGetDevice(&c->device));
+  fill_desc(c);
+  Plan& P = c->plan;
+  P.stream = c->stream;
+  P.fp32 = d.fp32;
+  P.d_desc = (Desc*)(c->ws + l.desc);
+  P.d_blkoff = (int*)(c->ws + l.blkoff);
+  P.d_force = (int32_t*)(c->ws + l.force);
+  P.d_rec = (gfmc_step_record*)(c->ws + l.rec);
+  P.d_mag = (double*)(c->ws + l.mag);
+  plan_shape(P, {c});
+  CHK(upload_plan(P, {c}));
+  Ctl h;
+  memset(&h, 0, sizeof(h));
+  HIPCHK(hipMemcpyAsync(c->desc.ctl, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemsetAsync(c->desc.theta, 0, (size_t)d.N * 8, c->stream));
+  HIPCHK(hipMemsetAsync(c->desc.phi, 0, (size_t)d.N * 8, c->stream));
+  HIPCHK(launch_spinors(d.fp32, P.d_desc, 1, d.N, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return GFMC_OK;
+}
+
+gfmc_status chain_init_spins(gfmc_chain* c, int mode, double frac) {
+  Plan& P = c->plan;
+  HIPCHK(launch_init_spins(P.d_desc, c->d.N, mode == GFMC_INIT_RANDOM ? 0 : 1, c->stream));
+  if (mode == GFMC_INIT_FM_PLUS_RANDOM) {
+    int64_t nr = (int64_t)std::floor(frac * (double)c->d.N);
+    nr = std::min<int64_t>(std::max<int64_t>(nr, 0), c->d.N);
+    // the vector buffer (7N complex) is free scratch between proposals
+    HIPCHK(launch_fisher_yates(P.d_desc, nr, (int32_t*)c->desc.vec, c->stream));
+  }
+  HIPCHK(launch_spinors(c->d.fp32, P.d_desc, 1, c->d.N, c->stream));
+  return GFMC_OK;
+}
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -321,43 +286,9 @@ gfmc_status gfmc_chain_create(const gfmc_chain_params* p, void* ws, size_t bytes
   Derived d;
   CHK(derive(p, d));
   if (!out) return fail(GFMC_EINVAL, "out is NULL");
-  if (!ws) return fail(GFMC_EINVAL, "workspace is NULL");
-  if ((uintptr_t)ws & 255) return fail(GFMC_EINVAL, "workspace must be 256-byte aligned");
-  const Layout l = layout_of(d);
-  if (bytes < l.total) return fail(GFMC_ENOMEM, "workspace smaller than gfmc_workspace_bytes");
   gfmc_chain* c = new (std::nothrow) gfmc_chain();
   if (!c) return fail(GFMC_ENOMEM, "host allocation failed");
-  c->p = *p;
-  c->d = d;
-  c->l = l;
-  c->ws = (char*)ws;
-  c->bytes = bytes;
-  c->stream = (hipStream_t)stream;
-  if (hipGetDevice(&c->device) != hipSuccess) {
-    delete c;
-    return fail(GFMC_EDEVICE, "hipGetDevice failed");
-  }
-  fill_desc(c);
-  Plan& P = c->plan;
-  P.stream = c->stream;
-  P.fp32 = d.fp32;
-  P.d_desc = (Desc*)(c->ws + l.desc);
-  P.d_blkoff = (int*)(c->ws + l.blkoff);
-  P.d_force = (int32_t*)(c->ws + l.force);
-  P.d_rec = (gfmc_step_record*)(c->ws + l.rec);
-  P.d_mag = (double*)(c->ws + l.mag);
-  plan_shape(P, {c});
-  gfmc_status st = upload_plan(P, {c});
-  if (st == GFMC_OK) {
-    Ctl h;
-    memset(&h, 0, sizeof(h));
-    if (hipMemcpyAsync(c->desc.ctl, &h, sizeof(h), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->desc.theta, 0, (size_t)d.N * 8, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->desc.phi, 0, (size_t)d.N * 8, c->stream) != hipSuccess ||
-        launch_spinors(d.fp32, P.d_desc, 1, d.N, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess)
-      st = fail(GFMC_EDEVICE, "chain initialisation failed");
-  }
+  gfmc_status st = chain_setup(c, p, d, ws, bytes, (hipStream_t)stream);
   if (st != GFMC_OK) {
     delete c;
     return st;
@@ -396,15 +327,7 @@ gfmc_status gfmc_init_spins(gfmc_chain* c, gfmc_init mode, double frac) {
     return fail(GFMC_EINVAL, "unknown init mode");
   if (mode == GFMC_INIT_FM_PLUS_RANDOM && !(frac >= 0 && frac <= 1))
     return fail(GFMC_EINVAL, "random_fraction must be in [0, 1]");
-  Plan& P = c->plan;
-  HIPCHK(launch_init_spins(P.d_desc, c->d.N, mode == GFMC_INIT_RANDOM ? 0 : 1, c->stream));
-  if (mode == GFMC_INIT_FM_PLUS_RANDOM) {
-    int64_t nr = (int64_t)std::floor(frac * (double)c->d.N);
-    nr = std::min<int64_t>(std::max<int64_t>(nr, 0), c->d.N);
-    // the vector buffer (7N complex) is free scratch between proposals
-    HIPCHK(launch_fisher_yates(P.d_desc, nr, (int32_t*)c->desc.vec, c->stream));
-  }
-  HIPCHK(launch_spinors(c->d.fp32, P.d_desc, 1, c->d.N, c->stream));
+  CHK(chain_init_spins(c, mode, frac));
   HIPCHK(hipStreamSynchronize(c->stream));
   return GFMC_OK;
 }

@@ -1,0 +1,447 @@
+// gfmc_engine.hip -- serving engine of the C ABI (include/gfmc.h, "serving"):
+// continuous batching of independent chain requests on one device.
+//
+// A host worker thread owns the device stream.  Each iteration it (1) admits
+// queued requests in arrival order while a slot and a large enough block of
+// the HBM budget are free, (2) retires cancelled requests, (3) rebuilds the
+// launch plan when the set of running chains changed, (4) advances every
+// running chain by one proposal with one batched launch sequence (one launch
+// per Chebyshev step over all chains that still need that step), and (5) at
+// each chain's sweep boundary measures |m| and records the sweep's wall time.
+// Per-chain arithmetic does not depend on which chains share the plan.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "gfmc_host.h"
+
+namespace {
+
+// First-fit allocator over the engine's device allocation, 256-byte blocks.
+struct Arena {
+  size_t size = 0, used = 0;
+  std::map<size_t, size_t> free_;   // offset -> length
+  void init(size_t n) {
+    size = n;
+    used = 0;
+    free_.clear();
+    free_[0] = n;
+  }
+  bool alloc(size_t n, size_t& off) {
+    n = align256(n);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        off = it->first;
+        const size_t rest = it->second - n;
+        free_.erase(it);
+        if (rest) free_[off + n] = rest;
+        used += n;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = align256(n);
+    used -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+struct Request {
+  uint64_t id = 0;
+  gfmc_chain_params p;
+  Derived d;
+  int init = 0;
+  double frac = 0;
+  int nsweeps = 1;
+  double t_submit = 0, t_admit = -1, t_first_sweep = -1, t_sweep_start = 0;
+  bool cancel = false;
+  gfmc_chain* chain = nullptr;
+  size_t off = 0, bytes = 0;
+  int64_t done_props = 0;
+  int sweeps = 0;
+  double mag_last = 0, mag_sum = 0;
+};
+
+}  // namespace
+
+struct gfmc_engine {
+  int device = 0;
+  size_t budget = 0;
+  int max_slots = 0;
+  char* base = nullptr;
+  char* plan_mem = nullptr;
+  hipStream_t stream = nullptr;
+  Arena arena;
+  Plan plan;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request*> queue;
+  std::vector<Request*> running;
+  std::vector<gfmc_result> done;
+  std::vector<std::pair<double, uint64_t>> lat;
+  std::thread worker;
+  bool stop = false;
+  bool busy = false;          // worker is between admission and retirement
+  uint64_t next_id = 1;
+  std::chrono::steady_clock::time_point t0;
+  gfmc_status fatal = GFMC_OK;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+static size_t plan_bytes(int n) {
+  return align256((size_t)n * sizeof(Desc)) + align256((size_t)(n + 1) * sizeof(int)) +
+         align256((size_t)kRecCap * n * sizeof(int32_t)) +
+         align256((size_t)kRecCap * n * sizeof(gfmc_step_record)) +
+         align256((size_t)kMagCap * n * sizeof(double));
+}
+
+static gfmc_result make_result(const Request* r, gfmc_status st, int64_t accepted, double t) {
+  gfmc_result x;
+  memset(&x, 0, sizeof(x));
+  x.request_id = r->id;
+  x.status = st;
+  x.L = r->p.L;
+  x.M = r->p.M;
+  x.sweeps = r->sweeps;
+  x.proposals = r->done_props;
+  x.accepted = accepted;
+  x.magnetization = r->mag_last;
+  x.magnetization_mean = r->sweeps ? r->mag_sum / r->sweeps : 0.0;
+  x.t_submit = r->t_submit;
+  x.t_admit = r->t_admit;
+  x.t_first_sweep = r->t_first_sweep;
+  x.t_done = t;
+  return x;
+}
+
+// Retire a running request (caller holds no lock; the worker thread only).
+static void retire(gfmc_engine* E, Request* r, gfmc_status st) {
+  int64_t acc = 0;
+  if (r->chain) {
+    if (hipMemcpy(&acc, &r->chain->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      acc = -1;
+  }
+  const gfmc_result res = make_result(r, st, acc, E->now());
+  std::lock_guard<std::mutex> g(E->mu);
+  E->done.push_back(res);
+  if (r->chain) {
+    delete r->chain;
+    r->chain = nullptr;
+    E->arena.release(r->off, r->bytes);
+  }
+  E->running.erase(std::remove(E->running.begin(), E->running.end(), r), E->running.end());
+  delete r;
+}
+
+// One proposal for every running chain of one precision (a plan holds one
+// precision; FP64 and FP32 requests advance in two launch sequences).
+static gfmc_status iterate_precision(gfmc_engine* E, int fp32, bool& any) {
+  std::vector<Request*> rs;
+  for (auto* r : E->running)
+    if (r->d.fp32 == fp32) rs.push_back(r);
+  if (rs.empty()) return GFMC_OK;
+  any = true;
+  std::vector<gfmc_chain*> sorted;
+  for (auto* r : rs) sorted.push_back(r->chain);
+  std::stable_sort(sorted.begin(), sorted.end(),
+                   [](gfmc_chain* a, gfmc_chain* b) { return a->d.S > b->d.S; });
+  Plan& P = E->plan;
+  P.fp32 = fp32;
+  plan_shape(P, sorted);
+  CHK(upload_plan(P, sorted));
+  CHK(enqueue_proposal(P, nullptr, nullptr, true));
+  return GFMC_OK;
+}
+
+static void worker_main(gfmc_engine* E) {
+  (void)hipSetDevice(E->device);
+  std::vector<Request*> admitted;
+  while (true) {
+    admitted.clear();
+    {
+      std::unique_lock<std::mutex> lk(E->mu);
+      if (E->stop) break;
+      while (!E->queue.empty() && (int)(E->running.size() + admitted.size()) < E->max_slots) {
+        Request* r = E->queue.front();
+        size_t off = 0;
+        if (!E->arena.alloc(r->bytes, off)) break;   // wait for memory (arrival order)
+        r->off = off;
+        E->queue.pop_front();
+        admitted.push_back(r);
+      }
+      if (E->running.empty() && admitted.empty()) {
+        E->busy = false;
+        E->cv.notify_all();
+        E->cv.wait(lk, [&] { return E->stop || !E->queue.empty(); });
+        continue;
+      }
+      E->busy = true;
+    }
+    for (auto* r : admitted) {
+      gfmc_chain* c = new (std::nothrow) gfmc_chain();
+      gfmc_status st = c ? chain_setup(c, &r->p, r->d, E->base + r->off, r->bytes, E->stream)
+                         : GFMC_ENOMEM;
+      if (st == GFMC_OK) st = chain_init_spins(c, r->init, r->frac);
+      if (st == GFMC_OK && hipStreamSynchronize(E->stream) != hipSuccess) st = GFMC_EDEVICE;
+      std::lock_guard<std::mutex> g(E->mu);
+      if (st != GFMC_OK) {
+        delete c;
+        E->arena.release(r->off, r->bytes);
+        E->done.push_back(make_result(r, st, 0, E->now()));
+        delete r;
+        continue;
+      }
+      r->chain = c;
+      r->t_admit = E->now();
+      r->t_sweep_start = r->t_admit;
+      E->running.push_back(r);
+    }
+    // cancelled requests leave before the next proposal
+    std::vector<Request*> cancelled;
+    {
+      std::lock_guard<std::mutex> g(E->mu);
+      for (auto* r : E->running)
+        if (r->cancel) cancelled.push_back(r);
+    }
+    for (auto* r : cancelled) retire(E, r, GFMC_ECANCELED);
+    if (E->running.empty()) continue;
+
+    bool any = false;
+    gfmc_status st = iterate_precision(E, 0, any);
+    if (st == GFMC_OK) st = iterate_precision(E, 1, any);
+    if (st == GFMC_OK && hipStreamSynchronize(E->stream) != hipSuccess) st = GFMC_EDEVICE;
+    if (st != GFMC_OK) {
+      std::vector<Request*> all = E->running;
+      for (auto* r : all) retire(E, r, st);
+      std::lock_guard<std::mutex> g(E->mu);
+      E->fatal = st;
+      E->stop = true;
+      break;
+    }
+    const double t = E->now();
+    std::vector<Request*> boundary;
+    for (auto* r : E->running) {
+      r->done_props += 1;
+      if (r->done_props % r->d.N == 0) boundary.push_back(r);
+    }
+    if (boundary.empty()) continue;
+    std::vector<double> mags(boundary.size());
+    bool ok = true;
+    for (size_t i = 0; i < boundary.size(); ++i) {
+      Plan& cp = boundary[i]->chain->plan;
+      ok = ok && launch_magnetization(cp.d_desc, 1, cp.d_mag, E->stream) == hipSuccess &&
+           hipMemcpyAsync(&mags[i], cp.d_mag, 8, hipMemcpyDeviceToHost, E->stream) == hipSuccess;
+    }
+    ok = ok && hipStreamSynchronize(E->stream) == hipSuccess;
+    std::vector<Request*> finished;
+    {
+      std::lock_guard<std::mutex> g(E->mu);
+      for (size_t i = 0; i < boundary.size(); ++i) {
+        Request* r = boundary[i];
+        E->lat.push_back({t - r->t_sweep_start, r->id});
+        r->t_sweep_start = t;
+        r->sweeps += 1;
+        r->mag_last = mags[i];
+        r->mag_sum += mags[i];
+        if (r->t_first_sweep < 0) r->t_first_sweep = t;
+        if (r->sweeps >= r->nsweeps) finished.push_back(r);
+      }
+    }
+    for (auto* r : finished) retire(E, r, ok ? GFMC_OK : GFMC_EDEVICE);
+  }
+  // stop: cancel whatever is still running
+  std::vector<Request*> all = E->running;
+  for (auto* r : all) retire(E, r, GFMC_ECANCELED);
+  std::lock_guard<std::mutex> g(E->mu);
+  E->busy = false;
+  E->cv.notify_all();
+}
+
+extern "C" {
+
+gfmc_status gfmc_engine_create(int device, size_t budget, int32_t max_slots, gfmc_engine** out) {
+  if (!out) return gfmc_fail(GFMC_EINVAL, "out is NULL");
+  if (max_slots < 1 || max_slots > 4096) return gfmc_fail(GFMC_EINVAL, "max_slots in [1, 4096]");
+  if (budget < 4096) return gfmc_fail(GFMC_EINVAL, "hbm_budget_bytes too small");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return gfmc_fail(GFMC_EINVAL, "no such device");
+  HIPCHK(hipSetDevice(device));
+  gfmc_engine* E = new (std::nothrow) gfmc_engine();
+  if (!E) return gfmc_fail(GFMC_ENOMEM, "host allocation failed");
+  E->device = device;
+  E->budget = budget & ~(size_t)255;
+  E->max_slots = max_slots;
+  E->t0 = std::chrono::steady_clock::now();
+  if (hipMalloc(&E->base, E->budget) != hipSuccess) {
+    delete E;
+    return gfmc_fail(GFMC_ENOMEM, "hipMalloc of the HBM budget failed");
+  }
+  if (hipMalloc(&E->plan_mem, plan_bytes(max_slots)) != hipSuccess ||
+      hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipFree(E->base);
+    if (E->plan_mem) (void)hipFree(E->plan_mem);
+    delete E;
+    return gfmc_fail(GFMC_EDEVICE, "engine device setup failed");
+  }
+  E->arena.init(E->budget);
+  Plan& P = E->plan;
+  char* w = E->plan_mem;
+  P.stream = E->stream;
+  P.d_desc = (Desc*)w; w += align256((size_t)max_slots * sizeof(Desc));
+  P.d_blkoff = (int*)w; w += align256((size_t)(max_slots + 1) * sizeof(int));
+  P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * max_slots * sizeof(int32_t));
+  P.d_rec = (gfmc_step_record*)w; w += align256((size_t)kRecCap * max_slots * sizeof(gfmc_step_record));
+  P.d_mag = (double*)w;
+  E->worker = std::thread(worker_main, E);
+  *out = E;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_engine_submit(gfmc_engine* E, const gfmc_chain_params* p, gfmc_init init,
+                               double frac, int32_t nsweeps, uint64_t* id) {
+  if (!E || !id) return gfmc_fail(GFMC_EINVAL, "NULL argument");
+  Derived d;
+  CHK(derive(p, d));
+  if (nsweeps < 1) return gfmc_fail(GFMC_EINVAL, "nsweeps must be >= 1");
+  if (init != GFMC_INIT_RANDOM && init != GFMC_INIT_FM && init != GFMC_INIT_FM_PLUS_RANDOM)
+    return gfmc_fail(GFMC_EINVAL, "unknown init mode");
+  if (init == GFMC_INIT_FM_PLUS_RANDOM && !(frac >= 0 && frac <= 1))
+    return gfmc_fail(GFMC_EINVAL, "random_fraction must be in [0, 1]");
+  const size_t need = layout_of(d).total;
+  if (align256(need) > E->budget) return gfmc_fail(GFMC_EBUSY, "request exceeds the HBM budget");
+  Request* r = new (std::nothrow) Request();
+  if (!r) return gfmc_fail(GFMC_ENOMEM, "host allocation failed");
+  r->p = *p;
+  r->d = d;
+  r->init = init;
+  r->frac = frac;
+  r->nsweeps = nsweeps;
+  r->bytes = need;
+  std::lock_guard<std::mutex> g(E->mu);
+  if (E->stop) {
+    delete r;
+    return gfmc_fail(E->fatal != GFMC_OK ? E->fatal : GFMC_ESTATE, "engine stopped");
+  }
+  r->id = E->next_id++;
+  r->t_submit = E->now();
+  E->queue.push_back(r);
+  *id = r->id;
+  E->cv.notify_all();
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_engine_poll(gfmc_engine* E, gfmc_result* out, int32_t cap, int32_t* n) {
+  if (!E || !n || (cap > 0 && !out)) return gfmc_fail(GFMC_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> g(E->mu);
+  const int k = std::min<int>(cap, (int)E->done.size());
+  for (int i = 0; i < k; ++i) out[i] = E->done[i];
+  E->done.erase(E->done.begin(), E->done.begin() + k);
+  *n = k;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_engine_cancel(gfmc_engine* E, uint64_t id) {
+  if (!E) return gfmc_fail(GFMC_EINVAL, "engine is NULL");
+  std::lock_guard<std::mutex> g(E->mu);
+  for (auto it = E->queue.begin(); it != E->queue.end(); ++it) {
+    if ((*it)->id == id) {
+      Request* r = *it;
+      E->queue.erase(it);
+      E->done.push_back(make_result(r, GFMC_ECANCELED, 0, E->now()));
+      delete r;
+      E->cv.notify_all();
+      return GFMC_OK;
+    }
+  }
+  for (auto* r : E->running)
+    if (r->id == id) {
+      r->cancel = true;
+      return GFMC_OK;
+    }
+  return gfmc_fail(GFMC_EINVAL, "unknown or finished request id");
+}
+
+gfmc_status gfmc_engine_sweep_latencies(gfmc_engine* E, double* sec, uint64_t* ids, int32_t cap,
+                                        int32_t* n) {
+  if (!E || !n || (cap > 0 && !sec)) return gfmc_fail(GFMC_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> g(E->mu);
+  const int k = std::min<int>(cap, (int)E->lat.size());
+  for (int i = 0; i < k; ++i) {
+    sec[i] = E->lat[i].first;
+    if (ids) ids[i] = E->lat[i].second;
+  }
+  E->lat.erase(E->lat.begin(), E->lat.begin() + k);
+  *n = k;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_engine_status(gfmc_engine* E, int32_t* queued, int32_t* running,
+                               int32_t* finished, size_t* bytes_in_use) {
+  if (!E) return gfmc_fail(GFMC_EINVAL, "engine is NULL");
+  std::lock_guard<std::mutex> g(E->mu);
+  if (queued) *queued = (int32_t)E->queue.size();
+  if (running) *running = (int32_t)E->running.size();
+  if (finished) *finished = (int32_t)E->done.size();
+  if (bytes_in_use) *bytes_in_use = E->arena.used;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_engine_drain(gfmc_engine* E, double timeout_s) {
+  if (!E) return gfmc_fail(GFMC_EINVAL, "engine is NULL");
+  std::unique_lock<std::mutex> lk(E->mu);
+  const auto until = std::chrono::steady_clock::now() +
+                     std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                         std::chrono::duration<double>(timeout_s));
+  const bool ok = E->cv.wait_until(lk, until, [&] {
+    return E->stop || (E->queue.empty() && E->running.empty() && !E->busy);
+  });
+  if (E->fatal != GFMC_OK) return gfmc_fail(E->fatal, "engine stopped after a device error");
+  return ok ? GFMC_OK : gfmc_fail(GFMC_EBUSY, "drain timed out");
+}
+
+gfmc_status gfmc_engine_destroy(gfmc_engine* E) {
+  if (!E) return GFMC_OK;
+  {
+    std::lock_guard<std::mutex> g(E->mu);
+    E->stop = true;
+    for (auto* r : E->queue) delete r;
+    E->queue.clear();
+    E->cv.notify_all();
+  }
+  if (E->worker.joinable()) E->worker.join();
+  (void)hipSetDevice(E->device);
+  (void)hipStreamSynchronize(E->stream);
+  (void)hipStreamDestroy(E->stream);
+  (void)hipFree(E->plan_mem);
+  (void)hipFree(E->base);
+  delete E;
+  return GFMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// gfmc_host.h -- host-side internals shared by the C ABI translation units
+// (chain/batch handles, workspace layout, launch plans).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "gfmc_device.h"
+
+namespace gfmc {
+hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
+hipError_t launch_step(int fp32, int ppt, const Desc* d, const int* blkoff, int nact, int blocks,
+                       int s, hipStream_t st);
+hipError_t launch_moments(const Desc* d, int n, int smax, hipStream_t st);
+hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
+                        gfmc_step_record* recs, hipStream_t st);
+hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t st);
+hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st);
+hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st);
+hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t st);
+}  // namespace gfmc
+
+using namespace gfmc;
+
+gfmc_status gfmc_fail(gfmc_status s, const std::string& msg);
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return gfmc_fail(GFMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+  } while (0)
+
+#define CHK(expr)                          \
+  do {                                     \
+    gfmc_status s_ = (expr);               \
+    if (s_ != GFMC_OK) return s_;          \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------- chain layout ----
+struct Derived {
+  int L, N, half, M, S, K, log2K, nblk, fp32;
+  double a, lambda;
+};
+
+struct Layout {
+  size_t desc, blkoff, force, rec, mag, ctl, theta, phi, spin, vec, part, mom, gscr, total;
+};
+
+// A launch plan: a device table of chain descriptors (sorted by number of
+// Chebyshev steps, largest first) and the block offsets of the step kernel.
+struct Plan {
+  int n = 0, fp32 = 0, smax = 0, kmax = 0, nmax = 0;
+  int ppt = 1;                         // site pairs per thread of the step kernel
+  Desc* d_desc = nullptr;
+  int* d_blkoff = nullptr;
+  int32_t* d_force = nullptr;          // [kRecCap][n]
+  gfmc_step_record* d_rec = nullptr;   // [kRecCap][n]
+  double* d_mag = nullptr;             // [kMagCap][n]
+  std::vector<int> S, blkoff;          // per sorted chain; blkoff has n+1 entries
+  hipStream_t stream = nullptr;
+  // timing of the step launches
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  double step_ms = 0;
+  int64_t step_launches = 0;
+  bool timing = false;
+  // graph replay of one proposal
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+struct gfmc_chain {
+  gfmc_chain_params p;
+  Derived d;
+  Layout l;
+  char* ws = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Desc desc;
+  Plan plan;            // single-chain plan living in the chain's workspace
+  bool in_batch = false;
+};
+
+struct gfmc_batch {
+  std::vector<gfmc_chain*> chains;   // caller order
+  std::vector<gfmc_chain*> sorted;   // plan order
+  std::vector<int> order;            // sorted position -> caller index
+  Plan plan;
+  bool use_graph = false;
+};
+
+
+gfmc_status derive(const gfmc_chain_params* p, Derived& d);
+Layout layout_of(const Derived& d);
+void fill_desc(gfmc_chain* c);
+gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted);
+void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted);
+gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* d_rec,
+                             bool with_recon);
+gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived& d, void* ws,
+                        size_t bytes, hipStream_t stream);
+gfmc_status chain_init_spins(gfmc_chain* c, int mode, double frac);

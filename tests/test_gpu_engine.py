@@ -1,0 +1,84 @@
+"""Serving engine on the GPU: continuous batching of uneven chains gives each
+request the same result as running it alone; admission by slots and HBM
+budget; cancellation."""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1303_6016_amd as g
+    g.lib()
+    return g
+
+
+SPECS = [  # L, M, T, precision, init, nsweeps
+    (4, 128, 0.05, 0, 0, 2),
+    (6, 64, 0.2, 1, 0, 1),
+    (4, 256, 0.1, 1, 2, 1),
+    (2, 32, 0.02, 0, 1, 3),
+    (6, 128, 0.15, 0, 0, 1),
+]
+
+
+def params(g, i, spec):
+    L, M, T, prec, _, _ = spec
+    return g.Params(L=L, M=M, beta=1.0 / T, precision=prec, seed=2024, chain_id=i)
+
+
+def test_engine_results_equal_alone_runs(g):
+    eng = g.Engine(0, hbm_budget_bytes=256 << 20, max_slots=3)
+    ids = []
+    for i, spec in enumerate(SPECS):
+        ids.append(eng.submit(params(g, i, spec), init=spec[4], frac=0.1, nsweeps=spec[5]))
+        time.sleep(0.01)   # staggered arrivals join running work
+    eng.drain(600)
+    res = {r.request_id: r for r in eng.poll()}
+    lat, lat_ids = eng.sweep_latencies()
+    assert len(lat) == sum(s[5] for s in SPECS) and np.all(lat > 0)
+    st = eng.status()
+    assert st["running"] == 0 and st["queued"] == 0 and st["bytes"] == 0
+    eng.close()
+    for i, spec in enumerate(SPECS):
+        r = res[ids[i]]
+        assert r.status == 0 and r.sweeps == spec[5]
+        ch = g.Chain(params(g, i, spec))
+        ch.init_spins(spec[4], 0.1)
+        mag, acc = ch.sweep(spec[5])
+        print(f"request {i}: L={spec[0]} M={spec[1]} accepted {r.accepted} alone {acc} "
+              f"|m| {r.magnetization:.12f} alone {mag[-1]:.12f}", flush=True)
+        assert r.proposals == spec[5] * spec[0] ** 3
+        assert r.accepted == acc
+        assert r.magnetization == mag[-1]
+        assert abs(r.magnetization_mean - mag.mean()) < 1e-15
+        assert r.t_submit <= r.t_admit <= r.t_first_sweep <= r.t_done
+
+
+def test_engine_budget_and_cancel(g):
+    p_big = g.Params(L=32, M=2048)
+    eng = g.Engine(0, hbm_budget_bytes=8 << 20, max_slots=2)
+    with pytest.raises(g.GfmcError) as e:
+        eng.submit(p_big)
+    assert e.value.status == g.GFMC_EBUSY
+    long_id = eng.submit(g.Params(L=8, M=256, seed=1), nsweeps=1000)
+    queued_id = eng.submit(g.Params(L=8, M=256, seed=2), nsweeps=1000)
+    third = eng.submit(g.Params(L=8, M=256, seed=3), nsweeps=1000)   # waits for a slot
+    time.sleep(0.5)
+    assert eng.status()["queued"] >= 1
+    eng.cancel(third)
+    eng.cancel(long_id)
+    eng.cancel(queued_id)
+    eng.drain(120)
+    res = {r.request_id: r for r in eng.poll()}
+    assert {long_id, queued_id, third} <= set(res)
+    assert all(res[i].status == g.GFMC_ECANCELED for i in (long_id, queued_id, third))
+    with pytest.raises(g.GfmcError):
+        eng.cancel(long_id)
+    eng.close()
