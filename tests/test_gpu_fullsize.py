@@ -1,0 +1,143 @@
+"""Full-size GPU checks: the 64^3 (M = 4096) and 32^3 (M = 2048) shapes.
+
+At 64^3 the oracle needs minutes per site, so the checks use what holds at any
+size: for uniform spins H is the tight-binding operator and its local moments
+are the exact k-sums (1/N) sum_q cos(q.(r_j - r_k)) T_n(e_q / a); for random
+spins the moment invariants (mu_0, mu_1, mu_2^{oo}, Hermiticity, bipartite
+zeros, |mu| <= 1).  At 32^3 the oracle is run one site / one proposal at a time.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1303_6016_amd as g
+    g.lib()
+    return g
+
+
+def ksum_classes(L, M, a):
+    """Exact moments of the uniform-spin lattice for displacement classes
+    0, e_x, 2 e_x, e_x + e_y (cubic symmetry makes every pair of the 7 start
+    sites fall in one of them); Chebyshev recursion on the q grid."""
+    q1 = 2 * np.pi * np.arange(L) / L
+    c = np.cos(q1)
+    x = ((-2.0 / a) * (c[:, None, None] + c[None, :, None] + c[None, None, :])).ravel()
+    disps = [(0, 0, 0), (1, 0, 0), (2, 0, 0), (1, 1, 0)]
+    ph = np.stack([np.cos(q1[:, None, None] * D[0] + q1[None, :, None] * D[1] +
+                          q1[None, None, :] * D[2]).ravel() for D in disps])
+    out = np.zeros((M, 4))
+    t0, t1 = np.ones_like(x), x.copy()
+    out[0], out[1] = ph @ t0 / x.size, ph @ t1 / x.size
+    for n in range(2, M):
+        t0, t1 = t1, 2 * x * t1 - t0
+        out[n] = ph @ t1 / x.size
+    return out
+
+
+def class_of(L, i, j):
+    ri = np.array([i % L, (i // L) % L, i // (L * L)])
+    rj = np.array([j % L, (j // L) % L, j // (L * L)])
+    d = np.abs(ri - rj)
+    d = np.minimum(d, L - d)
+    key = tuple(sorted(d.tolist(), reverse=True))
+    return {(0, 0, 0): 0, (1, 0, 0): 1, (2, 0, 0): 2, (1, 1, 0): 3}[key]
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+def test_64cubed_uniform_spins_k_sum(g, prec, tol):
+    L, M = 64, 4096
+    ch = g.Chain(g.Params(L=L, M=M, precision=prec))
+    ch.init_spins(g.INIT_FM)
+    o = 123457
+    mu = ch.moments(o)
+    a = 6.0 / 0.99
+    ref_c = ksum_classes(L, M, a)
+    s = oracle.start_sites(L, o)
+    ref = np.zeros((M, 7, 7))
+    for j in range(7):
+        for k in range(7):
+            ref[:, j, k] = ref_c[:, class_of(L, s[j], s[k])]
+    err = np.abs(mu - ref).max()
+    print(f"64^3 M=4096 prec={prec} uniform spins: max|dmu|={err:.2e}", flush=True)
+    assert err < tol
+
+
+def test_64cubed_random_spins_invariants(g):
+    L, M = 64, 4096
+    ch64 = g.Chain(g.Params(L=L, M=M, precision=0, seed=11))
+    ch64.init_spins(g.INIT_RANDOM)
+    th, ph = ch64.get_spins()
+    o = 200001
+    mu = ch64.moments(o)
+    s = oracle.start_sites(L, o)
+    a = 6.0 / 0.99
+    # mu_1 = Ht between start sites, from the angles (equation "ht")
+    H1 = np.zeros((7, 7), complex)
+    for j in range(7):
+        for k in range(7):
+            for d in range(6):
+                if oracle.neighbor(L, s[j], d) == s[k]:
+                    H1[j, k] += -oracle.hopping(th[s[j]], ph[s[j]], th[s[k]], ph[s[k]]) / a
+    assert np.abs(mu[0] - np.eye(7)).max() == 0
+    assert np.abs(mu[1] - H1).max() < 1e-15
+    S = lambda t, p: np.array([np.sin(t) * np.cos(p), np.sin(t) * np.sin(p), np.cos(t)])
+    t2 = sum((1 + S(th[o], ph[o]) @ S(th[n], ph[n])) / 2 for n in s[1:])
+    assert abs(mu[2, 0, 0] - (2 * t2 / a ** 2 - 1)) < 1e-14
+    assert np.abs(mu - mu.conj().transpose(0, 2, 1)).max() == 0
+    assert np.abs(mu).max() <= 1 + 1e-12
+    assert np.all(mu[1::2, 0, 0] == 0) and np.all(mu[0::2, 0, 1:] == 0)
+    assert np.all(mu[1::2, 1:, 1:] == 0)
+    # FP32 recursion on the same spins stays within the FP32 tolerance
+    ch32 = g.Chain(g.Params(L=L, M=M, precision=1, seed=11))
+    ch32.set_spins(th, ph)
+    err = np.abs(ch32.moments(o) - mu).max()
+    print(f"64^3 random spins: FP32 vs FP64 max|dmu|={err:.2e}", flush=True)
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
+def test_32cubed_delta_seff_against_oracle(g, prec, tol):
+    L, M = 32, 2048
+    ch = g.Chain(g.Params(L=L, M=M, beta=1 / 0.05, precision=prec, seed=7, chain_id=1))
+    m = oracle.Model(L=L, M=M, beta=1 / 0.05, seed=7, chain_id=1)
+    th, ph = oracle.init_spins(m, 0)
+    ch.set_spins(th, ph)
+    for idx in range(2):
+        ro = oracle.step(m, th, ph, idx)
+        rg = ch.step(force=ro.accepted)
+        print(f"32^3 prec={prec} proposal {idx}: dS={ro.dseff:.9f} err={rg.dseff - ro.dseff:.2e}",
+              flush=True)
+        assert rg.site == ro.site and rg.u == ro.u
+        assert abs(rg.dseff - ro.dseff) < tol
+
+
+def test_64cubed_with_eight_32cubed_chains_in_one_batch(g):
+    # one 64^3 chain (M = 4096) and eight 32^3 chains (M = 2048), FP32
+    # recursion: each chain's proposal in the mixed batch equals its alone run
+    def build():
+        chs = [g.Chain(g.Params(L=64, M=4096, beta=20.0, precision=1, seed=11, chain_id=0))]
+        for c in range(8):
+            chs.append(g.Chain(g.Params(L=32, M=2048, beta=20.0, precision=1, seed=11,
+                                        chain_id=1 + c)))
+        for ch in chs:
+            ch.init_spins(g.INIT_RANDOM)
+        return chs
+    alone = [ch.step() for ch in build()]
+    mixed = build()
+    b = g.Batch(mixed)
+    recs = b.step(1, records=True)[0]
+    b.close()
+    for r, a in zip(recs, alone):
+        assert (r.site, r.u, r.accepted) == (a.site, a.u, a.accepted)
+        assert r.dseff == a.dseff
