@@ -74,6 +74,11 @@ typedef enum { GFMC_FP64 = 0, GFMC_FP32_ACC64 = 1 } gfmc_precision;
 typedef enum { GFMC_JACKSON = 0, GFMC_LORENTZ = 1 } gfmc_kernel;
 typedef enum { GFMC_PROPOSE_SPHERE = 0, GFMC_PROPOSE_CONE = 1 } gfmc_proposal;
 typedef enum { GFMC_INIT_RANDOM = 0, GFMC_INIT_FM = 1, GFMC_INIT_FM_PLUS_RANDOM = 2 } gfmc_init;
+/* Start vectors of the recursion: the 7 unit vectors of o and its neighbours
+ * (all 7x7 local moments), or the pair {|o>, |v> = Delta|o>} (only the three
+ * series mu^{oo}, mu^{vv}, mu^{ov} that the 2x2 determinant needs; 2/7 of the
+ * vector work per proposal). */
+typedef enum { GFMC_VECTORS_SITES = 0, GFMC_VECTORS_OV = 1 } gfmc_vectors;
 
 /* Parameters of one Markov chain (all energies in units of t). */
 typedef struct {
@@ -92,6 +97,7 @@ typedef struct {
   double cone_angle;        /* cap half-angle in rad (GFMC_PROPOSE_CONE)              */
   uint64_t seed;            /* Philox key word 0                                      */
   uint64_t chain_id;        /* Philox key word 1                                      */
+  gfmc_vectors vectors;     /* start vectors (GFMC_VECTORS_SITES default)             */
 } gfmc_chain_params;
 
 /* Outcome of one proposal (Algorithm 1, inner loop body). */
@@ -143,8 +149,16 @@ gfmc_status gfmc_set_counter(gfmc_chain* chain, int64_t index);
 gfmc_status gfmc_get_counter(gfmc_chain* chain, int64_t* index);
 
 /* Local moments around `site` for the current spins (no state change):
- * writes mu[M][7][7][2] (host). */
+ * writes mu[M][7][7][2] (host).  Chains created with GFMC_VECTORS_SITES only
+ * (ESTATE otherwise). */
 gfmc_status gfmc_moments(gfmc_chain* chain, int32_t site, double* mu);
+
+/* Moments of the pair {|o>, |v>} for moving the spin at `site` to
+ * (theta_new, phi_new), no state change: mu[n][s][2] with s = 0: <o|T_n|o>,
+ * 1: <v|T_n|v>, 2: <o|T_n|v>, |v> = sum_d Delta_{n_d,o} |n_d>.  Chains created
+ * with GFMC_VECTORS_OV only (ESTATE otherwise). */
+gfmc_status gfmc_pair_moments(gfmc_chain* chain, int32_t site, double theta_new, double phi_new,
+                              double* mu);
 
 /* Delta S_eff for moving the spin at `site` to (theta_new, phi_new), no state
  * change.  phase_top may be NULL. */

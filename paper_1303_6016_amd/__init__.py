@@ -23,6 +23,7 @@ FP64, FP32_ACC64 = 0, 1
 JACKSON, LORENTZ = 0, 1
 PROPOSE_SPHERE, PROPOSE_CONE = 0, 1
 INIT_RANDOM, INIT_FM, INIT_FM_PLUS_RANDOM = 0, 1, 2
+VECTORS_SITES, VECTORS_OV = 0, 1
 
 
 class GfmcError(RuntimeError):
@@ -39,6 +40,7 @@ class ChainParams(ctypes.Structure):
         ("scale_a", ctypes.c_double), ("scale_b", ctypes.c_double),
         ("precision", ctypes.c_int32), ("proposal", ctypes.c_int32),
         ("cone_angle", ctypes.c_double), ("seed", ctypes.c_uint64), ("chain_id", ctypes.c_uint64),
+        ("vectors", ctypes.c_int32),
     ]
 
 
@@ -77,6 +79,7 @@ _SIGS = {
     "gfmc_get_counter": [_vp, _P(_i64)],
     "gfmc_moments": [_vp, _i32, _P(_d)],
     "gfmc_delta_seff": [_vp, _i32, _d, _d, _P(_d), _P(_d)],
+    "gfmc_pair_moments": [_vp, _i32, _d, _d, _P(_d)],
     "gfmc_step": [_vp, _i32, _P(StepRecord)],
     "gfmc_sweep": [_vp, _i32, _P(_d), _P(_i64)],
     "gfmc_sync": [_vp],
@@ -153,12 +156,13 @@ class Params:
     cone_angle: float = 0.0
     seed: int = 0
     chain_id: int = 0
+    vectors: int = VECTORS_SITES
 
     def c(self) -> ChainParams:
         return ChainParams(self.L, self.t, self.beta, self.mu, self.M, self.K, self.kernel,
                            self.lorentz_lambda, self.scale_a, self.scale_b, self.precision,
                            self.proposal, self.cone_angle, self.seed & (2**64 - 1),
-                           self.chain_id & (2**64 - 1))
+                           self.chain_id & (2**64 - 1), self.vectors)
 
     @property
     def N(self) -> int:
@@ -241,6 +245,12 @@ class Chain:
     def moments(self, site: int) -> np.ndarray:
         out = np.zeros((self.p.M, 7, 7, 2))
         _check(lib().gfmc_moments(self.h, site, _dptr(out)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def pair_moments(self, site: int, theta_new: float, phi_new: float) -> np.ndarray:
+        """(M, 3) complex: <o|T_n|o>, <v|T_n|v>, <o|T_n|v> for the proposed move."""
+        out = np.zeros((self.p.M, 3, 2))
+        _check(lib().gfmc_pair_moments(self.h, site, theta_new, phi_new, _dptr(out)))
         return out[..., 0] + 1j * out[..., 1]
 
     def delta_seff(self, site: int, theta_new: float, phi_new: float, with_phase_top=False):

@@ -46,6 +46,8 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   if (p->proposal == GFMC_PROPOSE_CONE && !(p->cone_angle > 0 && p->cone_angle <= M_PI))
     return fail(GFMC_EINVAL, "cone_angle must be in (0, pi]");
   if (p->kernel == GFMC_LORENTZ && p->lorentz_lambda < 0) return fail(GFMC_EINVAL, "lambda < 0");
+  if (p->vectors != GFMC_VECTORS_SITES && p->vectors != GFMC_VECTORS_OV)
+    return fail(GFMC_EINVAL, "unknown start-vector form");
   d.L = p->L;
   d.N = p->L * p->L * p->L;
   d.half = d.N / 2;
@@ -56,6 +58,7 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   while ((1 << d.log2K) < K) ++d.log2K;
   d.nblk = (d.half + kStepThreads - 1) / kStepThreads;
   d.fp32 = p->precision == GFMC_FP32_ACC64;
+  d.ov = p->vectors == GFMC_VECTORS_OV;
   d.a = p->scale_a > 0 ? p->scale_a : 6.0 * p->t / (1.0 - 0.01);
   d.lambda = p->lorentz_lambda > 0 ? p->lorentz_lambda : 4.0;
   if (d.a < 6.0 * p->t) return fail(GFMC_EINVAL, "scale_a must be >= 6t (spectrum inside [-1,1])");
@@ -76,9 +79,9 @@ Layout layout_of(const Derived& d) {
   l.theta = take((size_t)d.N * 8);
   l.phi = take((size_t)d.N * 8);
   l.spin = take((size_t)d.N * 4 * tsz);
-  l.vec = take((size_t)7 * d.N * 2 * tsz);
-  l.part = take((size_t)d.S * d.nblk * kNP * 8);
-  l.mom = take((size_t)d.M * 49 * 16);
+  l.vec = take((size_t)(d.ov ? 2 : 7) * d.N * 2 * tsz);
+  l.part = take((size_t)d.S * d.nblk * (d.ov ? kNP2 : kNP) * 8);
+  l.mom = take((size_t)d.M * (d.ov ? 3 : 49) * 16);
   l.gscr = take((size_t)4 * d.K * 16);
   l.total = o;
   return l;
@@ -89,6 +92,7 @@ void fill_desc(gfmc_chain* c) {
   memset(&D, 0, sizeof(D));
   D.L = c->d.L; D.N = c->d.N; D.half = c->d.half; D.M = c->d.M; D.S = c->d.S; D.K = c->d.K;
   D.nblk = c->d.nblk; D.kernel = c->p.kernel; D.proposal = c->p.proposal; D.log2K = c->d.log2K;
+  D.vectors = c->p.vectors;
   D.t = c->p.t; D.beta = c->p.beta; D.mu = c->p.mu; D.a = c->d.a; D.cone = c->p.cone_angle;
   D.lambda = c->d.lambda; D.seed = c->p.seed; D.chain_id = c->p.chain_id;
   D.theta = (double*)(c->ws + c->l.theta);
@@ -145,14 +149,15 @@ gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* 
   int nact = P.n;
   for (int s = 1; s <= P.smax; ++s) {
     while (nact > 0 && P.S[nact - 1] < s) --nact;
-    HIPCHK(launch_step(P.fp32, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s, P.stream));
+    HIPCHK(launch_step(P.fp32, P.ov, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s,
+                       P.stream));
   }
   if (tm) {
     HIPCHK(hipEventRecord(P.ev[P.ev_used + 1], P.stream));
     P.ev_used += 2;
   }
   if (P.timing) P.step_launches += P.smax;
-  HIPCHK(launch_moments(P.d_desc, P.n, P.smax, P.stream));
+  HIPCHK(launch_moments(P.ov, P.d_desc, P.n, P.smax, P.stream));
   if (with_recon) HIPCHK(launch_recon(P.fp32, P.d_desc, P.n, P.kmax, d_force, d_rec, P.stream));
   return GFMC_OK;
 }
@@ -224,6 +229,7 @@ gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived
   Plan& P = c->plan;
   P.stream = c->stream;
   P.fp32 = d.fp32;
+  P.ov = d.ov;
   P.d_desc = (Desc*)(c->ws + l.desc);
   P.d_blkoff = (int*)(c->ws + l.blkoff);
   P.d_force = (int32_t*)(c->ws + l.force);
@@ -376,9 +382,24 @@ gfmc_status gfmc_moments(gfmc_chain* c, int32_t site, double* mu) {
   CHK(check_chain(c));
   if (site < 0 || site >= c->d.N) return fail(GFMC_EINVAL, "site out of range");
   if (!mu) return fail(GFMC_EINVAL, "mu is NULL");
+  if (c->d.ov) return fail(GFMC_ESTATE, "chain uses the {o,v} start vectors");
   CHK(set_mode(c, 2, site, 0.0, 0.0));
   CHK(enqueue_proposal(c->plan, nullptr, nullptr, false));
   HIPCHK(hipMemcpyAsync(mu, c->desc.mom, (size_t)c->d.M * 49 * 16, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return set_mode(c, 0, 0, 0.0, 0.0);
+}
+
+gfmc_status gfmc_pair_moments(gfmc_chain* c, int32_t site, double tn, double pn, double* mu) {
+  CHK(check_chain(c));
+  if (site < 0 || site >= c->d.N) return fail(GFMC_EINVAL, "site out of range");
+  if (!std::isfinite(tn) || !std::isfinite(pn)) return fail(GFMC_EINVAL, "angles not finite");
+  if (!mu) return fail(GFMC_EINVAL, "mu is NULL");
+  if (!c->d.ov) return fail(GFMC_ESTATE, "chain uses the 7 site start vectors");
+  CHK(set_mode(c, 1, site, tn, pn));
+  CHK(enqueue_proposal(c->plan, nullptr, nullptr, false));
+  HIPCHK(hipMemcpyAsync(mu, c->desc.mom, (size_t)c->d.M * 3 * 16, hipMemcpyDeviceToHost,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return set_mode(c, 0, 0, 0.0, 0.0);
@@ -461,9 +482,11 @@ gfmc_status gfmc_chain_step_bytes(gfmc_chain* c, double* bytes_per_step, int32_t
   // Per step: read both stored values of every site (7 complex: one class is
   // the stencil input, the other the a_{s-2} term), write 3.5 complex per
   // site (the class being advanced), read the spinor of every site.
+  // The {o,v} form stores 2 complex values per site and advances 1.
   const double tsz = c->d.fp32 ? 4 : 8;
   const double N = c->d.N;
-  *bytes_per_step = N * (7.0 * 2 * tsz + 3.5 * 2 * tsz + 4 * tsz);
+  const double stored = c->d.ov ? 2.0 : 7.0;
+  *bytes_per_step = N * (stored * 2 * tsz + 0.5 * stored * 2 * tsz + 4 * tsz);
   *steps = c->d.S;
   return GFMC_OK;
 }
@@ -493,6 +516,7 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
     if (!chains[i]) return fail(GFMC_EINVAL, "NULL chain");
     if (chains[i]->in_batch) return fail(GFMC_ESTATE, "chain already in a batch");
     if (chains[i]->d.fp32 != chains[0]->d.fp32) return fail(GFMC_EINVAL, "mixed precision");
+    if (chains[i]->d.ov != chains[0]->d.ov) return fail(GFMC_EINVAL, "mixed start-vector forms");
     if (chains[i]->device != dev) return fail(GFMC_EINVAL, "chain on another device");
     for (int j = 0; j < i; ++j)
       if (chains[j] == chains[i]) return fail(GFMC_EINVAL, "chain listed twice");
@@ -510,6 +534,7 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
   char* w = (char*)ws;
   P.stream = (hipStream_t)stream;
   P.fp32 = chains[0]->d.fp32;
+  P.ov = chains[0]->d.ov;
   P.d_desc = (Desc*)w; w += align256((size_t)n * sizeof(Desc));
   P.d_blkoff = (int*)w; w += align256((size_t)(n + 1) * sizeof(int));
   P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * n * sizeof(int32_t));
@@ -671,7 +696,7 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   if (!b) return fail(GFMC_EINVAL, "batch is NULL");
   if (trial_steps < 1) return fail(GFMC_EINVAL, "trial_steps must be >= 1");
   Plan& P = b->plan;
-  std::vector<int> key = {P.fp32, P.n};
+  std::vector<int> key = {P.fp32, P.ov, P.n};
   for (auto* c : b->sorted) { key.push_back(c->d.L); key.push_back(c->d.M); }
   for (auto& kv : g_tune_cache)
     if (kv.first == key) {
@@ -689,14 +714,16 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
     CHK(gfmc_batch_set_tuning(b, ppt));
     // a proposal state for the trial (the counter only advances in k_recon)
     HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
-    HIPCHK(launch_step(P.fp32, P.ppt, P.d_desc, P.d_blkoff, P.n, P.blkoff[P.n], 1, P.stream));
+    HIPCHK(launch_step(P.fp32, P.ov, P.ppt, P.d_desc, P.d_blkoff, P.n, P.blkoff[P.n], 1,
+                       P.stream));
     const int smax = std::max(2, std::min(P.smax, trial_steps + 1));
     int nact = P.n;
     HIPCHK(hipEventRecord(e0, P.stream));
     for (int s = 2; s <= smax; ++s) {
       while (nact > 0 && P.S[nact - 1] < s) --nact;
       if (nact == 0) break;
-      HIPCHK(launch_step(P.fp32, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s, P.stream));
+      HIPCHK(launch_step(P.fp32, P.ov, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s,
+                         P.stream));
     }
     HIPCHK(hipEventRecord(e1, P.stream));
     HIPCHK(hipEventSynchronize(e1));

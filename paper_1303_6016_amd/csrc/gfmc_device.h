@@ -9,7 +9,8 @@
 namespace gfmc {
 
 constexpr int kStepThreads = 256;   // threads per block of the Chebyshev step kernel
-constexpr int kNP = 49;             // moment partial sums per block and step
+constexpr int kNP = 49;             // moment partial sums per block and step (7 site vectors)
+constexpr int kNP2 = 4;             // ... for the pair {o, v}
 constexpr int kReconThreads = 256;  // threads of the reconstruction block (one per chain)
 constexpr int kRecCap = 64;         // proposals per host round trip (records, forcing)
 constexpr int kMagCap = 64;         // sweeps per host round trip (magnetization)
@@ -44,14 +45,16 @@ struct Ctl {
 // Per-chain descriptor (device table read by the batched kernels).
 struct Desc {
   int32_t L, N, half, M, S, K, nblk, kernel, proposal, log2K;
+  int32_t vectors, pad_;      // GFMC_VECTORS_SITES or GFMC_VECTORS_OV
   double t, beta, mu, a, cone, lambda;
   uint64_t seed, chain_id;
   double* theta;            // [N]
   double* phi;              // [N]
   void* spin;               // spn<T>[2][half]   (parity, half-row index)
-  void* vec;                // cpx<T>[7][2][half] (slot, parity, half-row index)
-  double* part;             // [S][nblk][kNP]
-  double* mom;              // [M][7][7][2]
+  void* vec;                // o-slots cpx<T>[2][half], then n-slots six<T>[2][half]
+                            // ({o,v}: o-slots, then v-slots cpx<T>[2][half])
+  double* part;             // [S][nblk][kNP] ({o,v}: [S][nblk][kNP2])
+  double* mom;              // [M][7][7][2]  ({o,v}: [M][3][2])
   double* gscr;             // [4][K][2]
   Ctl* ctl;
 };

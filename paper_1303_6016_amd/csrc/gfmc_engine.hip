@@ -158,12 +158,12 @@ static void retire(gfmc_engine* E, Request* r, gfmc_status st) {
   delete r;
 }
 
-// One proposal for every running chain of one precision (a plan holds one
-// precision; FP64 and FP32 requests advance in two launch sequences).
-static gfmc_status iterate_precision(gfmc_engine* E, int fp32, bool& any) {
+// One proposal for every running chain of one precision and start-vector
+// form (a plan holds one of each; the groups advance in separate sequences).
+static gfmc_status iterate_precision(gfmc_engine* E, int fp32, int ov, bool& any) {
   std::vector<Request*> rs;
   for (auto* r : E->running)
-    if (r->d.fp32 == fp32) rs.push_back(r);
+    if (r->d.fp32 == fp32 && r->d.ov == ov) rs.push_back(r);
   if (rs.empty()) return GFMC_OK;
   any = true;
   std::vector<gfmc_chain*> sorted;
@@ -172,6 +172,7 @@ static gfmc_status iterate_precision(gfmc_engine* E, int fp32, bool& any) {
                    [](gfmc_chain* a, gfmc_chain* b) { return a->d.S > b->d.S; });
   Plan& P = E->plan;
   P.fp32 = fp32;
+  P.ov = ov;
   plan_shape(P, sorted);
   CHK(upload_plan(P, sorted));
   CHK(enqueue_proposal(P, nullptr, nullptr, true));
@@ -232,8 +233,8 @@ static void worker_main(gfmc_engine* E) {
     if (E->running.empty()) continue;
 
     bool any = false;
-    gfmc_status st = iterate_precision(E, 0, any);
-    if (st == GFMC_OK) st = iterate_precision(E, 1, any);
+    gfmc_status st = GFMC_OK;
+    for (int q = 0; q < 4 && st == GFMC_OK; ++q) st = iterate_precision(E, q & 1, q >> 1, any);
     if (st == GFMC_OK && hipStreamSynchronize(E->stream) != hipSuccess) st = GFMC_EDEVICE;
     if (st != GFMC_OK) {
       std::vector<Request*> all = E->running;

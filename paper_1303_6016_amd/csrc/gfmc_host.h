@@ -10,9 +10,9 @@
 
 namespace gfmc {
 hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
-hipError_t launch_step(int fp32, int ppt, const Desc* d, const int* blkoff, int nact, int blocks,
-                       int s, hipStream_t st);
-hipError_t launch_moments(const Desc* d, int n, int smax, hipStream_t st);
+hipError_t launch_step(int fp32, int ov, int ppt, const Desc* d, const int* blkoff, int nact,
+                       int blocks, int s, hipStream_t st);
+hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st);
 hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
                         gfmc_step_record* recs, hipStream_t st);
 hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t st);
@@ -42,7 +42,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------- chain layout ----
 struct Derived {
-  int L, N, half, M, S, K, log2K, nblk, fp32;
+  int L, N, half, M, S, K, log2K, nblk, fp32, ov;
   double a, lambda;
 };
 
@@ -55,6 +55,7 @@ struct Layout {
 struct Plan {
   int n = 0, fp32 = 0, smax = 0, kmax = 0, nmax = 0;
   int ppt = 1;                         // site pairs per thread of the step kernel
+  int ov = 0;                          // start vectors {o, v} instead of the 7 sites
   Desc* d_desc = nullptr;
   int* d_blkoff = nullptr;
   int32_t* d_force = nullptr;          // [kRecCap][n]

@@ -470,6 +470,195 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   }
 }
 
+// The pair form {|o>, |v>}: |a^o_0> = |o>, |a^v_0> = |v> = sum_d delta_d |n_d>
+// (|v> = Delta|o>, Section 2.2).  Same bipartite storage as above with one
+// v-slot in place of the six n-slots: a^o_s lives on parity p(o)^(s&1), a^v_s
+// on the other.  Per step the block sums P^{oo}_s = <a^o_s|a^o_s>,
+// P^{vv}_s = <a^v_s|a^v_s> and Q^{ov}_s = <a^o_{s-1}|a^v_s> (4 real numbers;
+// the pairs that vanish on a bipartite lattice are not formed) with wavefront
+// shuffles and one LDS step.
+template <typename T, bool FIRST, int PPT>
+__global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict__ descs,
+                                                          const int* __restrict__ blkoff,
+                                                          int nact, int s) {
+  __shared__ double red[4][kNP2];
+  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+  int c = 0;
+  {
+    int lo = 0, hi = nact - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (blkoff[mid] <= gb) lo = mid; else hi = mid - 1;
+    }
+    c = lo;
+  }
+  const Desc& D = descs[c];
+  const int lb = gb - blkoff[c];
+  const int L = D.L, hx = L >> 1, half = D.half;
+  const Ctl* ctl = D.ctl;
+  const int pO = ctl->parity_o;
+  const int po = pO ^ (s & 1);          // parity of the sites that carry a^o_s
+  const int pn = po ^ 1;                // parity of the sites that carry a^v_s
+  const int o_half = ctl->o_half;
+  int sh[6];
+  T dr[6], di[6];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    sh[e] = FIRST ? ctl->start_half[1 + e] : 0;
+    dr[e] = FIRST ? (T)ctl->delta[2 * e] : (T)0;
+    di[e] = FIRST ? (T)ctl->delta[2 * e + 1] : (T)0;
+  }
+  const T c1 = FIRST ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
+  const GLOBAL spn<T>* sp = (const GLOBAL spn<T>*)D.spin;
+  GLOBAL cpx<T>* vo = (GLOBAL cpx<T>*)D.vec;               // o-slots [2][half]
+  GLOBAL cpx<T>* vv = (GLOBAL cpx<T>*)D.vec + D.N;         // v-slots [2][half]
+  const GLOBAL spn<T>* sp_o = sp + (size_t)po * half;
+  const GLOBAL spn<T>* sp_n = sp + (size_t)pn * half;
+  // a^v_0 at a site with half-row index hh on the parity of o's neighbours
+  auto v0 = [&](int hh) {
+    cpx<T> r = {(T)0, (T)0};
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+      if (hh == sh[e]) { r.x += dr[e]; r.y += di[e]; }
+    return r;
+  };
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const int h = (lb * PPT + p) * kStepThreads + (int)threadIdx.x;
+    if (h >= half) continue;
+    const int k = h % hx, r = h / hx, y = r % L, z = r / L;
+    const int xo = 2 * k + ((y + z + po) & 1);
+    const int xn = 2 * k + ((y + z + pn) & 1);
+    cpx<T> ao, av, aop;
+    {
+      const spn<T> si = ld(sp_o + h);
+      T ar = 0, ai = 0;
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        const int nh = nb_half(xo, y, z, d, L);
+        const spn<T> sj = ld(sp_n + nh);
+        T hr, hi_;
+        hop_spinor(si, sj, hr, hi_);
+        cpx<T> an;
+        if (FIRST) { an.x = (nh == o_half) ? (T)1 : (T)0; an.y = 0; }
+        else an = ld(vo + (size_t)pn * half + nh);
+        ar += hr * an.x - hi_ * an.y;
+        ai += hr * an.y + hi_ * an.x;
+      }
+      ao.x = c1 * ar;
+      ao.y = c1 * ai;
+      if (!FIRST) {
+        const cpx<T> pr = ld(vo + (size_t)po * half + h);
+        ao.x -= pr.x;
+        ao.y -= pr.y;
+      }
+      st(vo + (size_t)po * half + h, ao);
+    }
+    {
+      const spn<T> si = ld(sp_n + h);
+      T ar = 0, ai = 0;
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        const int nh = nb_half(xn, y, z, d, L);
+        const spn<T> sj = ld(sp_o + nh);
+        T hr, hi_;
+        hop_spinor(si, sj, hr, hi_);
+        const cpx<T> an = FIRST ? v0(nh) : ld(vv + (size_t)po * half + nh);
+        ar += hr * an.x - hi_ * an.y;
+        ai += hr * an.y + hi_ * an.x;
+      }
+      av.x = c1 * ar;
+      av.y = c1 * ai;
+      if (!FIRST) {
+        const cpx<T> pr = ld(vv + (size_t)pn * half + h);
+        av.x -= pr.x;
+        av.y -= pr.y;
+      }
+      st(vv + (size_t)pn * half + h, av);
+      if (FIRST) {
+        aop.x = (h == o_half) ? (T)1 : (T)0;
+        aop.y = 0;
+        st(vo + (size_t)pn * half + h, aop);
+        st(vv + (size_t)po * half + h, v0(h));
+      } else {
+        aop = ld(vo + (size_t)pn * half + h);
+      }
+    }
+    const double aor = ao.x, aoi = ao.y, avr = av.x, avi = av.y, apr = aop.x, api = aop.y;
+    acc[0] += aor * aor + aoi * aoi;
+    acc[1] += avr * avr + avi * avi;
+    acc[2] += apr * avr + api * avi;
+    acc[3] += apr * avi - api * avr;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_xor(acc[v], off);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w][v] = acc[v];
+  __syncthreads();
+  if (threadIdx.x < kNP2) {
+    const int t = threadIdx.x;
+    D.part[((size_t)(s - 1) * D.nblk + lb) * kNP2 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  }
+}
+
+// grid (Smax, n), 64 threads: pair-form moments [M][3] (oo, vv, ov):
+//   mu^{oo}_{2s} = 2 P^{oo}_s - 1, mu^{vv}_{2s} = 2 P^{vv}_s - <v|v>,
+//   mu^{ov}_{2s-1} = 2 Q^{ov}_s - mu^{ov}_1, mu^{ov}_1 = Q^{ov}_1; the others vanish
+//   on the bipartite lattice (mu^{ov}_0 = <o|v> = 0).
+__global__ void k_moments_ov(const Desc* __restrict__ descs) {
+  const Desc& D = descs[blockIdx.y];
+  const int s = blockIdx.x + 1;
+  if (s > D.S) return;
+  __shared__ double P[6];
+  const int t = threadIdx.x;
+  if (t < 4 || (t < 6 && s > 1)) {
+    const int step = (t < 4) ? s - 1 : 0;
+    const int q = (t < 4) ? t : t - 2;
+    const double* src = D.part + (size_t)step * D.nblk * kNP2 + q;
+    double sum = 0.0, comp = 0.0;
+    for (int b = 0; b < D.nblk; ++b) {
+      const double v = src[(size_t)b * kNP2];
+      const double tt = sum + v;
+      comp += (fabs(sum) >= fabs(v)) ? (sum - tt) + v : (v - tt) + sum;
+      sum = tt;
+    }
+    P[t] = sum + comp;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  const Ctl* ctl = D.ctl;
+  double vv0 = 0.0;   // <v|v> = sum_{de} conj(delta_d) delta_e [n_d == n_e]
+  for (int d = 0; d < 6; ++d)
+    for (int e = 0; e < 6; ++e)
+      if (ctl->start_site[1 + d] == ctl->start_site[1 + e])
+        vv0 += ctl->delta[2 * d] * ctl->delta[2 * e] + ctl->delta[2 * d + 1] * ctl->delta[2 * e + 1];
+  double* mom = D.mom;
+  auto put = [&](int n, int q, double re, double im) {
+    mom[((size_t)n * 3 + q) * 2] = re;
+    mom[((size_t)n * 3 + q) * 2 + 1] = im;
+  };
+  const double q1r = (s == 1) ? P[2] : P[4], q1i = (s == 1) ? P[3] : P[5];
+  if (s == 1) {
+    put(0, 0, 1.0, 0.0);
+    put(0, 1, vv0, 0.0);
+    put(0, 2, 0.0, 0.0);
+  }
+  put(2 * s - 1, 0, 0.0, 0.0);
+  put(2 * s - 1, 1, 0.0, 0.0);
+  if (s == 1) put(1, 2, q1r, q1i);
+  else put(2 * s - 1, 2, 2.0 * P[2] - q1r, 2.0 * P[3] - q1i);
+  if (2 * s < D.M) {
+    put(2 * s, 0, 2.0 * P[0] - 1.0, 0.0);
+    put(2 * s, 1, 2.0 * P[1] - vv0, 0.0);
+    put(2 * s, 2, 0.0, 0.0);
+  }
+}
+
 // Index of P^{de} (d <= e) in the packed 49-value block partial.
 __device__ inline int pidx(int d, int e) {
   int idx = 1;
@@ -585,8 +774,12 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
     for (int m = tid; m < K; m += kReconThreads) {
       double val = 0.0;
       if (m < M) {
-        const double2* mm = mom + (size_t)m * 49;
         double x;
+        if (D.vectors == GFMC_VECTORS_OV) {
+          const double2* m3 = mom + (size_t)m * 3;
+          x = (q == 0) ? m3[0].x : (q == 1) ? m3[1].x : (q == 2) ? m3[2].x : m3[2].y;
+        } else {
+        const double2* mm = mom + (size_t)m * 49;
         if (q == 0) {
           x = mm[0].x;
         } else if (q == 1) {
@@ -609,6 +802,7 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
             si += dl[2 * e] * me.y + dl[2 * e + 1] * me.x;
           }
           x = (q == 2) ? sr : si;
+        }
         }
         double g;
         if (D.kernel == GFMC_LORENTZ) {
@@ -835,28 +1029,31 @@ hipError_t launch_propose(const Desc* d, int n, hipStream_t st) {
 }
 
 template <typename T, int PPT>
-hipError_t launch_step_t(const Desc* d, const int* blkoff, int nact, int blocks, int s,
+hipError_t launch_step_t(int ov, const Desc* d, const int* blkoff, int nact, int blocks, int s,
                          hipStream_t st) {
-  if (s == 1)
-    hipLaunchKernelGGL((k_step<T, true, PPT>), dim3(blocks), dim3(kStepThreads), 0, st, d,
-                       blkoff, nact, s);
-  else
-    hipLaunchKernelGGL((k_step<T, false, PPT>), dim3(blocks), dim3(kStepThreads), 0, st, d,
-                       blkoff, nact, s);
+  const dim3 g(blocks), b(kStepThreads);
+  if (ov) {
+    if (s == 1) hipLaunchKernelGGL((k_step_ov<T, true, PPT>), g, b, 0, st, d, blkoff, nact, s);
+    else hipLaunchKernelGGL((k_step_ov<T, false, PPT>), g, b, 0, st, d, blkoff, nact, s);
+  } else {
+    if (s == 1) hipLaunchKernelGGL((k_step<T, true, PPT>), g, b, 0, st, d, blkoff, nact, s);
+    else hipLaunchKernelGGL((k_step<T, false, PPT>), g, b, 0, st, d, blkoff, nact, s);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_step(int fp32, int ppt, const Desc* d, const int* blkoff, int nact, int blocks,
-                       int s, hipStream_t st) {
+hipError_t launch_step(int fp32, int ov, int ppt, const Desc* d, const int* blkoff, int nact,
+                       int blocks, int s, hipStream_t st) {
   if (fp32)
-    return ppt == 2 ? launch_step_t<float, 2>(d, blkoff, nact, blocks, s, st)
-                    : launch_step_t<float, 1>(d, blkoff, nact, blocks, s, st);
-  return ppt == 2 ? launch_step_t<double, 2>(d, blkoff, nact, blocks, s, st)
-                  : launch_step_t<double, 1>(d, blkoff, nact, blocks, s, st);
+    return ppt == 2 ? launch_step_t<float, 2>(ov, d, blkoff, nact, blocks, s, st)
+                    : launch_step_t<float, 1>(ov, d, blkoff, nact, blocks, s, st);
+  return ppt == 2 ? launch_step_t<double, 2>(ov, d, blkoff, nact, blocks, s, st)
+                  : launch_step_t<double, 1>(ov, d, blkoff, nact, blocks, s, st);
 }
 
-hipError_t launch_moments(const Desc* d, int n, int smax, hipStream_t st) {
-  hipLaunchKernelGGL(k_moments, dim3(smax, n), dim3(64), 0, st, d);
+hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st) {
+  if (ov) hipLaunchKernelGGL(k_moments_ov, dim3(smax, n), dim3(64), 0, st, d);
+  else hipLaunchKernelGGL(k_moments, dim3(smax, n), dim3(64), 0, st, d);
   return hipGetLastError();
 }
 

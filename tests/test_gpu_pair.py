@@ -1,0 +1,106 @@
+"""GPU parity of the pair form {|o>, |v> = Delta|o>} against the oracle.
+
+The oracle has one definition of the local moments (7 unit start vectors);
+the pair form must reproduce its contracted series <o|T_n|o>, <v|T_n|v>,
+<o|T_n|v> and the same Delta S_eff.  Tolerances as for the 7-vector form, with
+the moments of |v> taken relative to <v|v>.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1303_6016_amd as g
+    g.lib()
+    return g
+
+
+def pair(g, L, M, prec, **kw):
+    ch = g.Chain(g.Params(L=L, M=M, precision=prec, vectors=g.VECTORS_OV, **kw))
+    m = oracle.Model(L=L, M=M, **{k: v for k, v in kw.items()
+                                  if k in ("beta", "seed", "chain_id", "K")})
+    return ch, m
+
+
+@pytest.mark.parametrize("L,M", [(2, 32), (4, 256), (8, 256)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+def test_pair_moments_match_contracted_oracle(g, L, M, prec, tol):
+    ch, m = pair(g, L, M, prec)
+    th, ph = synth.random_angles(m.N, L + 3)
+    ch.set_spins(th, ph)
+    rng = np.random.default_rng(L)
+    for _ in range(2):
+        o = int(rng.integers(m.N))
+        tn, pn = float(np.arccos(rng.uniform(-1, 1))), float(rng.uniform(0, 2 * np.pi))
+        got = ch.pair_moments(o, tn, pn)
+        ref = oracle.contract(oracle.moments(m, th, ph, o), oracle.deltas(m, th, ph, o, tn, pn))
+        vv0 = ref[3, 0].real
+        e_oo = np.abs(got[:, 0] - ref[0]).max()
+        e_vv = np.abs(got[:, 1] - ref[3]).max() / max(1.0, vv0)
+        e_ov = np.abs(got[:, 2] - ref[1]).max() / max(1.0, math.sqrt(vv0))
+        print(f"L={L} M={M} prec={prec} site={o}: oo {e_oo:.1e} vv {e_vv:.1e} ov {e_ov:.1e}",
+              flush=True)
+        assert max(e_oo, e_vv, e_ov) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
+def test_pair_delta_seff(g, prec, tol):
+    ch, m = pair(g, 8, 512, prec, beta=20.0)
+    th, ph = synth.random_angles(m.N, 5)
+    ch.set_spins(th, ph)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        o = int(rng.integers(m.N))
+        tn, pn = float(np.arccos(rng.uniform(-1, 1))), float(rng.uniform(0, 2 * np.pi))
+        got = ch.delta_seff(o, tn, pn)
+        ref = oracle.delta_seff(m, th, ph, o, tn, pn)
+        print(f"pair prec={prec} dS={ref:.6f} err={got - ref:.2e}", flush=True)
+        assert abs(got - ref) < tol
+    assert ch.delta_seff(7, th[7], ph[7]) == 0.0
+
+
+def test_pair_trajectory_4cubed(g):
+    ch, m = pair(g, 4, 256, 0, beta=20.0, seed=2)
+    th, ph = oracle.init_spins(m, 0)
+    ch.set_spins(th, ph)
+    for idx in range(2 * m.N):
+        ro = oracle.step(m, th, ph, idx)
+        rg = ch.step(force=ro.accepted)
+        assert rg.site == ro.site and rg.u == ro.u
+        assert abs(rg.dseff - ro.dseff) < 1e-10
+        if rg.own != ro.own:
+            assert abs(math.log(ro.u) + ro.dseff) < 1e-9
+    gth, gph = ch.get_spins()
+    assert np.abs(gth - th).max() < 1e-13 and np.abs(gph - ph).max() < 1e-13
+
+
+def test_pair_batch_alone_vs_mix(g):
+    specs = [(4, 256), (6, 128), (8, 64)]
+
+    def build():
+        out = []
+        for i, (L, M) in enumerate(specs):
+            ch = g.Chain(g.Params(L=L, M=M, precision=1, vectors=g.VECTORS_OV, seed=9,
+                                  chain_id=i, beta=10.0))
+            ch.init_spins(g.INIT_RANDOM)
+            out.append(ch)
+        return out
+    alone = [[ch.step() for _ in range(4)] for ch in build()]
+    b = g.Batch(build())
+    recs = b.step(4, records=True)
+    b.close()
+    for q in range(4):
+        for i in range(len(specs)):
+            r, a = recs[q][i], alone[i][q]
+            assert (r.site, r.accepted, r.dseff) == (a.site, a.accepted, a.dseff)
