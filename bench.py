@@ -36,6 +36,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-single", action="store_true")
     ap.add_argument("--graph", type=int, default=0, help="replay one proposal as a HIP graph")
+    ap.add_argument("--pair", type=int, default=1,
+                    help="also time the {o, v} start-vector form on the same workload")
+    ap.add_argument("--serving", type=float, default=0.0,
+                    help="run the serving engine for this many seconds of Poisson arrivals")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -59,6 +63,59 @@ def cpu_baseline(n_prop: int = 2):
             "mc_spin_updates_per_s": n_prop / dt}
 
 
+def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
+    """Continuous-batching serving run: Poisson arrivals (rate per second,
+    seeded) of chains with L in {4, 6, 8}, M = 64 L (K the next power of two),
+    T uniform in [0.02, 0.2], FP32 recursion, 2 sweeps each; arrivals stop
+    after `seconds`, then the engine drains.  Reports per-sweep latency
+    percentiles overall and per L, queueing delay and throughput."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    eng = g.Engine(0, hbm_budget_bytes=16 << 30, max_slots=64)
+    t0 = time.perf_counter()
+    t_next, k, meta = rng.exponential(1.0 / rate), 0, {}
+    while True:
+        now = time.perf_counter() - t0
+        if now >= seconds:
+            break
+        if now >= t_next:
+            Lk = int(rng.choice([4, 6, 8]))
+            Mk = 64 * Lk
+            Kk = 1 << (Mk - 1).bit_length()
+            T = float(rng.uniform(0.02, 0.2))
+            rid = eng.submit(g.Params(L=Lk, M=Mk, K=Kk, beta=1.0 / T, precision=g.FP32_ACC64,
+                                      seed=seed, chain_id=k), init=g.INIT_RANDOM, nsweeps=2)
+            meta[rid] = Lk
+            k += 1
+            t_next += rng.exponential(1.0 / rate)
+        else:
+            time.sleep(min(0.01, t_next - now))
+    eng.drain(1800)
+    wall = time.perf_counter() - t0
+    res = eng.poll(1 << 16)
+    lat, ids = eng.sweep_latencies()
+    eng.close()
+    props = sum(r.proposals for r in res)
+    svu = sum(r.proposals * (r.L ** 3) * 7 * (r.M // 2) for r in res)
+    per_L = {}
+    for Lk in (4, 6, 8):
+        sel = np.array([meta.get(int(i)) == Lk for i in ids], dtype=bool)
+        if sel.any():
+            per_L[str(Lk)] = {"p50_s": float(np.percentile(lat[sel], 50)),
+                              "p99_s": float(np.percentile(lat[sel], 99)), "sweeps": int(sel.sum())}
+    wait = np.array([r.t_admit - r.t_submit for r in res])
+    print(json.dumps({
+        "mode": "serving", "requests": k, "completed": sum(r.status == 0 for r in res),
+        "arrival_rate_per_s": rate, "arrival_window_s": seconds, "wall_s": wall,
+        "sweep_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                            "per_L": per_L, "sweeps": int(len(lat))},
+        "queue_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+        "mc_spin_updates_per_s": props / wall, "svu_per_s": svu / wall,
+        "config": {"workload": "Poisson arrivals, L in {4,6,8}, M = 64 L, T ~ U[0.02, 0.2], "
+                               "FP32 recursion, 2 sweeps per request, 16 GiB budget, 64 slots"}}),
+        flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -78,6 +135,9 @@ def main():
         return
     import paper_1303_6016_amd as g
     import synth
+    if args.serving > 0:
+        serving(g, args.serving)
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -147,6 +207,45 @@ def main():
         "wall_s": wall,
         "roofline": roof,
     }
+
+    if args.pair:
+        # the same workload with the {o, v} start-vector pair (2 vectors per proposal)
+        pch = []
+        for c in range(NCHAIN):
+            p = g.Params(L=L, M=M, beta=1.0 / temps[c], mu=0.0, precision=g.FP32_ACC64,
+                         seed=SEED, chain_id=c, vectors=g.VECTORS_OV)
+            ch = g.Chain(p, device=dev)
+            ch.init_spins(g.INIT_RANDOM)
+            pch.append(ch)
+        pb = g.Batch(pch)
+        pppt = pb.autotune(16)
+        pb.step(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        nps = max(4, args.steps // 2)
+        ms_tot, nl_tot = 0.0, 0
+        e0.record(pb.stream)
+        for _ in range(nps):
+            pb.step(1)
+            ms, nl = pb.step_timing()
+            ms_tot += ms
+            nl_tot += nl
+        e1.record(pb.stream)
+        torch.cuda.synchronize()
+        dt = e0.elapsed_time(e1) / 1e3
+        pbytes, _ = pch[0].step_bytes()
+        pavg = ms_tot / 1e3 / max(nl_tot, 1)
+        out["pair_form"] = {
+            "mc_spin_updates_per_s": nps * NCHAIN / dt,
+            "svu_per_s": nps * NCHAIN * N * 2 * (M // 2) / dt,
+            "ms_per_step": 1e3 * dt / nps, "pairs_per_thread": pppt,
+            "roofline": {"bound": "hbm", "achieved": NCHAIN * pbytes / pavg / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": NCHAIN * pbytes / pavg / 1e9 / HBM_PEAK_GBS,
+                         "kernel": "k_step_ov<float>", "avg_launch_us": pavg * 1e6,
+                         "bytes_per_launch": NCHAIN * pbytes}}
+        pb.close()
+        del pch
 
     if not args.no_fp64_single:
         p = g.Params(L=L, M=M, beta=1.0 / T_LO, precision=g.FP64, seed=SEED, chain_id=0)
