@@ -205,6 +205,21 @@ def main():
             "kernel": "k_step<float>", "avg_launch_us": avg_launch_s * 1e6,
             "bytes_per_launch": bytes_per_launch}
 
+    # measured copy bandwidth on this machine (1 GiB device copy, read + write)
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+    roof["measured_copy_GBs"] = copy_gbs
+    roof["frac_of_measured_copy"] = achieved / copy_gbs
+
     out = {
         "metric": "Chebyshev site-vector updates/s + MC spin updates/s at 32^3; p50/p99 sweep latency",
         "value": value, "unit": "svu/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
