@@ -83,6 +83,7 @@ Layout layout_of(const Derived& d) {
   l.part = take((size_t)d.S * d.nblk * (d.ov ? kNP2 : kNP) * 8);
   l.mom = take((size_t)d.M * (d.ov ? 3 : 49) * 16);
   l.gscr = take((size_t)4 * d.K * 16);
+  l.tab = take(((size_t)d.M + 2 * (size_t)d.K + (size_t)d.K + 2 * (size_t)d.K) * 8);
   l.total = o;
   return l;
 }
@@ -102,6 +103,7 @@ void fill_desc(gfmc_chain* c) {
   D.part = (double*)(c->ws + c->l.part);
   D.mom = (double*)(c->ws + c->l.mom);
   D.gscr = (double*)(c->ws + c->l.gscr);
+  D.tab = (double*)(c->ws + c->l.tab);
   D.ctl = (Ctl*)(c->ws + c->l.ctl);
 }
 
@@ -243,6 +245,7 @@ gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived
   HIPCHK(hipMemsetAsync(c->desc.theta, 0, (size_t)d.N * 8, c->stream));
   HIPCHK(hipMemsetAsync(c->desc.phi, 0, (size_t)d.N * 8, c->stream));
   HIPCHK(launch_spinors(d.fp32, P.d_desc, 1, d.N, c->stream));
+  HIPCHK(launch_tables(P.d_desc, d.K, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return GFMC_OK;
 }
@@ -324,7 +327,10 @@ gfmc_status gfmc_set_params(gfmc_chain* c, double t, double beta, double mu) {
   c->p = p;
   c->d = d;
   fill_desc(c);
-  return upload_plan(c->plan, {c});
+  CHK(upload_plan(c->plan, {c}));
+  HIPCHK(launch_tables(c->plan.d_desc, d.K, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return GFMC_OK;
 }
 
 gfmc_status gfmc_init_spins(gfmc_chain* c, gfmc_init mode, double frac) {

@@ -56,6 +56,8 @@ struct Desc {
   double* part;             // [S][nblk][kNP] ({o,v}: [S][nblk][kNP2])
   double* mom;              // [M][7][7][2]  ({o,v}: [M][3][2])
   double* gscr;             // [4][K][2]
+  double* tab;              // per-chain constant tables of the reconstruction:
+                            // g[M], pre[K][2], tw[K/2][2], sinth[K], wt[K]
   Ctl* ctl;
 };
 

@@ -19,6 +19,7 @@ hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t 
 hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st);
 hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st);
 hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t st);
+hipError_t launch_tables(const Desc* d, int kmax, hipStream_t st);
 }  // namespace gfmc
 
 using namespace gfmc;
@@ -47,7 +48,7 @@ struct Derived {
 };
 
 struct Layout {
-  size_t desc, blkoff, force, rec, mag, ctl, theta, phi, spin, vec, part, mom, gscr, total;
+  size_t desc, blkoff, force, rec, mag, ctl, theta, phi, spin, vec, part, mom, gscr, tab, total;
 };
 
 // A launch plan: a device table of chain descriptors (sorted by number of

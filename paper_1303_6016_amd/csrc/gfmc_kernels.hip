@@ -667,32 +667,56 @@ __device__ inline int pidx(int d, int e) {
 }
 
 // ------------------------------------------------------------- moments ---
-// grid (Smax, n), 64 threads: sums the block partials of step s with
-// Neumaier compensation and writes mu_{2s-1}, mu_{2s} (and mu_0 for s = 1):
+// Neumaier-compensated sum helper: (sum, comp) += v.
+__device__ inline void nsum(double& sum, double& comp, double v) {
+  const double tt = sum + v;
+  comp += (fabs(sum) >= fabs(v)) ? (sum - tt) + v : (v - tt) + sum;
+  sum = tt;
+}
+
+// grid (Smax, n), 256 threads: sums the block partials of step s with
+// Neumaier compensation (4 thread groups per value, combined in a fixed
+// order) and writes mu_{2s-1}, mu_{2s} (and mu_0 for s = 1):
 //   mu_{2s}   = 2 P_s - mu_0,  mu_{2s-1} = 2 Q_s - mu_1  (s >= 2),
 //   mu_1 = Q_1, mu_0^{jk} = [site_j == site_k];
 // pairs that vanish on the bipartite lattice are written as exact zeros and
 // the lower triangle follows from Hermiticity.
-__global__ void k_moments(const Desc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void k_moments(const Desc* __restrict__ descs) {
   const Desc& D = descs[blockIdx.y];
   const int s = blockIdx.x + 1;
   if (s > D.S) return;
   __shared__ double P[kNP];
   __shared__ double Q1[12];
-  const int t = threadIdx.x;
+  __shared__ double gs[4][64], gc[4][64];
+  const int t = threadIdx.x, col = t & 63, grp = t >> 6;
   const int nblk = D.nblk;
-  if (t < kNP || (t < kNP + 12 && s > 1)) {
-    const int step = (t < kNP) ? s - 1 : 0;
-    const int p = (t < kNP) ? t : 37 + (t - kNP);
+  double sum = 0.0, comp = 0.0;
+  if (col < kNP || (col < kNP + 12 && s > 1)) {
+    const int step = (col < kNP) ? s - 1 : 0;
+    const int p = (col < kNP) ? col : 37 + (col - kNP);
     const double* src = D.part + (size_t)step * nblk * kNP + p;
-    double sum = 0.0, comp = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-      const double v = src[(size_t)b * kNP];
-      const double tt = sum + v;
-      comp += (fabs(sum) >= fabs(v)) ? (sum - tt) + v : (v - tt) + sum;
-      sum = tt;
+    int b = grp;
+    for (; b + 12 < nblk; b += 16) {
+      const double v0 = src[(size_t)b * kNP], v1 = src[(size_t)(b + 4) * kNP];
+      const double v2 = src[(size_t)(b + 8) * kNP], v3 = src[(size_t)(b + 12) * kNP];
+      nsum(sum, comp, v0);
+      nsum(sum, comp, v1);
+      nsum(sum, comp, v2);
+      nsum(sum, comp, v3);
     }
-    if (t < kNP) P[t] = sum + comp; else Q1[t - kNP] = sum + comp;
+    for (; b < nblk; b += 4) nsum(sum, comp, src[(size_t)b * kNP]);
+  }
+  gs[grp][col] = sum;
+  gc[grp][col] = comp;
+  __syncthreads();
+  if (t < 64) {
+    double S = 0.0, C = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      nsum(S, C, gs[q][t]);
+      C += gc[q][t];
+    }
+    if (t < kNP) P[t] = S + C;
+    else if (t < kNP + 12) Q1[t - kNP] = S + C;
   }
   __syncthreads();
   if (t >= 49) return;
@@ -749,6 +773,52 @@ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Constant tables of the reconstruction of one chain (depend on M, K, the
+// damping kernel, beta, mu and a only): damping g_n (Jackson, or Lorentz
+// sinh(lambda(1 - n/M))/sinh(lambda)); pre-twiddles exp(-i pi m / 2K) of
+// equation "mu_to_mu_tilde"; FFT twiddles exp(-2 pi i j / K); node sines
+// sin th_k; quadrature weights (beta a / K) f(a w_k + b) sin th_k of
+// equation "d_seff2" with w_k = cos th_k, th_k = pi (k + 1/2) / K.
+__global__ void k_tables(const Desc* __restrict__ descs) {
+  const Desc& D = descs[0];
+  const int M = D.M, K = D.K;
+  double* g = D.tab;
+  double* pre = g + M;
+  double* tw = pre + 2 * (size_t)K;
+  double* sth = tw + (size_t)K;
+  double* wt = sth + K;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) {
+    if (D.kernel == GFMC_LORENTZ) {
+      g[i] = sinh(D.lambda * (1.0 - (double)i / M)) / sinh(D.lambda);
+    } else {
+      const double qn = (double)i / (M + 1.0);
+      g[i] = ((M - i + 1.0) * cospi(qn) + sinpi(qn) * cospi(1.0 / (M + 1.0)) /
+                                             sinpi(1.0 / (M + 1.0))) / (M + 1.0);
+    }
+  }
+  if (i < K) {
+    double sn, cs;
+    sincospi(-(double)i / (2.0 * K), &sn, &cs);
+    pre[2 * i] = cs;
+    pre[2 * i + 1] = sn;
+    const double st = sinpi((i + 0.5) / K);
+    sth[i] = st;
+    const double e = D.a * cospi((i + 0.5) / K);
+    const double xx = D.beta * (e - D.mu);
+    double f;
+    if (xx > 0) { const double qq = exp(-xx); f = qq / (1.0 + qq); }
+    else f = 1.0 / (1.0 + exp(xx));
+    wt[i] = D.beta * D.a / K * f * st;
+  }
+  if (i < K / 2) {
+    double sn, cs;
+    sincospi(-2.0 * i / K, &sn, &cs);
+    tw[2 * i] = cs;
+    tw[2 * i + 1] = sn;
+  }
+}
+
 // One block per chain.  mode 0: proposal from the counter (Metropolis,
 // update, counter advance); mode 1/2: evaluation only.
 __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict__ descs,
@@ -767,6 +837,11 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
   for (int i = 0; i < 12; ++i) dl[i] = ctl->delta[i];
   const double2* __restrict__ mom = (const double2*)D.mom;   // [M][7][7]
   double2* __restrict__ gs = (double2*)D.gscr;                // [4][K]
+  const double* __restrict__ gtab = D.tab;                    // g[M]
+  const double2* __restrict__ pre = (const double2*)(gtab + M);
+  const double2* __restrict__ tw = pre + K;                   // [K/2]
+  const double* __restrict__ sth = (const double*)(tw + K / 2);
+  const double* __restrict__ wt = sth + K;
 
   // Four real series: 0 mu^{oo}, 1 mu^{vv}, 2 Re mu^{ov}, 3 Im mu^{ov};
   // mu^{vo} = conj(mu^{ov}) (Hermitian moments), so G_vo uses the same series.
@@ -804,20 +879,11 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
           x = (q == 2) ? sr : si;
         }
         }
-        double g;
-        if (D.kernel == GFMC_LORENTZ) {
-          g = sinh(D.lambda * (1.0 - (double)m / M)) / sinh(D.lambda);
-        } else {
-          const double qn = (double)m / (M + 1.0);
-          g = ((M - m + 1.0) * cospi(qn) + sinpi(qn) * cospi(1.0 / (M + 1.0)) /
-                                               sinpi(1.0 / (M + 1.0))) / (M + 1.0);
-        }
-        val = g * x;
+        val = gtab[m] * x;
         if (m == 0) val *= 0.5;
       }
-      double sn, cs;   // c_m = mu'_m exp(-i pi m / (2K))
-      sincospi(-(double)m / (2.0 * K), &sn, &cs);
-      buf[bitrev(m, lg)] = make_double2(val * cs, val * sn);
+      const double2 pm = pre[m];   // c_m = mu'_m exp(-i pi m / (2K))
+      buf[bitrev(m, lg)] = make_double2(val * pm.x, val * pm.y);
     }
     __syncthreads();
     // radix-2 decimation-in-time FFT, gamma_n = sum_m c_m exp(-2 pi i m n / K)
@@ -825,10 +891,8 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
       const int hl = len >> 1;
       for (int b = tid; b < (K >> 1); b += kReconThreads) {
         const int j = b % hl, base = (b / hl) * len;
-        double sn, cs;
-        sincospi(-2.0 * j / len, &sn, &cs);
         const double2 u = buf[base + j];
-        const double2 t = cmul(buf[base + j + hl], make_double2(cs, sn));
+        const double2 t = cmul(buf[base + j + hl], tw[j * (K / len)]);
         buf[base + j] = make_double2(u.x + t.x, u.y + t.y);
         buf[base + j + hl] = make_double2(u.x - t.x, u.y - t.y);
       }
@@ -842,7 +906,7 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
         chi = buf[K - j - 1];
         chi.y = -chi.y;
       }
-      const double st = sinpi((k + 0.5) / K);
+      const double st = sth[k];
       gs[(size_t)q * K + k] = make_double2(-2.0 * chi.y / st, 2.0 * chi.x / st);
     }
     __syncthreads();
@@ -884,13 +948,7 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
   double phi = tot[tid], part = 0.0, ptop = 0.0;
   for (int k = k1 - 1; k >= k0; --k) {
     phi += inc(k);
-    const double sth = sinpi((k + 0.5) / K);
-    const double e = a * cospi((k + 0.5) / K);
-    const double xx = D.beta * (e - D.mu);
-    double f;
-    if (xx > 0) { const double qq = exp(-xx); f = qq / (1.0 + qq); }
-    else f = 1.0 / (1.0 + exp(xx));
-    part += f * sth * phi;
+    part += wt[k] * phi;
     if (k == 0) ptop = phi;
   }
   red[tid] = part;
@@ -900,7 +958,7 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
     __syncthreads();
   }
   if (tid == 0) {
-    const double ds = D.beta * a / K * red[0];
+    const double ds = red[0];
     ctl->dseff = ds;
     ctl->phase_top = ptop;
     if (ctl->mode == 0) {
@@ -1053,7 +1111,7 @@ hipError_t launch_step(int fp32, int ov, int ppt, const Desc* d, const int* blko
 
 hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st) {
   if (ov) hipLaunchKernelGGL(k_moments_ov, dim3(smax, n), dim3(64), 0, st, d);
-  else hipLaunchKernelGGL(k_moments, dim3(smax, n), dim3(64), 0, st, d);
+  else hipLaunchKernelGGL(k_moments, dim3(smax, n), dim3(256), 0, st, d);
   return hipGetLastError();
 }
 
@@ -1098,4 +1156,11 @@ hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t s
   return hipGetLastError();
 }
 
+}  // namespace gfmc
+
+namespace gfmc {
+hipError_t launch_tables(const Desc* d, int kmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_tables, dim3((kmax + 255) / 256), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
 }  // namespace gfmc
