@@ -466,7 +466,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
       val = (q & 1) ? G(12, 2 * e + 1) - G(13, 2 * e) : G(12, 2 * e) + G(13, 2 * e + 1);
     }
 #undef G
-    D.part[((size_t)(s - 1) * D.nblk + lb) * kNP + t] = val;
+    D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = val;
   }
 }
 
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
   __syncthreads();
   if (threadIdx.x < kNP2) {
     const int t = threadIdx.x;
-    D.part[((size_t)(s - 1) * D.nblk + lb) * kNP2 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    D.part[((size_t)(s - 1) * kNP2 + t) * D.nblk + lb] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
   }
 }
 
@@ -610,27 +610,18 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
 //   mu^{oo}_{2s} = 2 P^{oo}_s - 1, mu^{vv}_{2s} = 2 P^{vv}_s - <v|v>,
 //   mu^{ov}_{2s-1} = 2 Q^{ov}_s - mu^{ov}_1, mu^{ov}_1 = Q^{ov}_1; the others vanish
 //   on the bipartite lattice (mu^{ov}_0 = <o|v> = 0).
-__global__ void k_moments_ov(const Desc* __restrict__ descs) {
+__global__ __launch_bounds__(256) void k_moments_ov(const Desc* __restrict__ descs) {
   const Desc& D = descs[blockIdx.y];
-  const int s = blockIdx.x + 1;
-  if (s > D.S) return;
-  __shared__ double P[6];
-  const int t = threadIdx.x;
-  if (t < 4 || (t < 6 && s > 1)) {
-    const int step = (t < 4) ? s - 1 : 0;
-    const int q = (t < 4) ? t : t - 2;
-    const double* src = D.part + (size_t)step * D.nblk * kNP2 + q;
-    double sum = 0.0, comp = 0.0;
-    for (int b = 0; b < D.nblk; ++b) {
-      const double v = src[(size_t)b * kNP2];
-      const double tt = sum + v;
-      comp += (fabs(sum) >= fabs(v)) ? (sum - tt) + v : (v - tt) + sum;
-      sum = tt;
-    }
-    P[t] = sum + comp;
+  __shared__ double PP[32][6];
+  const int t = threadIdx.x, col = t & 7, sl = t >> 3;
+  const int s = blockIdx.x * 32 + sl + 1;
+  if (s <= D.S) {
+    if (col < 4) PP[sl][col] = sum_run(D.part + ((size_t)(s - 1) * kNP2 + col) * D.nblk, D.nblk);
+    else if (col < 6 && s > 1) PP[sl][col] = sum_run(D.part + (size_t)(col - 2) * D.nblk, D.nblk);
   }
   __syncthreads();
-  if (t != 0) return;
+  if (s > D.S || col != 0) return;
+  const double* P = PP[sl];
   const Ctl* ctl = D.ctl;
   double vv0 = 0.0;   // <v|v> = sum_{de} conj(delta_d) delta_e [n_d == n_e]
   for (int d = 0; d < 6; ++d)
@@ -674,53 +665,55 @@ __device__ inline void nsum(double& sum, double& comp, double v) {
   sum = tt;
 }
 
-// grid (Smax, n), 256 threads: sums the block partials of step s with
-// Neumaier compensation (4 thread groups per value, combined in a fixed
-// order) and writes mu_{2s-1}, mu_{2s} (and mu_0 for s = 1):
+// Sum of one contiguous run of block partials, in block order, with
+// Neumaier compensation (two-double loads, eight in flight).
+__device__ inline double sum_run(const double* __restrict__ src, int n) {
+  double sum = 0.0, comp = 0.0;
+  int b = 0;
+  if ((((uintptr_t)src) & 15) == 0) {
+    const double2* s2 = (const double2*)src;
+    for (; b + 16 <= n; b += 16) {
+      double2 v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = s2[(b >> 1) + i];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        nsum(sum, comp, v[i].x);
+        nsum(sum, comp, v[i].y);
+      }
+    }
+  }
+  for (; b < n; ++b) nsum(sum, comp, src[b]);
+  return sum + comp;
+}
+
+// grid (ceil(Smax/4), n), 256 threads = 4 steps x 64 columns: sums the block
+// partials of each step (layout [S][kNP][nblk], one contiguous run per value)
+// and writes mu_{2s-1}, mu_{2s} (and mu_0 for s = 1):
 //   mu_{2s}   = 2 P_s - mu_0,  mu_{2s-1} = 2 Q_s - mu_1  (s >= 2),
 //   mu_1 = Q_1, mu_0^{jk} = [site_j == site_k];
 // pairs that vanish on the bipartite lattice are written as exact zeros and
 // the lower triangle follows from Hermiticity.
 __global__ __launch_bounds__(256) void k_moments(const Desc* __restrict__ descs) {
   const Desc& D = descs[blockIdx.y];
-  const int s = blockIdx.x + 1;
-  if (s > D.S) return;
-  __shared__ double P[kNP];
-  __shared__ double Q1[12];
-  __shared__ double gs[4][64], gc[4][64];
-  const int t = threadIdx.x, col = t & 63, grp = t >> 6;
+  __shared__ double PP[4][kNP];
+  __shared__ double QQ[4][12];
+  const int t = threadIdx.x, col = t & 63, sl = t >> 6;
+  const int s = blockIdx.x * 4 + sl + 1;
   const int nblk = D.nblk;
-  double sum = 0.0, comp = 0.0;
-  if (col < kNP || (col < kNP + 12 && s > 1)) {
-    const int step = (col < kNP) ? s - 1 : 0;
-    const int p = (col < kNP) ? col : 37 + (col - kNP);
-    const double* src = D.part + (size_t)step * nblk * kNP + p;
-    int b = grp;
-    for (; b + 12 < nblk; b += 16) {
-      const double v0 = src[(size_t)b * kNP], v1 = src[(size_t)(b + 4) * kNP];
-      const double v2 = src[(size_t)(b + 8) * kNP], v3 = src[(size_t)(b + 12) * kNP];
-      nsum(sum, comp, v0);
-      nsum(sum, comp, v1);
-      nsum(sum, comp, v2);
-      nsum(sum, comp, v3);
+  if (s <= D.S) {
+    if (col < kNP) {
+      PP[sl][col] = sum_run(D.part + ((size_t)(s - 1) * kNP + col) * nblk, nblk);
+    } else if (col < kNP + 12 && s > 1) {
+      QQ[sl][col - kNP] = sum_run(D.part + ((size_t)(37 + col - kNP)) * nblk, nblk);
     }
-    for (; b < nblk; b += 4) nsum(sum, comp, src[(size_t)b * kNP]);
-  }
-  gs[grp][col] = sum;
-  gc[grp][col] = comp;
-  __syncthreads();
-  if (t < 64) {
-    double S = 0.0, C = 0.0;
-    for (int q = 0; q < 4; ++q) {
-      nsum(S, C, gs[q][t]);
-      C += gc[q][t];
-    }
-    if (t < kNP) P[t] = S + C;
-    else if (t < kNP + 12) Q1[t - kNP] = S + C;
   }
   __syncthreads();
-  if (t >= 49) return;
-  const int j = t / 7, k = t % 7;
+  if (s > D.S) return;
+  const double* P = PP[sl];
+  const double* Q1 = QQ[sl];
+  if (col >= 49) return;
+  const int j = col / 7, k = col % 7;
   const Ctl* ctl = D.ctl;
   const double d0 = (ctl->start_site[j] == ctl->start_site[k]) ? 1.0 : 0.0;
   double* mom = D.mom;
@@ -1110,8 +1103,8 @@ hipError_t launch_step(int fp32, int ov, int ppt, const Desc* d, const int* blko
 }
 
 hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st) {
-  if (ov) hipLaunchKernelGGL(k_moments_ov, dim3(smax, n), dim3(64), 0, st, d);
-  else hipLaunchKernelGGL(k_moments, dim3(smax, n), dim3(256), 0, st, d);
+  if (ov) hipLaunchKernelGGL(k_moments_ov, dim3((smax + 31) / 32, n), dim3(256), 0, st, d);
+  else hipLaunchKernelGGL(k_moments, dim3((smax + 3) / 4, n), dim3(256), 0, st, d);
   return hipGetLastError();
 }
 
