@@ -470,6 +470,35 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   }
 }
 
+// Neumaier-compensated sum helper: (sum, comp) += v.
+__device__ inline void nsum(double& sum, double& comp, double v) {
+  const double tt = sum + v;
+  comp += (fabs(sum) >= fabs(v)) ? (sum - tt) + v : (v - tt) + sum;
+  sum = tt;
+}
+
+// Sum of one contiguous run of block partials, in block order, with
+// Neumaier compensation (two-double loads, eight in flight).
+__device__ inline double sum_run(const double* __restrict__ src, int n) {
+  double sum = 0.0, comp = 0.0;
+  int b = 0;
+  if ((((uintptr_t)src) & 15) == 0) {
+    const double2* s2 = (const double2*)src;
+    for (; b + 16 <= n; b += 16) {
+      double2 v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = s2[(b >> 1) + i];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        nsum(sum, comp, v[i].x);
+        nsum(sum, comp, v[i].y);
+      }
+    }
+  }
+  for (; b < n; ++b) nsum(sum, comp, src[b]);
+  return sum + comp;
+}
+
 // The pair form {|o>, |v>}: |a^o_0> = |o>, |a^v_0> = |v> = sum_d delta_d |n_d>
 // (|v> = Delta|o>, Section 2.2).  Same bipartite storage as above with one
 // v-slot in place of the six n-slots: a^o_s lives on parity p(o)^(s&1), a^v_s
@@ -658,35 +687,6 @@ __device__ inline int pidx(int d, int e) {
 }
 
 // ------------------------------------------------------------- moments ---
-// Neumaier-compensated sum helper: (sum, comp) += v.
-__device__ inline void nsum(double& sum, double& comp, double v) {
-  const double tt = sum + v;
-  comp += (fabs(sum) >= fabs(v)) ? (sum - tt) + v : (v - tt) + sum;
-  sum = tt;
-}
-
-// Sum of one contiguous run of block partials, in block order, with
-// Neumaier compensation (two-double loads, eight in flight).
-__device__ inline double sum_run(const double* __restrict__ src, int n) {
-  double sum = 0.0, comp = 0.0;
-  int b = 0;
-  if ((((uintptr_t)src) & 15) == 0) {
-    const double2* s2 = (const double2*)src;
-    for (; b + 16 <= n; b += 16) {
-      double2 v[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = s2[(b >> 1) + i];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        nsum(sum, comp, v[i].x);
-        nsum(sum, comp, v[i].y);
-      }
-    }
-  }
-  for (; b < n; ++b) nsum(sum, comp, src[b]);
-  return sum + comp;
-}
-
 // grid (ceil(Smax/4), n), 256 threads = 4 steps x 64 columns: sums the block
 // partials of each step (layout [S][kNP][nblk], one contiguous run per value)
 // and writes mu_{2s-1}, mu_{2s} (and mu_0 for s = 1):
