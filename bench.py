@@ -31,8 +31,9 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE (one counter per run), each scaled by what the same counter reads
 # for a plain 1 GiB device copy (FETCH x 1.99996, WRITE x 1.0); valid only for
 # the kernel source they were taken with (sha256 below), else reported as null.
-TRAFFIC_KERNEL_SHA256 = "2cc1887e6a6ef9f661e7bd4230e035a2b19b209379dbf88992a89a1a44954260"
-TRAFFIC_BYTES = {("k_step<float>", 1): 211934067, ("k_step<float>", 2): 215635840}
+TRAFFIC_KERNEL_SHA256 = "fc0b2bd888bbdbf5798d0c720a439fdd129ee289c6955dde36dcf3fb1f1c40a6"
+TRAFFIC_BYTES = {("k_step<float>", 1): 211836389, ("k_step<float>", 2): 215917114,
+                 ("k_step_ov<float>", 1): 84112190, ("k_step_ov<float>", 2): 85392416}
 
 
 def parse():
@@ -272,6 +273,7 @@ def main():
             "roofline": {"bound": "hbm", "achieved": NCHAIN * pbytes / pavg / 1e9,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": NCHAIN * pbytes / pavg / 1e9 / HBM_PEAK_GBS,
+                         "traffic": traffic_bytes("k_step_ov<float>", pppt),
                          "kernel": "k_step_ov<float>", "avg_launch_us": pavg * 1e6,
                          "bytes_per_launch": NCHAIN * pbytes}}
         pb.close()
