@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--graph", type=int, default=0, help="replay one proposal as a HIP graph")
     ap.add_argument("--pair", type=int, default=1,
                     help="also time the {o, v} start-vector form on the same workload")
+    ap.add_argument("--stored-hops", type=int, default=1,
+                    help="also time the stored-hopping A/B variant of the step kernel")
     ap.add_argument("--serving", type=float, default=0.0,
                     help="run the serving engine for this many seconds of Poisson arrivals")
     ap.add_argument("--copy-probe", action="store_true",
@@ -278,6 +280,36 @@ def main():
                          "bytes_per_launch": NCHAIN * pbytes}}
         pb.close()
         del pch
+
+    if args.stored_hops:
+        # A/B: the same workload with stored hopping rows instead of recomputation
+        hch = []
+        for c in range(NCHAIN):
+            p = g.Params(L=L, M=M, beta=1.0 / temps[c], mu=0.0, precision=g.FP32_ACC64,
+                         seed=SEED, chain_id=c, hoppings=g.HOP_STORED)
+            ch = g.Chain(p, device=dev)
+            ch.init_spins(g.INIT_RANDOM)
+            hch.append(ch)
+        hb = g.Batch(hch)
+        hb.set_tuning(ppt)
+        hb.step(1)
+        torch.cuda.synchronize()
+        nps = max(2, args.steps // 4)
+        ms_tot, nl_tot = 0.0, 0
+        for _ in range(nps):
+            hb.step(1)
+            ms, nl = hb.step_timing()
+            ms_tot += ms
+            nl_tot += nl
+        hbytes, _ = hch[0].step_bytes()
+        havg = ms_tot / 1e3 / max(nl_tot, 1)
+        out["stored_hoppings_ab"] = {
+            "kernel": "k_step<float> with stored rows", "avg_launch_us": havg * 1e6,
+            "bytes_per_launch": NCHAIN * hbytes,
+            "achieved_GBs": NCHAIN * hbytes / havg / 1e9,
+            "slowdown_vs_recompute": havg / avg_launch_s}
+        hb.close()
+        del hch
 
     if not args.no_fp64_single:
         p = g.Params(L=L, M=M, beta=1.0 / T_LO, precision=g.FP64, seed=SEED, chain_id=0)

@@ -79,6 +79,12 @@ typedef enum { GFMC_INIT_RANDOM = 0, GFMC_INIT_FM = 1, GFMC_INIT_FM_PLUS_RANDOM 
  * series mu^{oo}, mu^{vv}, mu^{ov} that the 2x2 determinant needs; 2/7 of the
  * vector work per proposal). */
 typedef enum { GFMC_VECTORS_SITES = 0, GFMC_VECTORS_OV = 1 } gfmc_vectors;
+/* Hopping amplitudes in the Chebyshev step: recomputed from the per-site
+ * spinor cache (16 B/site FP32), or read from a stored table of 6 amplitudes
+ * per site (48 B/site FP32; the paper stores H in ELLPACK form).  Both give
+ * bit-identical results; the stored form exists as an A/B measurement of the
+ * matrix-free design and needs GFMC_VECTORS_SITES. */
+typedef enum { GFMC_HOP_RECOMPUTE = 0, GFMC_HOP_STORED = 1 } gfmc_hoppings;
 
 /* Parameters of one Markov chain (all energies in units of t). */
 typedef struct {
@@ -98,6 +104,7 @@ typedef struct {
   uint64_t seed;            /* Philox key word 0                                      */
   uint64_t chain_id;        /* Philox key word 1                                      */
   gfmc_vectors vectors;     /* start vectors (GFMC_VECTORS_SITES default)             */
+  gfmc_hoppings hoppings;   /* hopping amplitudes (GFMC_HOP_RECOMPUTE default)        */
 } gfmc_chain_params;
 
 /* Outcome of one proposal (Algorithm 1, inner loop body). */

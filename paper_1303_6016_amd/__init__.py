@@ -24,6 +24,7 @@ JACKSON, LORENTZ = 0, 1
 PROPOSE_SPHERE, PROPOSE_CONE = 0, 1
 INIT_RANDOM, INIT_FM, INIT_FM_PLUS_RANDOM = 0, 1, 2
 VECTORS_SITES, VECTORS_OV = 0, 1
+HOP_RECOMPUTE, HOP_STORED = 0, 1
 
 
 class GfmcError(RuntimeError):
@@ -40,7 +41,7 @@ class ChainParams(ctypes.Structure):
         ("scale_a", ctypes.c_double), ("scale_b", ctypes.c_double),
         ("precision", ctypes.c_int32), ("proposal", ctypes.c_int32),
         ("cone_angle", ctypes.c_double), ("seed", ctypes.c_uint64), ("chain_id", ctypes.c_uint64),
-        ("vectors", ctypes.c_int32),
+        ("vectors", ctypes.c_int32), ("hoppings", ctypes.c_int32),
     ]
 
 
@@ -157,12 +158,13 @@ class Params:
     seed: int = 0
     chain_id: int = 0
     vectors: int = VECTORS_SITES
+    hoppings: int = HOP_RECOMPUTE
 
     def c(self) -> ChainParams:
         return ChainParams(self.L, self.t, self.beta, self.mu, self.M, self.K, self.kernel,
                            self.lorentz_lambda, self.scale_a, self.scale_b, self.precision,
                            self.proposal, self.cone_angle, self.seed & (2**64 - 1),
-                           self.chain_id & (2**64 - 1), self.vectors)
+                           self.chain_id & (2**64 - 1), self.vectors, self.hoppings)
 
     @property
     def N(self) -> int:

@@ -48,6 +48,10 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   if (p->kernel == GFMC_LORENTZ && p->lorentz_lambda < 0) return fail(GFMC_EINVAL, "lambda < 0");
   if (p->vectors != GFMC_VECTORS_SITES && p->vectors != GFMC_VECTORS_OV)
     return fail(GFMC_EINVAL, "unknown start-vector form");
+  if (p->hoppings != GFMC_HOP_RECOMPUTE && p->hoppings != GFMC_HOP_STORED)
+    return fail(GFMC_EINVAL, "unknown hopping mode");
+  if (p->hoppings == GFMC_HOP_STORED && p->vectors != GFMC_VECTORS_SITES)
+    return fail(GFMC_EINVAL, "stored hoppings need the 7 site start vectors");
   d.L = p->L;
   d.N = p->L * p->L * p->L;
   d.half = d.N / 2;
@@ -59,6 +63,7 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   d.nblk = (d.half + kStepThreads - 1) / kStepThreads;
   d.fp32 = p->precision == GFMC_FP32_ACC64;
   d.ov = p->vectors == GFMC_VECTORS_OV;
+  d.hops = p->hoppings == GFMC_HOP_STORED;
   d.a = p->scale_a > 0 ? p->scale_a : 6.0 * p->t / (1.0 - 0.01);
   d.lambda = p->lorentz_lambda > 0 ? p->lorentz_lambda : 4.0;
   if (d.a < 6.0 * p->t) return fail(GFMC_EINVAL, "scale_a must be >= 6t (spectrum inside [-1,1])");
@@ -79,6 +84,7 @@ Layout layout_of(const Derived& d) {
   l.theta = take((size_t)d.N * 8);
   l.phi = take((size_t)d.N * 8);
   l.spin = take((size_t)d.N * 4 * tsz);
+  l.hop = take(d.hops ? (size_t)d.N * 6 * 2 * tsz : 0);
   l.vec = take((size_t)(d.ov ? 2 : 7) * d.N * 2 * tsz);
   l.part = take((size_t)d.S * d.nblk * (d.ov ? kNP2 : kNP) * 8);
   l.mom = take((size_t)d.M * (d.ov ? 3 : 49) * 16);
@@ -94,6 +100,8 @@ void fill_desc(gfmc_chain* c) {
   D.L = c->d.L; D.N = c->d.N; D.half = c->d.half; D.M = c->d.M; D.S = c->d.S; D.K = c->d.K;
   D.nblk = c->d.nblk; D.kernel = c->p.kernel; D.proposal = c->p.proposal; D.log2K = c->d.log2K;
   D.vectors = c->p.vectors;
+  D.hops = c->p.hoppings;
+  D.hop = c->d.hops ? (void*)(c->ws + c->l.hop) : nullptr;
   D.t = c->p.t; D.beta = c->p.beta; D.mu = c->p.mu; D.a = c->d.a; D.cone = c->p.cone_angle;
   D.lambda = c->d.lambda; D.seed = c->p.seed; D.chain_id = c->p.chain_id;
   D.theta = (double*)(c->ws + c->l.theta);
@@ -151,8 +159,8 @@ gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* 
   int nact = P.n;
   for (int s = 1; s <= P.smax; ++s) {
     while (nact > 0 && P.S[nact - 1] < s) --nact;
-    HIPCHK(launch_step(P.fp32, P.ov, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s,
-                       P.stream));
+    HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact],
+                       s, P.stream));
   }
   if (tm) {
     HIPCHK(hipEventRecord(P.ev[P.ev_used + 1], P.stream));
@@ -232,6 +240,7 @@ gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived
   P.stream = c->stream;
   P.fp32 = d.fp32;
   P.ov = d.ov;
+  P.hops = d.hops;
   P.d_desc = (Desc*)(c->ws + l.desc);
   P.d_blkoff = (int*)(c->ws + l.blkoff);
   P.d_force = (int32_t*)(c->ws + l.force);
@@ -245,6 +254,7 @@ gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived
   HIPCHK(hipMemsetAsync(c->desc.theta, 0, (size_t)d.N * 8, c->stream));
   HIPCHK(hipMemsetAsync(c->desc.phi, 0, (size_t)d.N * 8, c->stream));
   HIPCHK(launch_spinors(d.fp32, P.d_desc, 1, d.N, c->stream));
+  if (d.hops) HIPCHK(launch_hops(d.fp32, P.d_desc, d.N, c->stream));
   HIPCHK(launch_tables(P.d_desc, d.K, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return GFMC_OK;
@@ -260,6 +270,7 @@ gfmc_status chain_init_spins(gfmc_chain* c, int mode, double frac) {
     HIPCHK(launch_fisher_yates(P.d_desc, nr, (int32_t*)c->desc.vec, c->stream));
   }
   HIPCHK(launch_spinors(c->d.fp32, P.d_desc, 1, c->d.N, c->stream));
+  if (c->d.hops) HIPCHK(launch_hops(c->d.fp32, P.d_desc, c->d.N, c->stream));
   return GFMC_OK;
 }
 
@@ -353,6 +364,7 @@ gfmc_status gfmc_set_spins(gfmc_chain* c, const double* th, const double* ph) {
   HIPCHK(hipMemcpyAsync(c->desc.theta, th, (size_t)c->d.N * 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->desc.phi, ph, (size_t)c->d.N * 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(launch_spinors(c->d.fp32, c->plan.d_desc, 1, c->d.N, c->stream));
+  if (c->d.hops) HIPCHK(launch_hops(c->d.fp32, c->plan.d_desc, c->d.N, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return GFMC_OK;
 }
@@ -491,8 +503,10 @@ gfmc_status gfmc_chain_step_bytes(gfmc_chain* c, double* bytes_per_step, int32_t
   // The {o,v} form stores 2 complex values per site and advances 1.
   const double tsz = c->d.fp32 ? 4 : 8;
   const double N = c->d.N;
+  // Stored hoppings read 6 complex amplitudes per site instead of a spinor.
   const double stored = c->d.ov ? 2.0 : 7.0;
-  *bytes_per_step = N * (stored * 2 * tsz + 0.5 * stored * 2 * tsz + 4 * tsz);
+  const double per_site_h = c->d.hops ? 6 * 2 * tsz : 4 * tsz;
+  *bytes_per_step = N * (stored * 2 * tsz + 0.5 * stored * 2 * tsz + per_site_h);
   *steps = c->d.S;
   return GFMC_OK;
 }
@@ -523,6 +537,7 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
     if (chains[i]->in_batch) return fail(GFMC_ESTATE, "chain already in a batch");
     if (chains[i]->d.fp32 != chains[0]->d.fp32) return fail(GFMC_EINVAL, "mixed precision");
     if (chains[i]->d.ov != chains[0]->d.ov) return fail(GFMC_EINVAL, "mixed start-vector forms");
+    if (chains[i]->d.hops != chains[0]->d.hops) return fail(GFMC_EINVAL, "mixed hopping modes");
     if (chains[i]->device != dev) return fail(GFMC_EINVAL, "chain on another device");
     for (int j = 0; j < i; ++j)
       if (chains[j] == chains[i]) return fail(GFMC_EINVAL, "chain listed twice");
@@ -541,6 +556,7 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
   P.stream = (hipStream_t)stream;
   P.fp32 = chains[0]->d.fp32;
   P.ov = chains[0]->d.ov;
+  P.hops = chains[0]->d.hops;
   P.d_desc = (Desc*)w; w += align256((size_t)n * sizeof(Desc));
   P.d_blkoff = (int*)w; w += align256((size_t)(n + 1) * sizeof(int));
   P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * n * sizeof(int32_t));
@@ -702,7 +718,7 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   if (!b) return fail(GFMC_EINVAL, "batch is NULL");
   if (trial_steps < 1) return fail(GFMC_EINVAL, "trial_steps must be >= 1");
   Plan& P = b->plan;
-  std::vector<int> key = {P.fp32, P.ov, P.n};
+  std::vector<int> key = {P.fp32, P.ov, P.hops, P.n};
   for (auto* c : b->sorted) { key.push_back(c->d.L); key.push_back(c->d.M); }
   for (auto& kv : g_tune_cache)
     if (kv.first == key) {
@@ -720,7 +736,7 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
     CHK(gfmc_batch_set_tuning(b, ppt));
     // a proposal state for the trial (the counter only advances in k_recon)
     HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
-    HIPCHK(launch_step(P.fp32, P.ov, P.ppt, P.d_desc, P.d_blkoff, P.n, P.blkoff[P.n], 1,
+    HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, P.n, P.blkoff[P.n], 1,
                        P.stream));
     const int smax = std::max(2, std::min(P.smax, trial_steps + 1));
     int nact = P.n;
@@ -728,8 +744,8 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
     for (int s = 2; s <= smax; ++s) {
       while (nact > 0 && P.S[nact - 1] < s) --nact;
       if (nact == 0) break;
-      HIPCHK(launch_step(P.fp32, P.ov, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact], s,
-                         P.stream));
+      HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact],
+                         s, P.stream));
     }
     HIPCHK(hipEventRecord(e1, P.stream));
     HIPCHK(hipEventSynchronize(e1));

@@ -45,7 +45,7 @@ struct Ctl {
 // Per-chain descriptor (device table read by the batched kernels).
 struct Desc {
   int32_t L, N, half, M, S, K, nblk, kernel, proposal, log2K;
-  int32_t vectors, pad_;      // GFMC_VECTORS_SITES or GFMC_VECTORS_OV
+  int32_t vectors, hops;      // GFMC_VECTORS_*, GFMC_HOP_*
   double t, beta, mu, a, cone, lambda;
   uint64_t seed, chain_id;
   double* theta;            // [N]
@@ -56,6 +56,7 @@ struct Desc {
   double* part;             // [S][nblk][kNP] ({o,v}: [S][nblk][kNP2])
   double* mom;              // [M][7][7][2]  ({o,v}: [M][3][2])
   double* gscr;             // [4][K][2]
+  void* hop;                // GFMC_HOP_STORED: t_{i, n_d(i)} as six<T>[2][half]
   double* tab;              // per-chain constant tables of the reconstruction:
                             // g[M], pre[K][2], tw[K/2][2], sinth[K], wt[K]
   Ctl* ctl;

@@ -10,12 +10,13 @@
 
 namespace gfmc {
 hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
-hipError_t launch_step(int fp32, int ov, int ppt, const Desc* d, const int* blkoff, int nact,
-                       int blocks, int s, hipStream_t st);
+hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const int* blkoff,
+                       int nact, int blocks, int s, hipStream_t st);
 hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st);
 hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
                         gfmc_step_record* recs, hipStream_t st);
 hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t st);
+hipError_t launch_hops(int fp32, const Desc* d, int nmax, hipStream_t st);
 hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st);
 hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st);
 hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t st);
@@ -43,12 +44,13 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------- chain layout ----
 struct Derived {
-  int L, N, half, M, S, K, log2K, nblk, fp32, ov;
+  int L, N, half, M, S, K, log2K, nblk, fp32, ov, hops;
   double a, lambda;
 };
 
 struct Layout {
-  size_t desc, blkoff, force, rec, mag, ctl, theta, phi, spin, vec, part, mom, gscr, tab, total;
+  size_t desc, blkoff, force, rec, mag, ctl, theta, phi, spin, hop, vec, part, mom, gscr, tab,
+      total;
 };
 
 // A launch plan: a device table of chain descriptors (sorted by number of
@@ -57,6 +59,7 @@ struct Plan {
   int n = 0, fp32 = 0, smax = 0, kmax = 0, nmax = 0;
   int ppt = 1;                         // site pairs per thread of the step kernel
   int ov = 0;                          // start vectors {o, v} instead of the 7 sites
+  int hops = 0;                        // stored hopping table instead of recompute
   Desc* d_desc = nullptr;
   int* d_blkoff = nullptr;
   int32_t* d_force = nullptr;          // [kRecCap][n]

@@ -277,7 +277,7 @@ __device__ inline void st(GLOBAL six<double>* p, const six<double>& r) {
 //   x = (Re/Im a^{n_0..5}_s, Re/Im a^o_{s-1}  at the n-site,  Re/Im a^o_s at the o-site)
 // summed over the block on the FP64 matrix core, and stores the 49 real
 // combinations per block (no reduction on the per-step critical path).
-template <typename T, bool FIRST, int PPT>
+template <typename T, bool FIRST, int PPT, bool HOPS>
 __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ descs,
                                                        const int* __restrict__ blkoff, int nact,
                                                        int s) {
@@ -310,6 +310,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   GLOBAL six<T>* vn = (GLOBAL six<T>*)((GLOBAL cpx<T>*)D.vec + D.N); // n-slots [2][half]
   const GLOBAL spn<T>* sp_o = sp + (size_t)po * half;
   const GLOBAL spn<T>* sp_n = sp + (size_t)pn * half;
+  // stored hopping rows t_{i, n_d(i)} (HOPS): six<T>[2][half]
+  const GLOBAL six<T>* hrow = (const GLOBAL six<T>*)D.hop;
 
   double x[PPT][16];
 #pragma unroll
@@ -323,14 +325,22 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
     const int xn = 2 * k + ((y + z + pn) & 1);
     // a^o_s on the o-site
     {
-      const spn<T> si = ld(sp_o + h);
+      spn<T> si;
+      six<T> row;
+      if (HOPS) row = ld(hrow + (size_t)po * half + h);
+      else si = ld(sp_o + h);
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         const int nh = nb_half(xo, y, z, d, L);
-        const spn<T> sj = ld(sp_n + nh);
         T hr, hi_;
-        hop_spinor(si, sj, hr, hi_);
+        if (HOPS) {
+          hr = row.v[d].x;
+          hi_ = row.v[d].y;
+        } else {
+          const spn<T> sj = ld(sp_n + nh);
+          hop_spinor(si, sj, hr, hi_);
+        }
         cpx<T> an;
         if (FIRST) { an.x = (nh == o_half) ? (T)1 : (T)0; an.y = 0; }
         else an = ld(vo + (size_t)pn * half + nh);
@@ -351,16 +361,24 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
     }
     // a^{n_e}_s, e = 0..5, on the n-site
     {
-      const spn<T> si = ld(sp_n + h);
+      spn<T> si;
+      six<T> row;
+      if (HOPS) row = ld(hrow + (size_t)pn * half + h);
+      else si = ld(sp_n + h);
       T accr[6], acci[6];
 #pragma unroll
       for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         const int nh = nb_half(xn, y, z, d, L);
-        const spn<T> sj = ld(sp_o + nh);
         T hr, hi_;
-        hop_spinor(si, sj, hr, hi_);
+        if (HOPS) {
+          hr = row.v[d].x;
+          hi_ = row.v[d].y;
+        } else {
+          const spn<T> sj = ld(sp_o + nh);
+          hop_spinor(si, sj, hr, hi_);
+        }
         six<T> an;
         if (FIRST) {
 #pragma unroll
@@ -981,6 +999,31 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
 
 // Spinor cache update for an accepted move (separate so that it runs in the
 // recursion precision).
+// Stored hopping row of `site`: t_{site, n_d(site)} = <chi_site|chi_{n_d}> from
+// the spinor cache (the same arithmetic as the recomputing step kernel).
+template <typename T>
+__device__ inline void build_row(const Desc& D, int site) {
+  int x, y, z;
+  site_xyz(site, D.L, x, y, z);
+  const int par = (x + y + z) & 1, hh = half_index(x, y, z, D.L);
+  const spn<T>* sp = (const spn<T>*)D.spin;
+  const spn<T> si = sp[(size_t)par * D.half + hh];
+  six<T> row;
+  for (int d = 0; d < 6; ++d) {
+    const int nh = nb_half(x, y, z, d, D.L);
+    const spn<T> sj = sp[(size_t)(par ^ 1) * D.half + nh];
+    hop_spinor(si, sj, row.v[d].x, row.v[d].y);
+  }
+  ((six<T>*)D.hop)[(size_t)par * D.half + hh] = row;
+}
+
+template <typename T>
+__global__ void k_hops(const Desc* __restrict__ descs) {
+  const Desc& D = descs[0];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < D.N && D.hop) build_row<T>(D, i);
+}
+
 template <typename T>
 __global__ void k_accept_spinor(const Desc* __restrict__ descs, int n) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -990,6 +1033,8 @@ __global__ void k_accept_spinor(const Desc* __restrict__ descs, int n) {
   if (ctl->mode != 0 || !ctl->accepted) return;
   spn<T>* sp = (spn<T>*)D.spin;
   sp[(size_t)ctl->parity_o * D.half + ctl->o_half] = make_spinor<T>(ctl->th_new, ctl->ph_new);
+  if (D.hop)   // rows of o and of its neighbours change
+    for (int j = 0; j < 7; ++j) build_row<T>(D, ctl->start_site[j]);
 }
 
 // ---------------------------------------------------------- per-site ops ---
@@ -1079,7 +1124,7 @@ hipError_t launch_propose(const Desc* d, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T, int PPT>
+template <typename T, int PPT, bool HOPS>
 hipError_t launch_step_t(int ov, const Desc* d, const int* blkoff, int nact, int blocks, int s,
                          hipStream_t st) {
   const dim3 g(blocks), b(kStepThreads);
@@ -1087,19 +1132,34 @@ hipError_t launch_step_t(int ov, const Desc* d, const int* blkoff, int nact, int
     if (s == 1) hipLaunchKernelGGL((k_step_ov<T, true, PPT>), g, b, 0, st, d, blkoff, nact, s);
     else hipLaunchKernelGGL((k_step_ov<T, false, PPT>), g, b, 0, st, d, blkoff, nact, s);
   } else {
-    if (s == 1) hipLaunchKernelGGL((k_step<T, true, PPT>), g, b, 0, st, d, blkoff, nact, s);
-    else hipLaunchKernelGGL((k_step<T, false, PPT>), g, b, 0, st, d, blkoff, nact, s);
+    if (s == 1)
+      hipLaunchKernelGGL((k_step<T, true, PPT, HOPS>), g, b, 0, st, d, blkoff, nact, s);
+    else
+      hipLaunchKernelGGL((k_step<T, false, PPT, HOPS>), g, b, 0, st, d, blkoff, nact, s);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_step(int fp32, int ov, int ppt, const Desc* d, const int* blkoff, int nact,
-                       int blocks, int s, hipStream_t st) {
+template <typename T, bool HOPS>
+hipError_t launch_step_h(int ov, int ppt, const Desc* d, const int* blkoff, int nact, int blocks,
+                         int s, hipStream_t st) {
+  return ppt == 2 ? launch_step_t<T, 2, HOPS>(ov, d, blkoff, nact, blocks, s, st)
+                  : launch_step_t<T, 1, HOPS>(ov, d, blkoff, nact, blocks, s, st);
+}
+
+hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const int* blkoff,
+                       int nact, int blocks, int s, hipStream_t st) {
   if (fp32)
-    return ppt == 2 ? launch_step_t<float, 2>(ov, d, blkoff, nact, blocks, s, st)
-                    : launch_step_t<float, 1>(ov, d, blkoff, nact, blocks, s, st);
-  return ppt == 2 ? launch_step_t<double, 2>(ov, d, blkoff, nact, blocks, s, st)
-                  : launch_step_t<double, 1>(ov, d, blkoff, nact, blocks, s, st);
+    return hops ? launch_step_h<float, true>(ov, ppt, d, blkoff, nact, blocks, s, st)
+                : launch_step_h<float, false>(ov, ppt, d, blkoff, nact, blocks, s, st);
+  return hops ? launch_step_h<double, true>(ov, ppt, d, blkoff, nact, blocks, s, st)
+              : launch_step_h<double, false>(ov, ppt, d, blkoff, nact, blocks, s, st);
+}
+
+hipError_t launch_hops(int fp32, const Desc* d, int nmax, hipStream_t st) {
+  if (fp32) hipLaunchKernelGGL(k_hops<float>, dim3((nmax + 255) / 256), dim3(256), 0, st, d);
+  else hipLaunchKernelGGL(k_hops<double>, dim3((nmax + 255) / 256), dim3(256), 0, st, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st) {
