@@ -48,6 +48,8 @@ def parse():
                     help="also time the {o, v} start-vector form on the same workload")
     ap.add_argument("--stored-hops", type=int, default=1,
                     help="also time the stored-hopping A/B variant of the step kernel")
+    ap.add_argument("--chain-sweep", action="store_true",
+                    help="step-kernel bandwidth for 8..128 chains of 32^3 (cache residency)")
     ap.add_argument("--serving", type=float, default=0.0,
                     help="run the serving engine for this many seconds of Poisson arrivals")
     ap.add_argument("--copy-probe", action="store_true",
@@ -134,6 +136,33 @@ def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
         flush=True)
 
 
+def chain_sweep(g, torch):
+    """Step-kernel time and algorithmic bandwidth of 32^3, M = 2048 batches of
+    8..128 chains (FP32 and FP64), both launch shapes: shows where the chains'
+    data stops fitting the 256 MB last-level cache."""
+    for prec in (g.FP32_ACC64, g.FP64):
+        for nch in (8, 16, 32, 64, 128):
+            chs = [g.Chain(g.Params(L=L, M=M, beta=20.0, precision=prec, seed=SEED, chain_id=c))
+                   for c in range(nch)]
+            for c in chs:
+                c.init_spins(g.INIT_RANDOM)
+            b = g.Batch(chs)
+            bps, _ = chs[0].step_bytes()
+            for ppt in (1, 2):
+                b.set_tuning(ppt)
+                b.step(1)
+                b.step(2)
+                ms, nl = b.step_timing()
+                us = ms * 1e3 / nl
+                print(json.dumps({"mode": "chain_sweep", "precision": "f32" if prec else "f64",
+                                  "chains": nch, "pairs_per_thread": ppt, "avg_launch_us": us,
+                                  "achieved_GBs": nch * bps / (us * 1e-6) / 1e9,
+                                  "bytes_per_launch": nch * bps}), flush=True)
+            b.close()
+            del chs
+            torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -155,6 +184,9 @@ def main():
     import synth
     if args.serving > 0:
         serving(g, args.serving)
+        return
+    if args.chain_sweep:
+        chain_sweep(g, torch)
         return
 
     dev = torch.device("cuda:0")
