@@ -31,9 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE (one counter per run), each scaled by what the same counter reads
 # for a plain 1 GiB device copy (FETCH x 1.99996, WRITE x 1.0); valid only for
 # the kernel source they were taken with (sha256 below), else reported as null.
-TRAFFIC_KERNEL_SHA256 = "fc0b2bd888bbdbf5798d0c720a439fdd129ee289c6955dde36dcf3fb1f1c40a6"
-TRAFFIC_BYTES = {("k_step<float>", 1): 211836389, ("k_step<float>", 2): 215917114,
-                 ("k_step_ov<float>", 1): 84112190, ("k_step_ov<float>", 2): 85392416}
+TRAFFIC_KERNEL_SHA256 = "286e0e901b52d7fdeacdfa3b35b7f5366ed8b57b6994b4aaa3307d0fe139f90d"
+TRAFFIC_BYTES = {("k_step<float>", 1): 212079264, ("k_step<float>", 2): 215841627, ("k_step_ov<float>", 1): 84127550, ("k_step_ov<float>", 2): 85341794}
 
 
 def parse():
@@ -339,7 +338,8 @@ def main():
             "kernel": "k_step<float> with stored rows", "avg_launch_us": havg * 1e6,
             "bytes_per_launch": NCHAIN * hbytes,
             "achieved_GBs": NCHAIN * hbytes / havg / 1e9,
-            "slowdown_vs_recompute": havg / avg_launch_s}
+            "slowdown_vs_recompute": havg / avg_launch_s,
+            "traffic": traffic_bytes("k_step<float> stored rows", ppt)}
         hb.close()
         del hch
 
