@@ -212,8 +212,13 @@ gfmc_status gfmc_batch_sweep(gfmc_batch* batch, int32_t nsweeps, double* magneti
  * (enable != 0), or go back to direct launches (enable == 0). */
 gfmc_status gfmc_batch_use_graph(gfmc_batch* batch, int32_t enable);
 
-/* Launch shape of the Chebyshev step kernel: site pairs per thread (1 or 2).
- * Results do not depend on it beyond the order of the per-block moment sums. */
+/* Launch shape of the Chebyshev steps: 1 or 2 site pairs per thread of the
+ * multi-block step kernel (one launch per step), or 0 for one LDS-resident
+ * workgroup per chain that runs all M/2 steps in a single launch (every
+ * chain must fit: 72 B/site FP32, 144 B/site FP64 within 140 KB, i.e. up to
+ * 12^3 FP32 / 8^3 FP64, 7 site start vectors, recomputed hoppings).  Results
+ * do not depend on the shape beyond the order of the moment partial sums.
+ * Single chains use shape 0 whenever they fit. */
 gfmc_status gfmc_batch_set_tuning(gfmc_batch* batch, int32_t pairs_per_thread);
 
 /* Time each step-kernel launch shape over `trial_steps` Chebyshev steps on the

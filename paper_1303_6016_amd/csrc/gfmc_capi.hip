@@ -116,15 +116,20 @@ void fill_desc(gfmc_chain* c) {
 }
 
 static int blocks_of(const Derived& d, int ppt) {
-  const int per = kStepThreads * ppt;
+  const int per = kStepThreads * (ppt < 1 ? 1 : ppt);
   return (d.half + per - 1) / per;
 }
+
+// The LDS-resident kernel holds spinors and the 7 bipartite vectors of a
+// chain: 72 B per site (FP32) or 144 B (FP64).
+static size_t resident_lds(const Derived& d) { return (size_t)d.N * (d.fp32 ? 72 : 144); }
+bool resident_ok(const Derived& d) { return !d.ov && !d.hops && resident_lds(d) <= (size_t)kResidentLds; }
 
 gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   std::vector<Desc> ds(sorted.size());
   for (size_t i = 0; i < sorted.size(); ++i) {
     ds[i] = sorted[i]->desc;
-    ds[i].nblk = blocks_of(sorted[i]->d, P.ppt);
+    ds[i].nblk = P.resident ? 1 : blocks_of(sorted[i]->d, P.ppt);
   }
   HIPCHK(hipMemcpyAsync(P.d_desc, ds.data(), ds.size() * sizeof(Desc), hipMemcpyHostToDevice,
                         P.stream));
@@ -139,6 +144,13 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   P.S.resize(P.n);
   P.blkoff.assign(P.n + 1, 0);
   P.smax = P.kmax = P.nmax = 0;
+  bool ok = P.ppt == 0;
+  P.res_lds = 0;
+  for (auto* c : sorted) {
+    ok = ok && resident_ok(c->d);
+    P.res_lds = std::max(P.res_lds, resident_lds(c->d));
+  }
+  P.resident = ok ? 1 : 0;
   for (int i = 0; i < P.n; ++i) {
     P.S[i] = sorted[i]->d.S;
     P.blkoff[i + 1] = P.blkoff[i] + blocks_of(sorted[i]->d, P.ppt);
@@ -156,17 +168,21 @@ gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* 
   HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
   const bool tm = P.timing && P.ev_used + 2 <= (int)P.ev.size();
   if (tm) HIPCHK(hipEventRecord(P.ev[P.ev_used], P.stream));
-  int nact = P.n;
-  for (int s = 1; s <= P.smax; ++s) {
-    while (nact > 0 && P.S[nact - 1] < s) --nact;
-    HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact],
-                       s, P.stream));
+  if (P.resident) {
+    HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
+  } else {
+    int nact = P.n;
+    for (int s = 1; s <= P.smax; ++s) {
+      while (nact > 0 && P.S[nact - 1] < s) --nact;
+      HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, nact,
+                         P.blkoff[nact], s, P.stream));
+    }
   }
   if (tm) {
     HIPCHK(hipEventRecord(P.ev[P.ev_used + 1], P.stream));
     P.ev_used += 2;
   }
-  if (P.timing) P.step_launches += P.smax;
+  if (P.timing) P.step_launches += P.resident ? 1 : P.smax;
   HIPCHK(launch_moments(P.ov, P.d_desc, P.n, P.smax, P.stream));
   if (with_recon) HIPCHK(launch_recon(P.fp32, P.d_desc, P.n, P.kmax, d_force, d_rec, P.stream));
   return GFMC_OK;
@@ -196,7 +212,7 @@ static gfmc_status timing_end(Plan& P) {
   }
   const int timed = P.ev_used / 2;
   // scale the step launch count to the timed proposals
-  if (timed > 0 && P.step_launches > 0) P.step_launches = (int64_t)timed * P.smax;
+  if (timed > 0 && P.step_launches > 0) P.step_launches = (int64_t)timed * (P.resident ? 1 : P.smax);
   P.step_ms = tot;
   P.timing = false;
   return GFMC_OK;
@@ -241,6 +257,7 @@ gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived
   P.fp32 = d.fp32;
   P.ov = d.ov;
   P.hops = d.hops;
+  P.ppt = resident_ok(d) ? 0 : 1;
   P.d_desc = (Desc*)(c->ws + l.desc);
   P.d_blkoff = (int*)(c->ws + l.blkoff);
   P.d_force = (int32_t*)(c->ws + l.force);
@@ -696,9 +713,13 @@ static void drop_graph(Plan& P) {
 
 gfmc_status gfmc_batch_set_tuning(gfmc_batch* b, int32_t pairs_per_thread) {
   if (!b) return fail(GFMC_EINVAL, "batch is NULL");
-  if (pairs_per_thread != 1 && pairs_per_thread != 2)
-    return fail(GFMC_EINVAL, "pairs_per_thread must be 1 or 2");
+  if (pairs_per_thread < 0 || pairs_per_thread > 2)
+    return fail(GFMC_EINVAL, "pairs_per_thread must be 0, 1 or 2");
   Plan& P = b->plan;
+  if (pairs_per_thread == 0)
+    for (auto* c : b->sorted)
+      if (!resident_ok(c->d))
+        return fail(GFMC_EINVAL, "shape 0 needs every chain to fit in LDS");
   HIPCHK(hipStreamSynchronize(P.stream));
   P.ppt = pairs_per_thread;
   plan_shape(P, b->sorted);
@@ -732,8 +753,23 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  for (int ppt : {1, 2}) {
+  bool all_res = true;
+  for (auto* c : b->sorted) all_res = all_res && resident_ok(c->d);
+  for (int ppt : {0, 1, 2}) {
+    if (ppt == 0 && !all_res) continue;
     CHK(gfmc_batch_set_tuning(b, ppt));
+    if (ppt == 0) {   // the resident kernel runs every step of a proposal in one launch
+      HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
+      HIPCHK(hipEventRecord(e0, P.stream));
+      HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
+      HIPCHK(hipEventRecord(e1, P.stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      ms = ms / std::max(1, P.smax) * std::min(P.smax - 1, trial_steps);
+      if (ms < best_ms) { best_ms = ms; best = 0; }
+      continue;
+    }
     // a proposal state for the trial (the counter only advances in k_recon)
     HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
     HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, P.n, P.blkoff[P.n], 1,

@@ -15,6 +15,9 @@ constexpr int kReconThreads = 256;  // threads of the reconstruction block (one 
 constexpr int kRecCap = 64;         // proposals per host round trip (records, forcing)
 constexpr int kMagCap = 64;         // sweeps per host round trip (magnetization)
 constexpr int kMaxK = 8192;         // energy nodes held in LDS by the transform
+// dynamic LDS of the single-workgroup (LDS-resident) Chebyshev kernel; the
+// kernel's static LDS (staging and Gram sums) is 16.9 KB of the 160 KB
+constexpr int kResidentLds = 140 * 1024;
 
 // Complex value and per-site spinor in the recursion precision T.
 template <typename T>

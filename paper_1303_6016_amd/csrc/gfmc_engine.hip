@@ -314,6 +314,7 @@ gfmc_status gfmc_engine_create(int device, size_t budget, int32_t max_slots, gfm
   Plan& P = E->plan;
   char* w = E->plan_mem;
   P.stream = E->stream;
+  P.ppt = 0;   // the LDS-resident kernel whenever every running chain fits
   P.d_desc = (Desc*)w; w += align256((size_t)max_slots * sizeof(Desc));
   P.d_blkoff = (int*)w; w += align256((size_t)(max_slots + 1) * sizeof(int));
   P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * max_slots * sizeof(int32_t));

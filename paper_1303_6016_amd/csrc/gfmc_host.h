@@ -17,6 +17,7 @@ hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t*
                         gfmc_step_record* recs, hipStream_t st);
 hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t st);
 hipError_t launch_hops(int fp32, const Desc* d, int nmax, hipStream_t st);
+hipError_t launch_resident(int fp32, const Desc* d, int n, size_t lds, hipStream_t st);
 hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st);
 hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st);
 hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t st);
@@ -57,7 +58,10 @@ struct Layout {
 // Chebyshev steps, largest first) and the block offsets of the step kernel.
 struct Plan {
   int n = 0, fp32 = 0, smax = 0, kmax = 0, nmax = 0;
-  int ppt = 1;                         // site pairs per thread of the step kernel
+  int ppt = 1;                         // site pairs per thread of the step kernel;
+                                       // 0: one LDS-resident workgroup per chain
+  int resident = 0;                    // shape 0 in effect (every chain fits in LDS)
+  size_t res_lds = 0;                  // dynamic LDS of the resident kernel
   int ov = 0;                          // start vectors {o, v} instead of the 7 sites
   int hops = 0;                        // stored hopping table instead of recompute
   Desc* d_desc = nullptr;
@@ -101,6 +105,7 @@ struct gfmc_batch {
 
 
 gfmc_status derive(const gfmc_chain_params* p, Derived& d);
+bool resident_ok(const Derived& d);
 Layout layout_of(const Derived& d);
 void fill_desc(gfmc_chain* c);
 gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted);

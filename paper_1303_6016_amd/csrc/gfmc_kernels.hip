@@ -277,6 +277,31 @@ __device__ inline void st(GLOBAL six<double>* p, const six<double>& r) {
 //   x = (Re/Im a^{n_0..5}_s, Re/Im a^o_{s-1}  at the n-site,  Re/Im a^o_s at the o-site)
 // summed over the block on the FP64 matrix core, and stores the 49 real
 // combinations per block (no reduction on the per-step critical path).
+// The 49 real block sums from the per-wave 16x16 Gram matrices in gsum:
+// t = 0: P^{oo}; 1..36: P^{de} (d <= e; diagonal -> Re, off-diagonal -> Re, Im);
+// 37..48: Q^{oe} (Re, Im).
+__device__ inline double gram_combo(const double (*gsum)[256], int t) {
+#define G(i, j) (gsum[0][(i) * 16 + (j)] + gsum[1][(i) * 16 + (j)] + gsum[2][(i) * 16 + (j)] + \
+                 gsum[3][(i) * 16 + (j)])
+  if (t == 0) return G(14, 14) + G(15, 15);
+  if (t < 37) {
+    int idx = t - 1, d = 0;
+    while (true) {
+      const int len = 1 + 2 * (5 - d);
+      if (idx < len) break;
+      idx -= len;
+      ++d;
+    }
+    if (idx == 0) return G(2 * d, 2 * d) + G(2 * d + 1, 2 * d + 1);
+    const int e = d + 1 + (idx - 1) / 2;
+    return ((idx - 1) & 1) ? G(2 * d, 2 * e + 1) - G(2 * d + 1, 2 * e)
+                           : G(2 * d, 2 * e) + G(2 * d + 1, 2 * e + 1);
+  }
+  const int q = t - 37, e = q >> 1;
+  return (q & 1) ? G(12, 2 * e + 1) - G(13, 2 * e) : G(12, 2 * e) + G(13, 2 * e + 1);
+#undef G
+}
+
 template <typename T, bool FIRST, int PPT, bool HOPS>
 __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ descs,
                                                        const int* __restrict__ blkoff, int nact,
@@ -457,34 +482,152 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   for (int r = 0; r < 4; ++r) gsum[w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
   __syncthreads();
   const int t = threadIdx.x;
-  if (t < kNP) {
-#define G(i, j) (gsum[0][(i) * 16 + (j)] + gsum[1][(i) * 16 + (j)] + gsum[2][(i) * 16 + (j)] + \
-                 gsum[3][(i) * 16 + (j)])
-    double val;
-    if (t == 0) {
-      val = G(14, 14) + G(15, 15);
-    } else if (t < 37) {
-      // P^{de}, d <= e, packed: diagonal -> Re, off-diagonal -> Re, Im
-      int idx = t - 1, d = 0;
-      while (true) {
-        const int len = 1 + 2 * (5 - d);
-        if (idx < len) break;
-        idx -= len;
-        ++d;
+  if (t < kNP) D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo(gsum, t);
+}
+
+// Small lattices: one workgroup runs all M/2 steps of one chain with its
+// spinors and the 7 bipartite vectors resident in LDS (72 B per site FP32,
+// 144 B FP64), so a proposal costs one launch instead of M/2.  Same
+// arithmetic and Gram sums as k_step; the block partial of step s is the
+// whole-lattice sum (one block per chain).
+template <typename T>
+__global__ __launch_bounds__(kStepThreads) void k_resident(const Desc* __restrict__ descs) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  __shared__ double xs[4][16][17];
+  __shared__ double gsum[4][256];
+  const Desc& D = descs[blockIdx.x];
+  const int L = D.L, hx = L >> 1, half = D.half, N = D.N;
+  spn<T>* sp = (spn<T>*)smem;                 // [2][half]
+  cpx<T>* vo = (cpx<T>*)(sp + N);             // o-slots [2][half]
+  six<T>* vn = (six<T>*)(vo + N);             // n-slots [2][half]
+  const Ctl* ctl = D.ctl;
+  const int pO = ctl->parity_o, o_half = ctl->o_half;
+  int sh[6];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) sh[e] = ctl->start_half[1 + e];
+  const spn<T>* gsp = (const spn<T>*)D.spin;
+  for (int i = threadIdx.x; i < N; i += kStepThreads) sp[i] = gsp[i];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int iters = (half + kStepThreads - 1) / kStepThreads;
+  for (int s = 1; s <= D.S; ++s) {
+    __syncthreads();   // the previous step's vectors (and the spinors) are in place
+    const bool first = (s == 1);
+    const int po = pO ^ (s & 1), pn = po ^ 1;
+    const T c1 = first ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
+    d4v acc = {0.0, 0.0, 0.0, 0.0};
+    for (int it = 0; it < iters; ++it) {
+      const int h = it * kStepThreads + (int)threadIdx.x;
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = 0.0;
+      if (h < half) {
+        const int k = h % hx, r = h / hx, y = r % L, z = r / L;
+        const int xo = 2 * k + ((y + z + po) & 1);
+        const int xn = 2 * k + ((y + z + pn) & 1);
+        {
+          const spn<T> si = sp[po * half + h];
+          T ar = 0, ai = 0;
+#pragma unroll
+          for (int d = 0; d < 6; ++d) {
+            const int nh = nb_half(xo, y, z, d, L);
+            T hr, hi_;
+            hop_spinor(si, sp[pn * half + nh], hr, hi_);
+            cpx<T> an;
+            if (first) { an.x = (nh == o_half) ? (T)1 : (T)0; an.y = 0; }
+            else an = vo[pn * half + nh];
+            ar += hr * an.x - hi_ * an.y;
+            ai += hr * an.y + hi_ * an.x;
+          }
+          cpx<T> ao;
+          ao.x = c1 * ar;
+          ao.y = c1 * ai;
+          if (!first) {
+            const cpx<T> pr = vo[po * half + h];
+            ao.x -= pr.x;
+            ao.y -= pr.y;
+          }
+          vo[po * half + h] = ao;
+          x[14] = (double)ao.x;
+          x[15] = (double)ao.y;
+        }
+        {
+          const spn<T> si = sp[pn * half + h];
+          T accr[6], acci[6];
+#pragma unroll
+          for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
+#pragma unroll
+          for (int d = 0; d < 6; ++d) {
+            const int nh = nb_half(xn, y, z, d, L);
+            T hr, hi_;
+            hop_spinor(si, sp[po * half + nh], hr, hi_);
+            six<T> an;
+            if (first) {
+#pragma unroll
+              for (int e = 0; e < 6; ++e) { an.v[e].x = (nh == sh[e]) ? (T)1 : (T)0; an.v[e].y = 0; }
+            } else {
+              an = vn[po * half + nh];
+            }
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+              accr[e] += hr * an.v[e].x - hi_ * an.v[e].y;
+              acci[e] += hr * an.v[e].y + hi_ * an.v[e].x;
+            }
+          }
+          six<T> out;
+          six<T> prev;
+          if (!first) prev = vn[pn * half + h];
+#pragma unroll
+          for (int e = 0; e < 6; ++e) {
+            out.v[e].x = c1 * accr[e];
+            out.v[e].y = c1 * acci[e];
+            if (!first) {
+              out.v[e].x -= prev.v[e].x;
+              out.v[e].y -= prev.v[e].y;
+            }
+            x[2 * e] = (double)out.v[e].x;
+            x[2 * e + 1] = (double)out.v[e].y;
+          }
+          vn[pn * half + h] = out;
+          cpx<T> aop;
+          if (first) {
+            aop.x = (h == o_half) ? (T)1 : (T)0;
+            aop.y = 0;
+            vo[pn * half + h] = aop;
+            six<T> u;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) { u.v[e].x = (h == sh[e]) ? (T)1 : (T)0; u.v[e].y = 0; }
+            vn[po * half + h] = u;
+          } else {
+            aop = vo[pn * half + h];
+          }
+          x[12] = (double)aop.x;
+          x[13] = (double)aop.y;
+        }
       }
-      if (idx == 0) {
-        val = G(2 * d, 2 * d) + G(2 * d + 1, 2 * d + 1);
-      } else {
-        const int e = d + 1 + (idx - 1) / 2;
-        val = ((idx - 1) & 1) ? G(2 * d, 2 * e + 1) - G(2 * d + 1, 2 * e)
-                              : G(2 * d, 2 * e) + G(2 * d + 1, 2 * e + 1);
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        if ((lane >> 4) == rr) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) xs[w][lane & 15][i] = x[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const double val = xs[w][4 * m + (lane >> 4)][lane & 15];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-    } else {
-      const int q = t - 37, e = q >> 1;
-      val = (q & 1) ? G(12, 2 * e + 1) - G(13, 2 * e) : G(12, 2 * e) + G(13, 2 * e + 1);
     }
-#undef G
-    D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = val;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gsum[w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < kNP) D.part[(size_t)(s - 1) * kNP + t] = gram_combo(gsum, t);
   }
 }
 
@@ -1214,6 +1357,22 @@ hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t s
 namespace gfmc {
 hipError_t launch_tables(const Desc* d, int kmax, hipStream_t st) {
   hipLaunchKernelGGL(k_tables, dim3((kmax + 255) / 256), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+}  // namespace gfmc
+
+namespace gfmc {
+hipError_t launch_resident(int fp32, const Desc* d, int n, size_t lds, hipStream_t st) {
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipFuncSetAttribute((const void*)k_resident<float>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, kResidentLds);
+    hipFuncSetAttribute((const void*)k_resident<double>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, kResidentLds);
+    attr_done = true;
+  }
+  if (fp32) hipLaunchKernelGGL(k_resident<float>, dim3(n), dim3(kStepThreads), lds, st, d);
+  else hipLaunchKernelGGL(k_resident<double>, dim3(n), dim3(kStepThreads), lds, st, d);
   return hipGetLastError();
 }
 }  // namespace gfmc
