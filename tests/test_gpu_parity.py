@@ -251,7 +251,7 @@ def test_batch_launch_shapes_agree(g, ppt):
     recs = b.step(1, records=True)[0]
     for r, a in zip(recs, alone):
         assert r.site == a.site and abs(r.dseff - a.dseff) < 1e-12
-    assert b.autotune(4) in (1, 2)
+    assert b.autotune(4) in (0, 1, 2)
     b.close()
 
 
