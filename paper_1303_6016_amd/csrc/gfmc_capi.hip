@@ -391,8 +391,9 @@ gfmc_status gfmc_get_spins(gfmc_chain* c, double* th, double* ph) {
   HIPCHK(hipSetDevice(c->device));
   if (!th || !ph) return fail(GFMC_EINVAL, "theta/phi is NULL");
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(th, c->desc.theta, (size_t)c->d.N * 8, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(ph, c->desc.phi, (size_t)c->d.N * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(th, c->desc.theta, (size_t)c->d.N * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(ph, c->desc.phi, (size_t)c->d.N * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return GFMC_OK;
 }
 
@@ -409,7 +410,9 @@ gfmc_status gfmc_get_counter(gfmc_chain* c, int64_t* index) {
   if (!c || !index) return fail(GFMC_EINVAL, "NULL argument");
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(index, &c->desc.ctl->index, sizeof(*index), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(index, &c->desc.ctl->index, sizeof(*index), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return GFMC_OK;
 }
 
@@ -493,14 +496,16 @@ gfmc_status gfmc_sweep(gfmc_chain* c, int32_t nsweeps, double* mag, int64_t* acc
   CHK(check_chain(c));
   if (nsweeps < 0) return fail(GFMC_EINVAL, "nsweeps must be >= 0");
   int64_t a0 = 0, a1 = 0;
-  HIPCHK(hipMemcpy(&a0, &c->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(&a0, &c->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   for (int s = 0; s < nsweeps; ++s) {
     CHK(run_proposals(c->plan, c->d.N, nullptr, nullptr));
     HIPCHK(launch_magnetization(c->plan.d_desc, 1, c->plan.d_mag, c->stream));
     if (mag) HIPCHK(hipMemcpyAsync(mag + s, c->plan.d_mag, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   }
-  HIPCHK(hipMemcpy(&a1, &c->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(&a1, &c->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   if (accepted) *accepted = a1 - a0;
   return GFMC_OK;
 }
@@ -677,8 +682,9 @@ gfmc_status gfmc_batch_sweep(gfmc_batch* b, int32_t nsweeps, double* mag, int64_
   const int n = P.n;
   std::vector<int64_t> a0(n), a1(n);
   for (int i = 0; i < n; ++i)
-    HIPCHK(hipMemcpy(&a0[i], &b->chains[b->order[i]]->desc.ctl->accepted_total, 8,
-                     hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(&a0[i], &b->chains[b->order[i]]->desc.ctl->accepted_total, 8,
+                          hipMemcpyDeviceToHost, P.stream));
+  HIPCHK(hipStreamSynchronize(P.stream));
   bool uniform = true;
   for (auto* c : b->chains) uniform = uniform && c->d.N == b->chains[0]->d.N;
   if (!uniform) return fail(GFMC_EINVAL, "gfmc_batch_sweep needs chains of one lattice size");
@@ -697,8 +703,9 @@ gfmc_status gfmc_batch_sweep(gfmc_batch* b, int32_t nsweeps, double* mag, int64_
       for (int i = 0; i < n; ++i) mag[(size_t)b->order[i] * nsweeps + s] = m[i];
   }
   for (int i = 0; i < n; ++i)
-    HIPCHK(hipMemcpy(&a1[i], &b->chains[b->order[i]]->desc.ctl->accepted_total, 8,
-                     hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(&a1[i], &b->chains[b->order[i]]->desc.ctl->accepted_total, 8,
+                          hipMemcpyDeviceToHost, P.stream));
+  HIPCHK(hipStreamSynchronize(P.stream));
   if (accepted)
     for (int i = 0; i < n; ++i) accepted[b->order[i]] = a1[i] - a0[i];
   return GFMC_OK;

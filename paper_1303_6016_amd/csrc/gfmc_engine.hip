@@ -85,6 +85,16 @@ struct Request {
 
 }  // namespace
 
+// Chains of one precision x start-vector form x hopping mode share a launch
+// plan; its descriptor table is re-uploaded only when its members change.
+constexpr int kGroups = 8;
+struct Group {
+  Plan plan;
+  std::vector<gfmc_chain*> members;   // plan order (most Chebyshev steps first)
+};
+
+static int group_of(const Derived& d) { return d.fp32 | (d.ov << 1) | (d.hops << 2); }
+
 struct gfmc_engine {
   int device = 0;
   size_t budget = 0;
@@ -93,7 +103,8 @@ struct gfmc_engine {
   char* plan_mem = nullptr;
   hipStream_t stream = nullptr;
   Arena arena;
-  Plan plan;
+  Group groups[kGroups];
+  bool members_changed = true;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request*> queue;
@@ -140,10 +151,13 @@ static gfmc_result make_result(const Request* r, gfmc_status st, int64_t accepte
 
 // Retire a running request (caller holds no lock; the worker thread only).
 static void retire(gfmc_engine* E, Request* r, gfmc_status st) {
+  // the chain's last proposals may still be queued: wait before its memory is reused
+  if (hipStreamSynchronize(E->stream) != hipSuccess && st == GFMC_OK) st = GFMC_EDEVICE;
   int64_t acc = 0;
   if (r->chain) {
-    if (hipMemcpy(&acc, &r->chain->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost) !=
-        hipSuccess)
+    if (hipMemcpyAsync(&acc, &r->chain->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost,
+                       E->stream) != hipSuccess ||
+        hipStreamSynchronize(E->stream) != hipSuccess)
       acc = -1;
   }
   const gfmc_result res = make_result(r, st, acc, E->now());
@@ -155,33 +169,43 @@ static void retire(gfmc_engine* E, Request* r, gfmc_status st) {
     E->arena.release(r->off, r->bytes);
   }
   E->running.erase(std::remove(E->running.begin(), E->running.end(), r), E->running.end());
+  E->members_changed = true;
   delete r;
 }
 
-// One proposal for every running chain of one precision and start-vector
-// form (a plan holds one of each; the groups advance in separate sequences).
-static gfmc_status iterate_precision(gfmc_engine* E, int fp32, int ov, bool& any) {
-  std::vector<Request*> rs;
-  for (auto* r : E->running)
-    if (r->d.fp32 == fp32 && r->d.ov == ov) rs.push_back(r);
-  if (rs.empty()) return GFMC_OK;
-  any = true;
-  std::vector<gfmc_chain*> sorted;
-  for (auto* r : rs) sorted.push_back(r->chain);
-  std::stable_sort(sorted.begin(), sorted.end(),
-                   [](gfmc_chain* a, gfmc_chain* b) { return a->d.S > b->d.S; });
-  Plan& P = E->plan;
-  P.fp32 = fp32;
-  P.ov = ov;
-  plan_shape(P, sorted);
-  CHK(upload_plan(P, sorted));
-  CHK(enqueue_proposal(P, nullptr, nullptr, true));
+// Rebuild the member lists of the groups after admissions or retirements and
+// re-upload the plans whose membership changed.
+static gfmc_status refresh_groups(gfmc_engine* E) {
+  std::vector<gfmc_chain*> lists[kGroups];
+  for (auto* r : E->running) lists[group_of(r->d)].push_back(r->chain);
+  for (int g = 0; g < kGroups; ++g) {
+    auto& L = lists[g];
+    std::stable_sort(L.begin(), L.end(),
+                     [](gfmc_chain* a, gfmc_chain* b) { return a->d.S > b->d.S; });
+    Group& G = E->groups[g];
+    if (L == G.members) continue;
+    G.members = L;
+    if (L.empty()) continue;
+    plan_shape(G.plan, L);
+    CHK(upload_plan(G.plan, L));
+  }
+  E->members_changed = false;
+  return GFMC_OK;
+}
+
+// One proposal for every running chain: one launch sequence per group.
+static gfmc_status iterate(gfmc_engine* E) {
+  if (E->members_changed) CHK(refresh_groups(E));
+  for (int g = 0; g < kGroups; ++g)
+    if (!E->groups[g].members.empty())
+      CHK(enqueue_proposal(E->groups[g].plan, nullptr, nullptr, true));
   return GFMC_OK;
 }
 
 static void worker_main(gfmc_engine* E) {
   (void)hipSetDevice(E->device);
   std::vector<Request*> admitted;
+  int since_sync = 0;
   while (true) {
     admitted.clear();
     {
@@ -221,6 +245,7 @@ static void worker_main(gfmc_engine* E) {
       r->t_admit = E->now();
       r->t_sweep_start = r->t_admit;
       E->running.push_back(r);
+      E->members_changed = true;
     }
     // cancelled requests leave before the next proposal
     std::vector<Request*> cancelled;
@@ -232,10 +257,23 @@ static void worker_main(gfmc_engine* E) {
     for (auto* r : cancelled) retire(E, r, GFMC_ECANCELED);
     if (E->running.empty()) continue;
 
-    bool any = false;
-    gfmc_status st = GFMC_OK;
-    for (int q = 0; q < 4 && st == GFMC_OK; ++q) st = iterate_precision(E, q & 1, q >> 1, any);
-    if (st == GFMC_OK && hipStreamSynchronize(E->stream) != hipSuccess) st = GFMC_EDEVICE;
+    gfmc_status st = iterate(E);
+    // The host knows every chain's proposal count, so it waits for the device
+    // only where it needs device results or time stamps: sweep boundaries,
+    // pending admissions or cancellations, and every 8th iteration (so that
+    // queued requests are not kept behind a long run of enqueued work).
+    bool boundary_now = false, pending = false;
+    for (auto* r : E->running) boundary_now |= ((r->done_props + 1) % r->d.N == 0);
+    {
+      std::lock_guard<std::mutex> g(E->mu);
+      pending = !E->queue.empty();
+      for (auto* r : E->running) pending |= r->cancel;
+    }
+    ++since_sync;
+    if (st == GFMC_OK && (boundary_now || pending || since_sync >= 8)) {
+      if (hipStreamSynchronize(E->stream) != hipSuccess) st = GFMC_EDEVICE;
+      since_sync = 0;
+    }
     if (st != GFMC_OK) {
       std::vector<Request*> all = E->running;
       for (auto* r : all) retire(E, r, st);
@@ -303,7 +341,7 @@ gfmc_status gfmc_engine_create(int device, size_t budget, int32_t max_slots, gfm
     delete E;
     return gfmc_fail(GFMC_ENOMEM, "hipMalloc of the HBM budget failed");
   }
-  if (hipMalloc(&E->plan_mem, plan_bytes(max_slots)) != hipSuccess ||
+  if (hipMalloc(&E->plan_mem, kGroups * plan_bytes(max_slots)) != hipSuccess ||
       hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipFree(E->base);
     if (E->plan_mem) (void)hipFree(E->plan_mem);
@@ -311,15 +349,22 @@ gfmc_status gfmc_engine_create(int device, size_t budget, int32_t max_slots, gfm
     return gfmc_fail(GFMC_EDEVICE, "engine device setup failed");
   }
   E->arena.init(E->budget);
-  Plan& P = E->plan;
-  char* w = E->plan_mem;
-  P.stream = E->stream;
-  P.ppt = 0;   // the LDS-resident kernel whenever every running chain fits
-  P.d_desc = (Desc*)w; w += align256((size_t)max_slots * sizeof(Desc));
-  P.d_blkoff = (int*)w; w += align256((size_t)(max_slots + 1) * sizeof(int));
-  P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * max_slots * sizeof(int32_t));
-  P.d_rec = (gfmc_step_record*)w; w += align256((size_t)kRecCap * max_slots * sizeof(gfmc_step_record));
-  P.d_mag = (double*)w;
+  const size_t pb = plan_bytes(max_slots);
+  for (int g = 0; g < kGroups; ++g) {
+    Plan& P = E->groups[g].plan;
+    char* w = E->plan_mem + g * pb;
+    P.stream = E->stream;
+    P.fp32 = g & 1;
+    P.ov = (g >> 1) & 1;
+    P.hops = (g >> 2) & 1;
+    P.ppt = 0;   // the LDS-resident kernel whenever every member chain fits
+    P.d_desc = (Desc*)w; w += align256((size_t)max_slots * sizeof(Desc));
+    P.d_blkoff = (int*)w; w += align256((size_t)(max_slots + 1) * sizeof(int));
+    P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * max_slots * sizeof(int32_t));
+    P.d_rec = (gfmc_step_record*)w;
+    w += align256((size_t)kRecCap * max_slots * sizeof(gfmc_step_record));
+    P.d_mag = (double*)w;
+  }
   E->worker = std::thread(worker_main, E);
   *out = E;
   return GFMC_OK;

@@ -1313,12 +1313,11 @@ hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st
 
 hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
                         gfmc_step_record* recs, hipStream_t st) {
-  static bool attr_done = false;
-  if (!attr_done) {
-    hipFuncSetAttribute((const void*)k_recon, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        kMaxK * (int)sizeof(double2));
-    attr_done = true;
-  }
+  static const bool attr_done = [] {   // thread-safe one-time setup
+    return hipFuncSetAttribute((const void*)k_recon, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kMaxK * (int)sizeof(double2)) == hipSuccess;
+  }();
+  (void)attr_done;
   hipLaunchKernelGGL(k_recon, dim3(n), dim3(kReconThreads), (size_t)kmax * sizeof(double2), st,
                      d, force, recs);
   hipError_t e = hipGetLastError();
@@ -1363,14 +1362,15 @@ hipError_t launch_tables(const Desc* d, int kmax, hipStream_t st) {
 
 namespace gfmc {
 hipError_t launch_resident(int fp32, const Desc* d, int n, size_t lds, hipStream_t st) {
-  static bool attr_done = false;
-  if (!attr_done) {
-    hipFuncSetAttribute((const void*)k_resident<float>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, kResidentLds);
-    hipFuncSetAttribute((const void*)k_resident<double>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, kResidentLds);
-    attr_done = true;
-  }
+  static const bool attr_done = [] {   // thread-safe one-time setup
+    return hipFuncSetAttribute((const void*)k_resident<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kResidentLds) ==
+               hipSuccess &&
+           hipFuncSetAttribute((const void*)k_resident<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kResidentLds) ==
+               hipSuccess;
+  }();
+  (void)attr_done;
   if (fp32) hipLaunchKernelGGL(k_resident<float>, dim3(n), dim3(kStepThreads), lds, st, d);
   else hipLaunchKernelGGL(k_resident<double>, dim3(n), dim3(kStepThreads), lds, st, d);
   return hipGetLastError();
