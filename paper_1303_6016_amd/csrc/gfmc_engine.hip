@@ -174,7 +174,8 @@ static void retire(gfmc_engine* E, Request* r, gfmc_status st) {
 }
 
 // Rebuild the member lists of the groups after admissions or retirements and
-// re-upload the plans whose membership changed.
+// re-upload every non-empty plan (a new chain may reuse the host address of a
+// retired one, so equal pointer lists do not mean equal descriptors).
 static gfmc_status refresh_groups(gfmc_engine* E) {
   std::vector<gfmc_chain*> lists[kGroups];
   for (auto* r : E->running) lists[group_of(r->d)].push_back(r->chain);
@@ -183,7 +184,6 @@ static gfmc_status refresh_groups(gfmc_engine* E) {
     std::stable_sort(L.begin(), L.end(),
                      [](gfmc_chain* a, gfmc_chain* b) { return a->d.S > b->d.S; });
     Group& G = E->groups[g];
-    if (L == G.members) continue;
     G.members = L;
     if (L.empty()) continue;
     plan_shape(G.plan, L);
