@@ -31,12 +31,12 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE (one counter per run), each scaled by what the same counter reads
 # for a plain 1 GiB device copy (FETCH x 1.99996, WRITE x 1.0); valid only for
 # the kernel source they were taken with (sha256 below), else reported as null.
-TRAFFIC_KERNEL_SHA256 = "01c92d8648a7f56230a22a3def94528828650b267da47ebeb9ee481beeef8fe1"
-TRAFFIC_BYTES = {("k_step<float>", 1): 211846261,
-                 ("k_step<float>", 2): 215917242,
+TRAFFIC_KERNEL_SHA256 = "c8f1b6661c0aac157bec7646dce83d2b10c0128dabfee2b0b8b830261092ca96"
+TRAFFIC_BYTES = {("k_step<float>", 1): 211848869,
+                 ("k_step<float>", 2): 215920410,
                  ("k_step_ov<float>", 1): 84127550,
-                 ("k_step_ov<float>", 2): 85350369,
-                 ("k_step<float> stored rows", 2): 285815583}
+                 ("k_step_ov<float>", 2): 85345185,
+                 ("k_step<float> stored rows", 2): 285840542}
 
 
 def parse():
