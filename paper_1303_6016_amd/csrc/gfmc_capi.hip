@@ -85,9 +85,7 @@ Layout layout_of(const Derived& d) {
   l.phi = take((size_t)d.N * 8);
   l.spin = take((size_t)d.N * 4 * tsz);
   l.hop = take(d.hops ? (size_t)d.N * 6 * 2 * tsz : 0);
-  // pair form: one record {spinor, o-slot, v-slot} per site (8 reals);
-  // 7 site vectors: 7 complex per site
-  l.vec = take(d.ov ? (size_t)d.N * 8 * tsz : (size_t)7 * d.N * 2 * tsz);
+  l.vec = take((size_t)(d.ov ? 2 : 7) * d.N * 2 * tsz);
   l.part = take((size_t)d.S * d.nblk * (d.ov ? kNP2 : kNP) * 8);
   l.mom = take((size_t)d.M * (d.ov ? 3 : 49) * 16);
   l.gscr = take((size_t)4 * d.K * 16);

@@ -661,39 +661,12 @@ __device__ inline double sum_run(const double* __restrict__ src, int n) {
 }
 
 // The pair form {|o>, |v>}: |a^o_0> = |o>, |a^v_0> = |v> = sum_d delta_d |n_d>
-// (|v> = Delta|o>, Section 2.2).  Same bipartite rule as the 7-vector form
-// with one v-slot in place of the six n-slots: a^o_s lives on parity
-// p(o)^(s&1), a^v_s on the other.  Each site is one record {spinor, o-slot,
-// v-slot} (32 B FP32, 64 B FP64), so a neighbour's spinor and vector value
-// arrive in one cache line.  Per step the block sums P^{oo}_s = <a^o_s|a^o_s>,
+// (|v> = Delta|o>, Section 2.2).  Same bipartite storage as above with one
+// v-slot in place of the six n-slots: a^o_s lives on parity p(o)^(s&1), a^v_s
+// on the other.  Per step the block sums P^{oo}_s = <a^o_s|a^o_s>,
 // P^{vv}_s = <a^v_s|a^v_s> and Q^{ov}_s = <a^o_{s-1}|a^v_s> (4 real numbers;
 // the pairs that vanish on a bipartite lattice are not formed) with wavefront
 // shuffles and one LDS step.
-template <typename T>
-struct alignas(16) recov {
-  spn<T> s;
-  cpx<T> o, v;
-};
-
-__device__ inline spn<float> ld_s(const GLOBAL recov<float>* r) { return ld((const GLOBAL spn<float>*)r); }
-__device__ inline spn<double> ld_s(const GLOBAL recov<double>* r) { return ld((const GLOBAL spn<double>*)r); }
-template <typename T>
-__device__ inline const GLOBAL cpx<T>* o_of(const GLOBAL recov<T>* r) {
-  return (const GLOBAL cpx<T>*)((const GLOBAL char*)r + sizeof(spn<T>));
-}
-template <typename T>
-__device__ inline const GLOBAL cpx<T>* v_of(const GLOBAL recov<T>* r) {
-  return (const GLOBAL cpx<T>*)((const GLOBAL char*)r + sizeof(spn<T>) + sizeof(cpx<T>));
-}
-template <typename T>
-__device__ inline GLOBAL cpx<T>* o_of(GLOBAL recov<T>* r) {
-  return (GLOBAL cpx<T>*)((GLOBAL char*)r + sizeof(spn<T>));
-}
-template <typename T>
-__device__ inline GLOBAL cpx<T>* v_of(GLOBAL recov<T>* r) {
-  return (GLOBAL cpx<T>*)((GLOBAL char*)r + sizeof(spn<T>) + sizeof(cpx<T>));
-}
-
 template <typename T, bool FIRST, int PPT>
 __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict__ descs,
                                                           const int* __restrict__ blkoff,
@@ -726,9 +699,11 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
     di[e] = FIRST ? (T)ctl->delta[2 * e + 1] : (T)0;
   }
   const T c1 = FIRST ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
-  GLOBAL recov<T>* rec = (GLOBAL recov<T>*)D.vec;          // [2][half]
-  GLOBAL recov<T>* rec_o = rec + (size_t)po * half;        // records of parity po
-  GLOBAL recov<T>* rec_n = rec + (size_t)pn * half;        // records of parity pn
+  const GLOBAL spn<T>* sp = (const GLOBAL spn<T>*)D.spin;
+  GLOBAL cpx<T>* vo = (GLOBAL cpx<T>*)D.vec;               // o-slots [2][half]
+  GLOBAL cpx<T>* vv = (GLOBAL cpx<T>*)D.vec + D.N;         // v-slots [2][half]
+  const GLOBAL spn<T>* sp_o = sp + (size_t)po * half;
+  const GLOBAL spn<T>* sp_n = sp + (size_t)pn * half;
   // a^v_0 at a site with half-row index hh on the parity of o's neighbours
   auto v0 = [&](int hh) {
     cpx<T> r = {(T)0, (T)0};
@@ -747,57 +722,57 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
     const int xn = 2 * k + ((y + z + pn) & 1);
     cpx<T> ao, av, aop;
     {
-      const spn<T> si = ld_s(rec_o + h);
+      const spn<T> si = ld(sp_o + h);
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         const int nh = nb_half(xo, y, z, d, L);
-        const spn<T> sj = ld_s(rec_n + nh);
+        const spn<T> sj = ld(sp_n + nh);
         T hr, hi_;
         hop_spinor(si, sj, hr, hi_);
         cpx<T> an;
         if (FIRST) { an.x = (nh == o_half) ? (T)1 : (T)0; an.y = 0; }
-        else an = ld(o_of(rec_n + nh));
+        else an = ld(vo + (size_t)pn * half + nh);
         ar += hr * an.x - hi_ * an.y;
         ai += hr * an.y + hi_ * an.x;
       }
       ao.x = c1 * ar;
       ao.y = c1 * ai;
       if (!FIRST) {
-        const cpx<T> pr = ld(o_of(rec_o + h));
+        const cpx<T> pr = ld(vo + (size_t)po * half + h);
         ao.x -= pr.x;
         ao.y -= pr.y;
       }
-      st(o_of(rec_o + h), ao);
+      st(vo + (size_t)po * half + h, ao);
     }
     {
-      const spn<T> si = ld_s(rec_n + h);
+      const spn<T> si = ld(sp_n + h);
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         const int nh = nb_half(xn, y, z, d, L);
-        const spn<T> sj = ld_s(rec_o + nh);
+        const spn<T> sj = ld(sp_o + nh);
         T hr, hi_;
         hop_spinor(si, sj, hr, hi_);
-        const cpx<T> an = FIRST ? v0(nh) : ld(v_of(rec_o + nh));
+        const cpx<T> an = FIRST ? v0(nh) : ld(vv + (size_t)po * half + nh);
         ar += hr * an.x - hi_ * an.y;
         ai += hr * an.y + hi_ * an.x;
       }
       av.x = c1 * ar;
       av.y = c1 * ai;
       if (!FIRST) {
-        const cpx<T> pr = ld(v_of(rec_n + h));
+        const cpx<T> pr = ld(vv + (size_t)pn * half + h);
         av.x -= pr.x;
         av.y -= pr.y;
       }
-      st(v_of(rec_n + h), av);
+      st(vv + (size_t)pn * half + h, av);
       if (FIRST) {
         aop.x = (h == o_half) ? (T)1 : (T)0;
         aop.y = 0;
-        st(o_of(rec_n + h), aop);
-        st(v_of(rec_o + h), v0(h));
+        st(vo + (size_t)pn * half + h, aop);
+        st(vv + (size_t)po * half + h, v0(h));
       } else {
-        aop = ld(o_of(rec_n + h));
+        aop = ld(vo + (size_t)pn * half + h);
       }
     }
     const double aor = ao.x, aoi = ao.y, avr = av.x, avi = av.y, apr = aop.x, api = aop.y;
@@ -1200,10 +1175,7 @@ __global__ void k_accept_spinor(const Desc* __restrict__ descs, int n) {
   const Ctl* ctl = D.ctl;
   if (ctl->mode != 0 || !ctl->accepted) return;
   spn<T>* sp = (spn<T>*)D.spin;
-  const spn<T> ns = make_spinor<T>(ctl->th_new, ctl->ph_new);
-  sp[(size_t)ctl->parity_o * D.half + ctl->o_half] = ns;
-  if (D.vectors == GFMC_VECTORS_OV)   // pair-form records carry their own spinor copy
-    ((recov<T>*)D.vec)[(size_t)ctl->parity_o * D.half + ctl->o_half].s = ns;
+  sp[(size_t)ctl->parity_o * D.half + ctl->o_half] = make_spinor<T>(ctl->th_new, ctl->ph_new);
   if (D.hop)   // rows of o and of its neighbours change
     for (int j = 0; j < 7; ++j) build_row<T>(D, ctl->start_site[j]);
 }
@@ -1217,10 +1189,8 @@ __global__ void k_spinors(const Desc* __restrict__ descs) {
   int x, y, z;
   site_xyz(i, D.L, x, y, z);
   spn<T>* sp = (spn<T>*)D.spin;
-  const size_t at = (size_t)((x + y + z) & 1) * D.half + half_index(x, y, z, D.L);
-  const spn<T> v = make_spinor<T>(D.theta[i], D.phi[i]);
-  sp[at] = v;
-  if (D.vectors == GFMC_VECTORS_OV) ((recov<T>*)D.vec)[at].s = v;
+  sp[(size_t)((x + y + z) & 1) * D.half + half_index(x, y, z, D.L)] =
+      make_spinor<T>(D.theta[i], D.phi[i]);
 }
 
 // Initial spins: mode 0 uniform on the sphere from counter (i, 2, 0, 0);
