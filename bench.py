@@ -51,10 +51,14 @@ def parse():
                     help="also time the {o, v} start-vector form on the same workload")
     ap.add_argument("--stored-hops", type=int, default=1,
                     help="also time the stored-hopping A/B variant of the step kernel")
+    ap.add_argument("--mixed", type=int, default=1,
+                    help="also time one 64^3 chain with eight 32^3 chains in one batch")
     ap.add_argument("--chain-sweep", action="store_true",
                     help="step-kernel bandwidth for 8..128 chains of 32^3 (cache residency)")
     ap.add_argument("--serving", type=float, default=0.0,
                     help="run the serving engine for this many seconds of Poisson arrivals")
+    ap.add_argument("--copy-sweep", action="store_true",
+                    help="device-copy bandwidth for working sets of 16 MiB .. 2 GiB")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -68,22 +72,107 @@ def traffic_bytes(kernel: str, ppt: int):
     return TRAFFIC_BYTES.get((kernel, ppt))
 
 
-def cpu_baseline(n_prop: int = 2):
-    """The FP64 oracle, single-threaded, on a bounded sample of the same
-    workload: n_prop proposals of one 32^3, M = 2048 chain."""
-    import numpy as np
+def host_cpu():
+    """Model name and core counts of the host the oracle runs on."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model_name": name, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(max_threads: int = 16):
+    """The FP64 oracle on a bounded sample of the same workload (32^3,
+    M = 2048, uniform-sphere starts, seed 7): one proposal on one thread,
+    then one independent chain per host core (at most max_threads), one
+    proposal each, run concurrently -- the chain-per-core decomposition.
+    The oracle is C called through ctypes, which releases the GIL, so the
+    threads run in parallel."""
+    import threading
     import oracle
-    m = oracle.Model(L=L, M=M, beta=1.0 / T_LO, seed=SEED, chain_id=0)
-    th, ph = oracle.init_spins(m, 0)
+    svu = L ** 3 * 7 * (M // 2)
+
+    def setup(c):
+        m = oracle.Model(L=L, M=M, beta=1.0 / T_LO, seed=SEED, chain_id=c)
+        th, ph = oracle.init_spins(m, 0)
+        return m, th, ph
+
+    m, th, ph = setup(0)
     t0 = time.perf_counter()
-    for idx in range(n_prop):
-        oracle.step(m, th, ph, idx)
-    dt = time.perf_counter() - t0
-    svu = n_prop * m.N * 7 * (M // 2)
-    return {"value": svu / dt, "unit": "svu/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_prop} proposals of one 32^3 M=2048 chain (FP64, single thread), "
-                      f"{dt:.1f} s; svu counted as N*7*M/2 per proposal",
-            "mc_spin_updates_per_s": n_prop / dt}
+    oracle.step(m, th, ph, 0)
+    dt1 = time.perf_counter() - t0
+
+    nthr = max(1, min(max_threads, len(os.sched_getaffinity(0))))
+    states = [setup(c) for c in range(nthr)]
+    gate = threading.Barrier(nthr + 1)
+
+    def work(st):
+        gate.wait()
+        oracle.step(st[0], st[1], st[2], 0)
+
+    threads = [threading.Thread(target=work, args=(st,)) for st in states]
+    for t in threads:
+        t.start()
+    gate.wait()
+    t0 = time.perf_counter()
+    for t in threads:
+        t.join()
+    dtn = time.perf_counter() - t0
+    return {"value": nthr * svu / dtn, "unit": "svu/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{nthr} independent 32^3 M=2048 chains, one FP64 proposal each on its "
+                      f"own host thread, {dtn:.1f} s wall; svu counted as N*7*M/2 per proposal",
+            "mc_spin_updates_per_s": nthr / dtn,
+            "single_core": {"value": svu / dt1, "unit": "svu/s", "cores": 1,
+                            "mc_spin_updates_per_s": 1.0 / dt1,
+                            "sample": f"1 proposal of one 32^3 M=2048 chain, {dt1:.1f} s"},
+            "host": host_cpu()}
+
+
+def mixed_batch(g, torch, dev, n_prop: int = 2):
+    """One 64^3 chain (M = 4096) and eight 32^3 chains (M = 2048) in one
+    batch, FP32 recursion, T = 0.05, uniform-sphere starts from seed 11:
+    n_prop timed batched proposals after one warm-up proposal."""
+    chs = [g.Chain(g.Params(L=64, M=4096, beta=20.0, precision=g.FP32_ACC64, seed=11,
+                            chain_id=0), device=dev)]
+    for c in range(8):
+        chs.append(g.Chain(g.Params(L=32, M=2048, beta=20.0, precision=g.FP32_ACC64, seed=11,
+                                    chain_id=1 + c), device=dev))
+    for ch in chs:
+        ch.init_spins(g.INIT_RANDOM)
+    b = g.Batch(chs)
+    ppt = b.autotune(4)
+    b.step(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms_tot, nl_tot = 0.0, 0
+    e0.record(b.stream)
+    for _ in range(n_prop):
+        b.step(1)
+        ms, nl = b.step_timing()
+        ms_tot += ms
+        nl_tot += nl
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3
+    svu = sum(ch.p.L ** 3 * 7 * (ch.p.M // 2) for ch in chs)
+    step_bytes = 0
+    for ch in chs:
+        bps, ns = ch.step_bytes()
+        step_bytes += bps * ns
+    b.close()
+    return {"workload": "one 64^3 chain (M=4096) + eight 32^3 chains (M=2048), FP32 recursion, "
+                        "T=0.05, uniform-sphere starts (seed 11)",
+            "proposals_per_chain": n_prop, "ms_per_batched_proposal": 1e3 * dt / n_prop,
+            "svu_per_s": n_prop * svu / dt, "mc_spin_updates_per_s": n_prop * len(chs) / dt,
+            "pairs_per_thread": ppt,
+            "step_kernel": {"launches": nl_tot, "avg_launch_us": 1e3 * ms_tot / max(nl_tot, 1),
+                            "achieved_GBs": n_prop * step_bytes / (ms_tot / 1e3) / 1e9}}
 
 
 def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
@@ -139,6 +228,29 @@ def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
         flush=True)
 
 
+def copy_sweep(torch):
+    """Read + write bandwidth of a plain device copy whose source and
+    destination together span 16 MiB .. 2 GiB: below the 256 MB last-level
+    cache the repeated copy is served partly from that cache."""
+    for mib in (16, 32, 64, 128, 192, 256, 384, 512, 1024, 2048):
+        n = (mib << 20) // 8                  # float32 elements per buffer (half the span)
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        reps = max(5, (4096 // mib))
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        c1.record()
+        torch.cuda.synchronize()
+        s = c0.elapsed_time(c1) / 1e3
+        print(json.dumps({"mode": "copy_sweep", "span_MiB": mib, "reps": reps,
+                          "GBs": reps * 2 * 4 * n / s / 1e9}), flush=True)
+        del src, dst
+
+
 def chain_sweep(g, torch):
     """Step-kernel time and algorithmic bandwidth of 32^3, M = 2048 batches of
     8..128 chains (FP32 and FP64), both launch shapes: shows where the chains'
@@ -182,6 +294,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
                           "dispatches": 3}), flush=True)
+        return
+    if args.copy_sweep:
+        copy_sweep(torch)
         return
     import paper_1303_6016_amd as g
     import synth
@@ -363,6 +478,9 @@ def main():
                                     "svu_per_s": n1 * svu_per_prop / d1,
                                     "proposals": n1}
         out["batched_vs_fp64_single_speedup"] = out["mc_spin_updates_per_s"] / (n1 / d1)
+
+    if args.mixed:
+        out["mixed_64cubed_plus_8x32cubed"] = mixed_batch(g, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

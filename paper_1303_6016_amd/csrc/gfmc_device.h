@@ -54,12 +54,14 @@ struct Desc {
   double* theta;            // [N]
   double* phi;              // [N]
   void* spin;               // spn<T>[2][half]   (parity, half-row index)
-  void* vec;                // o-slots cpx<T>[2][half], then n-slots six<T>[2][half]
+  void* vec;                // o-slots cpx<T>[2][half], then n-slots: six values per
+                            // [2][half] entry as 16-byte planes (3 FP32 / 6 FP64)
                             // ({o,v}: o-slots, then v-slots cpx<T>[2][half])
   double* part;             // [S][nblk][kNP] ({o,v}: [S][nblk][kNP2])
   double* mom;              // [M][7][7][2]  ({o,v}: [M][3][2])
   double* gscr;             // [4][K][2]
-  void* hop;                // GFMC_HOP_STORED: t_{i, n_d(i)} as six<T>[2][half]
+  void* hop;                // GFMC_HOP_STORED: t_{i, n_d(i)}, [2][half] entries,
+                            // same plane layout as the n-slots
   double* tab;              // per-chain constant tables of the reconstruction:
                             // g[M], pre[K][2], tw[K/2][2], sinth[K], wt[K]
   Ctl* ctl;

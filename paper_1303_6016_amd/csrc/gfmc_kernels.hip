@@ -13,6 +13,8 @@
 //                continuous phase, energy integral (equation "d_seff2"),
 //                Metropolis test and spin update
 //   k_magnetization: |sum_i S_i| / N at the end of a sweep
+#include <type_traits>
+
 #include "gfmc_device.h"
 
 namespace gfmc {
@@ -220,42 +222,61 @@ __device__ inline void st(GLOBAL cpx<double>* p, const cpx<double>& c) {
   d2v v = {c.x, c.y};
   *(GLOBAL d2v*)p = v;
 }
-__device__ inline six<float> ld(const GLOBAL six<float>* p) {
-  const GLOBAL f4v* q = (const GLOBAL f4v*)p;
-  six<float> r;
+// Global storage of six values per site (the n-slots, the stored hopping
+// rows): planes of 16-byte items, item i of plane q at q * stride + i, so a
+// wave's access to one plane is one contiguous run (a 48- or 96-byte record
+// per lane would spread each 16-byte access over three or six times as many
+// cache lines).  FP32: 3 planes, complex values 2q and 2q + 1 in plane q;
+// FP64: 6 planes, value q in plane q.  stride = items per plane (>= 2 half).
+template <typename T>
+struct Planes;
+template <>
+struct Planes<float> {
+  GLOBAL f4v* p;
+  size_t stride;
+  __device__ six<float> ld(size_t i) const {
+    six<float> r;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const f4v v = q[i];
-    r.v[2 * i] = {v.x, v.y};
-    r.v[2 * i + 1] = {v.z, v.w};
+    for (int q = 0; q < 3; ++q) {
+      const f4v v = p[q * stride + i];
+      r.v[2 * q] = {v.x, v.y};
+      r.v[2 * q + 1] = {v.z, v.w};
+    }
+    return r;
   }
-  return r;
-}
-__device__ inline six<double> ld(const GLOBAL six<double>* p) {
-  const GLOBAL d2v* q = (const GLOBAL d2v*)p;
-  six<double> r;
+  __device__ void st(size_t i, const six<float>& r) const {
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    const d2v v = q[i];
-    r.v[i] = {v.x, v.y};
+    for (int q = 0; q < 3; ++q) {
+      f4v v = {r.v[2 * q].x, r.v[2 * q].y, r.v[2 * q + 1].x, r.v[2 * q + 1].y};
+      p[q * stride + i] = v;
+    }
   }
-  return r;
-}
-__device__ inline void st(GLOBAL six<float>* p, const six<float>& r) {
-  GLOBAL f4v* q = (GLOBAL f4v*)p;
+};
+template <>
+struct Planes<double> {
+  GLOBAL d2v* p;
+  size_t stride;
+  __device__ six<double> ld(size_t i) const {
+    six<double> r;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    f4v v = {r.v[2 * i].x, r.v[2 * i].y, r.v[2 * i + 1].x, r.v[2 * i + 1].y};
-    q[i] = v;
+    for (int q = 0; q < 6; ++q) {
+      const d2v v = p[q * stride + i];
+      r.v[q] = {v.x, v.y};
+    }
+    return r;
   }
-}
-__device__ inline void st(GLOBAL six<double>* p, const six<double>& r) {
-  GLOBAL d2v* q = (GLOBAL d2v*)p;
+  __device__ void st(size_t i, const six<double>& r) const {
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    d2v v = {r.v[i].x, r.v[i].y};
-    q[i] = v;
+    for (int q = 0; q < 6; ++q) {
+      d2v v = {r.v[q].x, r.v[q].y};
+      p[q * stride + i] = v;
+    }
   }
+};
+template <typename T>
+__device__ inline Planes<T> planes(void* base, size_t stride) {
+  using I = typename std::conditional<sizeof(T) == 4, f4v, d2v>::type;
+  return Planes<T>{(GLOBAL I*)base, stride};
 }
 
 // One step s >= 1 of |a_s> = c1 Ht'|a_{s-1}> - c2 |a_{s-2}> for the 7 start
@@ -332,11 +353,11 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   const T c1 = FIRST ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
   const GLOBAL spn<T>* sp = (const GLOBAL spn<T>*)D.spin;            // [2][half]
   GLOBAL cpx<T>* vo = (GLOBAL cpx<T>*)D.vec;                         // o-slots [2][half]
-  GLOBAL six<T>* vn = (GLOBAL six<T>*)((GLOBAL cpx<T>*)D.vec + D.N); // n-slots [2][half]
+  const Planes<T> vn = planes<T>((cpx<T>*)D.vec + D.N, D.N);        // n-slots [2][half]
   const GLOBAL spn<T>* sp_o = sp + (size_t)po * half;
   const GLOBAL spn<T>* sp_n = sp + (size_t)pn * half;
   // stored hopping rows t_{i, n_d(i)} (HOPS): six<T>[2][half]
-  const GLOBAL six<T>* hrow = (const GLOBAL six<T>*)D.hop;
+  const Planes<T> hrow = planes<T>(D.hop, D.N);
 
   double x[PPT][16];
 #pragma unroll
@@ -352,7 +373,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
     {
       spn<T> si;
       six<T> row;
-      if (HOPS) row = ld(hrow + (size_t)po * half + h);
+      if (HOPS) row = hrow.ld((size_t)po * half + h);
       else si = ld(sp_o + h);
       T ar = 0, ai = 0;
 #pragma unroll
@@ -388,7 +409,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
     {
       spn<T> si;
       six<T> row;
-      if (HOPS) row = ld(hrow + (size_t)pn * half + h);
+      if (HOPS) row = hrow.ld((size_t)pn * half + h);
       else si = ld(sp_n + h);
       T accr[6], acci[6];
 #pragma unroll
@@ -409,7 +430,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
 #pragma unroll
           for (int e = 0; e < 6; ++e) { an.v[e].x = (nh == sh[e]) ? (T)1 : (T)0; an.v[e].y = 0; }
         } else {
-          an = ld(vn + (size_t)po * half + nh);
+          an = vn.ld((size_t)po * half + nh);
         }
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
@@ -419,7 +440,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
       }
       six<T> out;
       six<T> prev;
-      if (!FIRST) prev = ld(vn + (size_t)pn * half + h);
+      if (!FIRST) prev = vn.ld((size_t)pn * half + h);
 #pragma unroll
       for (int e = 0; e < 6; ++e) {
         out.v[e].x = c1 * accr[e];
@@ -431,7 +452,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
         x[p][2 * e] = (double)out.v[e].x;
         x[p][2 * e + 1] = (double)out.v[e].y;
       }
-      st(vn + (size_t)pn * half + h, out);
+      vn.st((size_t)pn * half + h, out);
       cpx<T> aop;   // a^o_{s-1} at the n-site
       if (FIRST) {
         aop.x = (h == o_half) ? (T)1 : (T)0;
@@ -441,7 +462,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
         six<T> u;
 #pragma unroll
         for (int e = 0; e < 6; ++e) { u.v[e].x = (h == sh[e]) ? (T)1 : (T)0; u.v[e].y = 0; }
-        st(vn + (size_t)po * half + h, u);
+        vn.st((size_t)po * half + h, u);
       } else {
         aop = ld(vo + (size_t)pn * half + h);
       }
@@ -1157,7 +1178,7 @@ __device__ inline void build_row(const Desc& D, int site) {
     const spn<T> sj = sp[(size_t)(par ^ 1) * D.half + nh];
     hop_spinor(si, sj, row.v[d].x, row.v[d].y);
   }
-  ((six<T>*)D.hop)[(size_t)par * D.half + hh] = row;
+  planes<T>(D.hop, D.N).st((size_t)par * D.half + hh, row);
 }
 
 template <typename T>
