@@ -31,12 +31,12 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE (one counter per run), each scaled by what the same counter reads
 # for a plain 1 GiB device copy (FETCH x 1.99996, WRITE x 1.0); valid only for
 # the kernel source they were taken with (sha256 below), else reported as null.
-TRAFFIC_KERNEL_SHA256 = "c8f1b6661c0aac157bec7646dce83d2b10c0128dabfee2b0b8b830261092ca96"
-TRAFFIC_BYTES = {("k_step<float>", 1): 211848869,
-                 ("k_step<float>", 2): 215920410,
+TRAFFIC_KERNEL_SHA256 = "7dba44969514031a44e285ccff6e0ed4fd1a217b9221b7179cd10bbde5a4d912"
+TRAFFIC_BYTES = {("k_step<float>", 1): 213184216,
+                 ("k_step<float>", 2): 217178558,
                  ("k_step_ov<float>", 1): 84127550,
-                 ("k_step_ov<float>", 2): 85345185,
-                 ("k_step<float> stored rows", 2): 285840542}
+                 ("k_step_ov<float>", 2): 85344865,
+                 ("k_step<float> stored rows", 2): 286712490}
 
 
 def parse():
