@@ -175,12 +175,18 @@ def mixed_batch(g, torch, dev, n_prop: int = 2):
                             "achieved_GBs": n_prop * step_bytes / (ms_tot / 1e3) / 1e9}}
 
 
+SERVING_L = (4, 6, 8, 12, 16)
+SERVING_P = (0.3, 0.25, 0.25, 0.15, 0.05)
+
+
 def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
     """Continuous-batching serving run: Poisson arrivals (rate per second,
-    seeded) of chains with L in {4, 6, 8}, M = 64 L (K the next power of two),
-    T uniform in [0.02, 0.2], FP32 recursion, 2 sweeps each; arrivals stop
-    after `seconds`, then the engine drains.  Reports per-sweep latency
-    percentiles overall and per L, queueing delay and throughput."""
+    seeded) of chains with L in {4, 6, 8, 12, 16} (probabilities 0.3, 0.25,
+    0.25, 0.15, 0.05), M = 64 L (K the next power of two), T uniform in
+    [0.02, 0.2], FP32 recursion, 2 sweeps each; arrivals stop after
+    `seconds`, then the engine drains.  L <= 12 runs the LDS-resident kernel,
+    L = 16 the multi-block one.  Reports per-sweep latency percentiles
+    overall and per L, queueing delay and throughput."""
     import numpy as np
     rng = np.random.default_rng(seed)
     eng = g.Engine(0, hbm_budget_bytes=16 << 30, max_slots=64)
@@ -191,7 +197,7 @@ def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
         if now >= seconds:
             break
         if now >= t_next:
-            Lk = int(rng.choice([4, 6, 8]))
+            Lk = int(rng.choice(SERVING_L, p=SERVING_P))
             Mk = 64 * Lk
             Kk = 1 << (Mk - 1).bit_length()
             T = float(rng.uniform(0.02, 0.2))
@@ -210,7 +216,7 @@ def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
     props = sum(r.proposals for r in res)
     svu = sum(r.proposals * (r.L ** 3) * 7 * (r.M // 2) for r in res)
     per_L = {}
-    for Lk in (4, 6, 8):
+    for Lk in SERVING_L:
         sel = np.array([meta.get(int(i)) == Lk for i in ids], dtype=bool)
         if sel.any():
             per_L[str(Lk)] = {"p50_s": float(np.percentile(lat[sel], 50)),
@@ -223,8 +229,9 @@ def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
                             "per_L": per_L, "sweeps": int(len(lat))},
         "queue_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
         "mc_spin_updates_per_s": props / wall, "svu_per_s": svu / wall,
-        "config": {"workload": "Poisson arrivals, L in {4,6,8}, M = 64 L, T ~ U[0.02, 0.2], "
-                               "FP32 recursion, 2 sweeps per request, 16 GiB budget, 64 slots"}}),
+        "config": {"workload": "Poisson arrivals, L in {4,6,8,12,16} w.p. 0.3/0.25/0.25/0.15/0.05, "
+                               "M = 64 L, T ~ U[0.02, 0.2], FP32 recursion, 2 sweeps per request, "
+                               "16 GiB budget, 64 slots"}}),
         flush=True)
 
 

@@ -218,7 +218,8 @@ gfmc_status gfmc_batch_use_graph(gfmc_batch* batch, int32_t enable);
  * chain must fit: 72 B/site FP32, 144 B/site FP64 within 140 KB, i.e. up to
  * 12^3 FP32 / 8^3 FP64, 7 site start vectors, recomputed hoppings).  Results
  * do not depend on the shape beyond the order of the moment partial sums.
- * Single chains use shape 0 whenever they fit. */
+ * Single chains use shape 0 when they fit and have at most 256 site pairs
+ * (L <= 8), else shape 1. */
 gfmc_status gfmc_batch_set_tuning(gfmc_batch* batch, int32_t pairs_per_thread);
 
 /* Time each step-kernel launch shape over `trial_steps` Chebyshev steps on the

@@ -123,7 +123,13 @@ static int blocks_of(const Derived& d, int ppt) {
 // The LDS-resident kernel holds spinors and the 7 bipartite vectors of a
 // chain: 72 B per site (FP32) or 144 B (FP64).
 static size_t resident_lds(const Derived& d) { return (size_t)d.N * (d.fp32 ? 72 : 144); }
-bool resident_ok(const Derived& d) { return !d.ov && !d.hops && resident_lds(d) <= (size_t)kResidentLds; }
+bool resident_fits(const Derived& d) {
+  return !d.ov && !d.hops && resident_lds(d) <= (size_t)kResidentLds;
+}
+// Preferred (single chains, serving groups) only while one pass of the
+// workgroup covers the lattice: at more site pairs the multi-block kernel,
+// spread over many CUs, is faster per step than one workgroup looping.
+bool resident_ok(const Derived& d) { return resident_fits(d) && d.half <= kStepThreads; }
 
 gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   std::vector<Desc> ds(sorted.size());
@@ -147,7 +153,7 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   bool ok = P.ppt == 0;
   P.res_lds = 0;
   for (auto* c : sorted) {
-    ok = ok && resident_ok(c->d);
+    ok = ok && resident_fits(c->d);
     P.res_lds = std::max(P.res_lds, resident_lds(c->d));
   }
   P.resident = ok ? 1 : 0;
@@ -725,7 +731,7 @@ gfmc_status gfmc_batch_set_tuning(gfmc_batch* b, int32_t pairs_per_thread) {
   Plan& P = b->plan;
   if (pairs_per_thread == 0)
     for (auto* c : b->sorted)
-      if (!resident_ok(c->d))
+      if (!resident_fits(c->d))
         return fail(GFMC_EINVAL, "shape 0 needs every chain to fit in LDS");
   HIPCHK(hipStreamSynchronize(P.stream));
   P.ppt = pairs_per_thread;
@@ -761,7 +767,7 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   bool all_res = true;
-  for (auto* c : b->sorted) all_res = all_res && resident_ok(c->d);
+  for (auto* c : b->sorted) all_res = all_res && resident_fits(c->d);
   for (int ppt : {0, 1, 2}) {
     if (ppt == 0 && !all_res) continue;
     CHK(gfmc_batch_set_tuning(b, ppt));

@@ -85,15 +85,44 @@ struct Request {
 
 }  // namespace
 
-// Chains of one precision x start-vector form x hopping mode share a launch
-// plan; its descriptor table is re-uploaded only when its members change.
-constexpr int kGroups = 8;
+// Chains of one precision x start-vector form x hopping mode x kernel shape
+// (LDS-resident or multi-block) share a launch plan; its descriptor table is
+// re-uploaded only when its members change.  Keeping the shapes apart lets
+// small chains run one launch per proposal while large ones run M/2.
+constexpr int kGroups = 16;
+constexpr int kMaxReps = 64;             // proposals per group and iteration
+constexpr double kConcurrentBlocks = 1024;   // step blocks resident at once (256 CUs)
 struct Group {
   Plan plan;
   std::vector<gfmc_chain*> members;   // plan order (most Chebyshev steps first)
+  std::vector<Request*> reqs;         // the members' requests
+  double cost = 0;                    // relative device time of one proposal
+  int reps = 1;                       // proposals per iteration
 };
 
-static int group_of(const Derived& d) { return d.fp32 | (d.ov << 1) | (d.hops << 2); }
+static int group_of(const Derived& d) {
+  return d.fp32 | (d.ov << 1) | (d.hops << 2) | (resident_ok(d) ? 8 : 0);
+}
+
+// Relative device time of one proposal of a group, counted in passes of one
+// 256-thread block over 256 half-rows for one Chebyshev step: the resident
+// kernel runs one block per chain, side by side, each over all its steps; the
+// multi-block path runs one launch per step over the blocks of the chains
+// still stepping, at least one pass long.
+static double proposal_cost(const Plan& P, const std::vector<gfmc_chain*>& m) {
+  double c = 0;
+  if (P.resident) {
+    for (auto* ch : m)
+      c = std::max(c, (double)ch->d.S * ((ch->d.half + kStepThreads - 1) / kStepThreads));
+    return c;
+  }
+  int nact = P.n;
+  for (int s = 1; s <= P.smax; ++s) {
+    while (nact > 0 && P.S[nact - 1] < s) --nact;
+    c += std::max(1.0, (double)P.blkoff[nact] / kConcurrentBlocks);
+  }
+  return c;
+}
 
 struct gfmc_engine {
   int device = 0;
@@ -101,7 +130,8 @@ struct gfmc_engine {
   int max_slots = 0;
   char* base = nullptr;
   char* plan_mem = nullptr;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;         // admissions, |m|, read-backs
+  hipStream_t gstream[kGroups] = {};    // one per group: groups run side by side
   Arena arena;
   Group groups[kGroups];
   bool members_changed = true;
@@ -150,9 +180,22 @@ static gfmc_result make_result(const Request* r, gfmc_status st, int64_t accepte
 }
 
 // Retire a running request (caller holds no lock; the worker thread only).
+// Wait for all device work of the engine (every group stream and the
+// engine's own stream).
+static hipError_t sync_all(gfmc_engine* E) {
+  hipError_t e = hipSuccess;
+  for (int g = 0; g < kGroups; ++g)
+    if (E->gstream[g]) {
+      const hipError_t eg = hipStreamSynchronize(E->gstream[g]);
+      if (e == hipSuccess) e = eg;
+    }
+  const hipError_t e0 = hipStreamSynchronize(E->stream);
+  return e == hipSuccess ? e0 : e;
+}
+
 static void retire(gfmc_engine* E, Request* r, gfmc_status st) {
   // the chain's last proposals may still be queued: wait before its memory is reused
-  if (hipStreamSynchronize(E->stream) != hipSuccess && st == GFMC_OK) st = GFMC_EDEVICE;
+  if (sync_all(E) != hipSuccess && st == GFMC_OK) st = GFMC_EDEVICE;
   int64_t acc = 0;
   if (r->chain) {
     if (hipMemcpyAsync(&acc, &r->chain->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost,
@@ -178,7 +221,11 @@ static void retire(gfmc_engine* E, Request* r, gfmc_status st) {
 // retired one, so equal pointer lists do not mean equal descriptors).
 static gfmc_status refresh_groups(gfmc_engine* E) {
   std::vector<gfmc_chain*> lists[kGroups];
-  for (auto* r : E->running) lists[group_of(r->d)].push_back(r->chain);
+  for (int g = 0; g < kGroups; ++g) E->groups[g].reqs.clear();
+  for (auto* r : E->running) {
+    lists[group_of(r->d)].push_back(r->chain);
+    E->groups[group_of(r->d)].reqs.push_back(r);
+  }
   for (int g = 0; g < kGroups; ++g) {
     auto& L = lists[g];
     std::stable_sort(L.begin(), L.end(),
@@ -188,17 +235,30 @@ static gfmc_status refresh_groups(gfmc_engine* E) {
     if (L.empty()) continue;
     plan_shape(G.plan, L);
     CHK(upload_plan(G.plan, L));
+    G.cost = proposal_cost(G.plan, L);
   }
   E->members_changed = false;
   return GFMC_OK;
 }
 
-// One proposal for every running chain: one launch sequence per group.
+// One iteration: every group advances its chains by reps proposals, reps
+// about the ratio of the costliest group's proposal to its own (so chains
+// of every size progress at a similar device-time rate), at most kMaxReps
+// and never past a member's next sweep boundary (|m| is taken there).
 static gfmc_status iterate(gfmc_engine* E) {
   if (E->members_changed) CHK(refresh_groups(E));
+  double cmax = 0;
   for (int g = 0; g < kGroups; ++g)
-    if (!E->groups[g].members.empty())
-      CHK(enqueue_proposal(E->groups[g].plan, nullptr, nullptr, true));
+    if (!E->groups[g].members.empty()) cmax = std::max(cmax, E->groups[g].cost);
+  for (int g = 0; g < kGroups; ++g) {
+    Group& G = E->groups[g];
+    if (G.members.empty()) continue;
+    int reps = (int)std::min((double)kMaxReps, std::max(1.0, cmax / std::max(G.cost, 1.0)));
+    for (auto* r : G.reqs)
+      reps = (int)std::min<int64_t>(reps, r->d.N - r->done_props % r->d.N);
+    G.reps = reps;
+    for (int k = 0; k < reps; ++k) CHK(enqueue_proposal(G.plan, nullptr, nullptr, true));
+  }
   return GFMC_OK;
 }
 
@@ -263,7 +323,8 @@ static void worker_main(gfmc_engine* E) {
     // pending admissions or cancellations, and every 8th iteration (so that
     // queued requests are not kept behind a long run of enqueued work).
     bool boundary_now = false, pending = false;
-    for (auto* r : E->running) boundary_now |= ((r->done_props + 1) % r->d.N == 0);
+    for (auto* r : E->running)
+      boundary_now |= ((r->done_props + E->groups[group_of(r->d)].reps) % r->d.N == 0);
     {
       std::lock_guard<std::mutex> g(E->mu);
       pending = !E->queue.empty();
@@ -271,7 +332,7 @@ static void worker_main(gfmc_engine* E) {
     }
     ++since_sync;
     if (st == GFMC_OK && (boundary_now || pending || since_sync >= 8)) {
-      if (hipStreamSynchronize(E->stream) != hipSuccess) st = GFMC_EDEVICE;
+      if (sync_all(E) != hipSuccess) st = GFMC_EDEVICE;
       since_sync = 0;
     }
     if (st != GFMC_OK) {
@@ -285,7 +346,7 @@ static void worker_main(gfmc_engine* E) {
     const double t = E->now();
     std::vector<Request*> boundary;
     for (auto* r : E->running) {
-      r->done_props += 1;
+      r->done_props += E->groups[group_of(r->d)].reps;
       if (r->done_props % r->d.N == 0) boundary.push_back(r);
     }
     if (boundary.empty()) continue;
@@ -341,8 +402,14 @@ gfmc_status gfmc_engine_create(int device, size_t budget, int32_t max_slots, gfm
     delete E;
     return gfmc_fail(GFMC_ENOMEM, "hipMalloc of the HBM budget failed");
   }
-  if (hipMalloc(&E->plan_mem, kGroups * plan_bytes(max_slots)) != hipSuccess ||
-      hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking) != hipSuccess) {
+  bool ok = hipMalloc(&E->plan_mem, kGroups * plan_bytes(max_slots)) == hipSuccess &&
+            hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking) == hipSuccess;
+  for (int g = 0; ok && g < kGroups; ++g)
+    ok = hipStreamCreateWithFlags(&E->gstream[g], hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    for (int g = 0; g < kGroups; ++g)
+      if (E->gstream[g]) (void)hipStreamDestroy(E->gstream[g]);
+    if (E->stream) (void)hipStreamDestroy(E->stream);
     (void)hipFree(E->base);
     if (E->plan_mem) (void)hipFree(E->plan_mem);
     delete E;
@@ -353,11 +420,11 @@ gfmc_status gfmc_engine_create(int device, size_t budget, int32_t max_slots, gfm
   for (int g = 0; g < kGroups; ++g) {
     Plan& P = E->groups[g].plan;
     char* w = E->plan_mem + g * pb;
-    P.stream = E->stream;
+    P.stream = E->gstream[g];
     P.fp32 = g & 1;
     P.ov = (g >> 1) & 1;
     P.hops = (g >> 2) & 1;
-    P.ppt = 0;   // the LDS-resident kernel whenever every member chain fits
+    P.ppt = (g & 8) ? 0 : 1;   // LDS-resident groups, else one site pair per thread
     P.d_desc = (Desc*)w; w += align256((size_t)max_slots * sizeof(Desc));
     P.d_blkoff = (int*)w; w += align256((size_t)(max_slots + 1) * sizeof(int));
     P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * max_slots * sizeof(int32_t));
@@ -483,7 +550,8 @@ gfmc_status gfmc_engine_destroy(gfmc_engine* E) {
   }
   if (E->worker.joinable()) E->worker.join();
   (void)hipSetDevice(E->device);
-  (void)hipStreamSynchronize(E->stream);
+  (void)sync_all(E);
+  for (int g = 0; g < kGroups; ++g) (void)hipStreamDestroy(E->gstream[g]);
   (void)hipStreamDestroy(E->stream);
   (void)hipFree(E->plan_mem);
   (void)hipFree(E->base);

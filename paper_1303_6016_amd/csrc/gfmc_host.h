@@ -105,7 +105,8 @@ struct gfmc_batch {
 
 
 gfmc_status derive(const gfmc_chain_params* p, Derived& d);
-bool resident_ok(const Derived& d);
+bool resident_fits(const Derived& d);   // the LDS-resident kernel can hold the chain
+bool resident_ok(const Derived& d);     // ... and is the preferred shape for it
 Layout layout_of(const Derived& d);
 void fill_desc(gfmc_chain* c);
 gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted);

@@ -82,3 +82,36 @@ def test_engine_budget_and_cancel(g):
     with pytest.raises(g.GfmcError):
         eng.cancel(long_id)
     eng.close()
+
+
+MIXED = [  # L, M, T, precision: LDS-resident (L <= 12 FP32, L <= 8 FP64) and multi-block chains
+    (4, 128, 0.05, 1),
+    (10, 64, 0.1, 0),
+    (12, 64, 0.2, 1),
+    (16, 64, 0.05, 1),
+    (6, 64, 0.02, 0),
+]
+
+
+def test_engine_mixed_kernel_shapes_equal_alone_runs(g):
+    # small chains run several proposals per iteration beside the multi-block
+    # ones; each stops exactly at its sweep boundaries, so |m| per sweep and
+    # the accepted count equal the alone run's
+    eng = g.Engine(0, hbm_budget_bytes=1 << 30, max_slots=8)
+    ids = [eng.submit(g.Params(L=L, M=M, beta=1.0 / T, precision=prec, seed=99, chain_id=i),
+                      init=g.INIT_RANDOM, nsweeps=2)
+           for i, (L, M, T, prec) in enumerate(MIXED)]
+    eng.drain(600)
+    res = {r.request_id: r for r in eng.poll()}
+    eng.close()
+    for i, (L, M, T, prec) in enumerate(MIXED):
+        r = res[ids[i]]
+        ch = g.Chain(g.Params(L=L, M=M, beta=1.0 / T, precision=prec, seed=99, chain_id=i))
+        ch.init_spins(g.INIT_RANDOM)
+        mag, acc = ch.sweep(2)
+        print(f"mixed request {i}: L={L} prec={prec} accepted {r.accepted} alone {acc} "
+              f"|m| {r.magnetization:.12f} alone {mag[-1]:.12f}", flush=True)
+        assert r.status == 0 and r.sweeps == 2 and r.proposals == 2 * L ** 3
+        assert r.accepted == acc
+        assert r.magnetization == mag[-1]
+        assert abs(r.magnetization_mean - mag.mean()) < 1e-15
