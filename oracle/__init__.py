@@ -112,6 +112,8 @@ def lib():
             "orc_phase": (None, [i32, dp, dp]),
             "orc_quadrature": (d, [i32, d, d, d, d, dp]),
             "orc_delta_seff": (d, [P(Params), dp, dp, i32, d, d, dp]),
+            "orc_mixed_moments": (None, [P(Params), dp, dp, i32, d, d, dp]),
+            "orc_delta_seff_mixed": (d, [P(Params), dp, dp, i32, d, d, dp]),
             "orc_propose": (None, [P(Params), dp, dp, i64, P(i32), dp, dp, dp]),
             "orc_step": (None, [P(Params), dp, dp, i64, i32, P(Record)]),
             "orc_sweep": (i64, [P(Params), dp, dp, i64, i32, dp]),
@@ -242,6 +244,24 @@ def delta_seff(m: Model, th, ph, o, th_new, ph_new, with_phase_top=False):
     top = np.zeros(1)
     ds = float(lib().orc_delta_seff(ctypes.byref(p), _dp(th), _dp(ph), o, th_new, ph_new,
                                     _dp(top)))
+    return (ds, float(top[0])) if with_phase_top else ds
+
+
+def mixed_moments(m: Model, th, ph, o, th_new, ph_new):
+    """Diagonal moments <a|T_n(Ht)|a> of the paper's mixed start vectors
+    a = |o>, |v>, |o>+|v>, |o>+i|v>: complex array [4, M]."""
+    p = m.c()
+    mu = np.zeros((4, m.M, 2))
+    lib().orc_mixed_moments(ctypes.byref(p), _dp(th), _dp(ph), o, th_new, ph_new, _dp(mu))
+    return mu[..., 0] + 1j * mu[..., 1]
+
+
+def delta_seff_mixed(m: Model, th, ph, o, th_new, ph_new, with_phase_top=False):
+    """Delta S_eff with G_ov, G_vo from the mixed diagonal Green's functions."""
+    p = m.c()
+    top = np.zeros(1)
+    ds = float(lib().orc_delta_seff_mixed(ctypes.byref(p), _dp(th), _dp(ph), o, th_new, ph_new,
+                                          _dp(top)))
     return (ds, float(top[0])) if with_phase_top else ds
 
 

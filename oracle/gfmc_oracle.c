@@ -349,6 +349,100 @@ double orc_delta_seff(const orc_params* p, const double* th, const double* ph, i
 }
 
 /* ------------------------------------------------------------------------ */
+/* Section 2.2, off-diagonal elements from mixed diagonal elements: the four  */
+/* start vectors |o>, |v>, |o> + |v>, |o> + i|v> (|v> = sum_d delta_d |n_d>), */
+/* their diagonal moments, and G_ov, G_vo from the diagonal Green's          */
+/* functions of the mixed vectors.                                            */
+/* ------------------------------------------------------------------------ */
+
+/* mu[(s * M + n) * 2 + {0,1}] = <a_s|T_n(Ht)|a_s> for the start vectors
+ * a_0 = |o>, a_1 = |v>, a_2 = |o> + |v>, a_3 = |o> + i|v>, from the
+ * definition: plain three-term recursion (equation "recursive") on the full
+ * vector, no doubling.  The imaginary parts vanish up to rounding (Ht is
+ * Hermitian) and are returned for checking. */
+void orc_mixed_moments(const orc_params* p, const double* th, const double* ph, int32_t o,
+                       double th_new, double ph_new, double* mu) {
+  const int32_t L = p->L, N = L * L * L, M = p->M;
+  double delta[12];
+  orc_deltas(p, th, ph, o, th_new, ph_new, delta);
+  int32_t* col = (int32_t*)malloc(sizeof(int32_t) * 6 * (size_t)N);
+  cplx* val = (cplx*)malloc(sizeof(cplx) * 6 * (size_t)N);
+  cplx* st = (cplx*)malloc(sizeof(cplx) * (size_t)N);
+  cplx* a0 = (cplx*)malloc(sizeof(cplx) * (size_t)N);
+  cplx* a1 = (cplx*)malloc(sizeof(cplx) * (size_t)N);
+  cplx* a2 = (cplx*)malloc(sizeof(cplx) * (size_t)N);
+  build_rows(p, th, ph, col, val);
+  const double diag = -p->b / p->a;
+  const cplx co[4] = {1.0, 0.0, 1.0, 1.0};     /* weight of |o> */
+  const cplx cv[4] = {0.0, 1.0, 1.0, I};       /* weight of |v> */
+  for (int32_t s = 0; s < 4; ++s) {
+    for (int32_t i = 0; i < N; ++i) st[i] = 0.0;
+    st[o] += co[s];
+    for (int32_t d = 0; d < 6; ++d)
+      st[orc_neighbor(L, o, d)] += cv[s] * (delta[2 * d] + I * delta[2 * d + 1]);
+    cplx *prev = a0, *cur = a1, *next = a2;
+    for (int32_t i = 0; i < N; ++i) prev[i] = st[i];
+    for (int32_t n = 0; n < M; ++n) {
+      cplx* an;
+      if (n == 0) {
+        an = prev;
+      } else if (n == 1) {
+        apply_ht(N, diag, col, val, prev, cur);
+        an = cur;
+      } else {
+        apply_ht(N, diag, col, val, cur, next);
+        for (int32_t i = 0; i < N; ++i) next[i] = 2.0 * next[i] - prev[i];
+        cplx* tmp = prev; prev = cur; cur = next; next = tmp;
+        an = cur;
+      }
+      cplx m = 0;
+      for (int32_t i = 0; i < N; ++i) m += conj(st[i]) * an[i];
+      mu[2 * ((size_t)s * M + n)] = creal(m);
+      mu[2 * ((size_t)s * M + n) + 1] = cimag(m);
+    }
+  }
+  free(col); free(val); free(st); free(a0); free(a1); free(a2);
+}
+
+/* Delta S_eff through the mixed start vectors: Gt_aa for a = o, v, o+v, o+iv
+ * from their diagonal moments (equation "green_short", direct sum), then
+ *   G_ov = [G_{o+v} - G_oo - G_vv + i (G_oo + G_vv - G_{o+iv})] / 2,
+ *   G_vo = [G_{o+v} - G_oo - G_vv + i (G_{o+iv} - G_oo - G_vv)] / 2,
+ * and the determinant, phase and energy integral as for the site vectors. */
+double orc_delta_seff_mixed(const orc_params* p, const double* th, const double* ph, int32_t o,
+                            double th_new, double ph_new, double* phase_top) {
+  const int32_t M = p->M, K = p->K;
+  double* mu = (double*)malloc(sizeof(double) * 2 * 4 * (size_t)M);
+  double* g = (double*)malloc(sizeof(double) * (size_t)M);
+  double* G = (double*)malloc(sizeof(double) * 2 * 4 * (size_t)K);
+  double* Gx = (double*)malloc(sizeof(double) * 2 * 2 * (size_t)K);
+  double* d = (double*)malloc(sizeof(double) * 2 * (size_t)K);
+  double* phi = (double*)malloc(sizeof(double) * (size_t)K);
+  orc_mixed_moments(p, th, ph, o, th_new, ph_new, mu);
+  for (int32_t i = 0; i < 4 * M; ++i) mu[2 * i + 1] = 0.0;   /* diagonal: real */
+  orc_kernel_coeffs(M, p->kernel, p->lambda, g);
+  for (int32_t s = 0; s < 4; ++s) orc_green(M, K, mu + 2 * (size_t)s * M, g, G + 2 * (size_t)s * K);
+  for (int32_t k = 0; k < K; ++k) {
+    cplx goo = G[2 * k] + I * G[2 * k + 1];
+    cplx gvv = G[2 * ((size_t)K + k)] + I * G[2 * ((size_t)K + k) + 1];
+    cplx gp = G[2 * (2 * (size_t)K + k)] + I * G[2 * (2 * (size_t)K + k) + 1];
+    cplx gi = G[2 * (3 * (size_t)K + k)] + I * G[2 * (3 * (size_t)K + k) + 1];
+    cplx gov = 0.5 * (gp - goo - gvv + I * (goo + gvv - gi));
+    cplx gvo = 0.5 * (gp - goo - gvv + I * (gi - goo - gvv));
+    Gx[2 * k] = creal(gov);
+    Gx[2 * k + 1] = cimag(gov);
+    Gx[2 * ((size_t)K + k)] = creal(gvo);
+    Gx[2 * ((size_t)K + k) + 1] = cimag(gvo);
+  }
+  orc_det(K, p->a, G, Gx, Gx + 2 * (size_t)K, G + 2 * (size_t)K, d);
+  orc_phase(K, d, phi);
+  double ds = orc_quadrature(K, p->beta, p->mu, p->a, p->b, phi);
+  if (phase_top) *phase_top = phi[0];
+  free(mu); free(g); free(G); free(Gx); free(d); free(phi);
+  return ds;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Algorithm 1: proposals, Metropolis, sweeps, magnetization.                 */
 /* ------------------------------------------------------------------------ */
 static void sphere_angles(double ua, double ub, double* th, double* ph) {

@@ -93,6 +93,15 @@ double orc_quadrature(int32_t K, double beta, double mu, double a, double b, con
 double orc_delta_seff(const orc_params* p, const double* th, const double* ph, int32_t o,
                       double th_new, double ph_new, double* phase_top);
 
+/* The paper's mixed start vectors |o>, |v>, |o>+|v>, |o>+i|v> (Section 2.2,
+ * off-diagonal Green's functions from mixed diagonal elements): diagonal
+ * moments mu[4][M][2] by plain recursion on full vectors, and Delta S_eff
+ * with G_ov, G_vo formed from the four diagonal Green's functions. */
+void orc_mixed_moments(const orc_params* p, const double* th, const double* ph, int32_t o,
+                       double th_new, double ph_new, double* mu);
+double orc_delta_seff_mixed(const orc_params* p, const double* th, const double* ph, int32_t o,
+                            double th_new, double ph_new, double* phase_top);
+
 /* Proposal draw for counter value `index`: site, new angles, acceptance draw. */
 void orc_propose(const orc_params* p, const double* th, const double* ph, int64_t index,
                  int32_t* site, double* th_new, double* ph_new, double* u);

@@ -407,3 +407,55 @@ def test_sweep_resume_is_bit_exact():
     assert np.array_equal(a_th, b_th) and np.array_equal(a_ph, b_ph)
     assert acc2 == acc_a + acc_b and mag2[1] == mag_b[0]
     assert abs(oracle.magnetization(2, *synth.ferro_angles(8)) - 1.0) < 1e-15
+
+
+# ------------------------------------------------- mixed start vectors ----
+def test_mixed_vector_moments_match_exact_diagonalisation():
+    # <a|T_n(Ht)|a> for a = o, v, o+v, o+iv from eigenvectors of the spinor-built
+    # H, with |v> = (H' - H)|o> from two full Hamiltonians
+    L, M = 4, 96
+    m = oracle.Model(L=L, M=M)
+    th, ph = synth.random_angles(m.N, 23)
+    o, tn, pn = 21, 2.3, 4.1
+    th2, ph2 = th.copy(), ph.copy()
+    th2[o], ph2[o] = tn, pn
+    v = (ed.hamiltonian(L, th2, ph2) - ed.hamiltonian(L, th, ph))[:, o]
+    eo = np.zeros(m.N, complex)
+    eo[o] = 1.0
+    e, U = np.linalg.eigh(ed.hamiltonian(L, th, ph) / m.scale_a())
+    T = np.cos(np.arange(M)[:, None] * np.arccos(np.clip(e, -1, 1))[None, :])
+    got = oracle.mixed_moments(m, th, ph, o, tn, pn)
+    for s, a in enumerate([eo, v, eo + v, eo + 1j * v]):
+        w = np.abs(a.conj() @ U) ** 2                   # |<a|l>|^2
+        assert np.abs(got[s] - T @ w).max() < 1e-12, s
+    assert np.abs(got.imag).max() < 1e-13
+
+
+def test_mixed_vector_moments_are_the_polarised_site_moments():
+    # linearity: mu^{o+v} = mu^oo + mu^vv + 2 Re mu^ov, mu^{o+iv} = mu^oo + mu^vv - 2 Im mu^ov,
+    # with mu^ov contracted from the 7x7 site moments (a separate recursion)
+    L, M = 4, 128
+    m = oracle.Model(L=L, M=M)
+    th, ph = synth.random_angles(m.N, 24)
+    o, tn, pn = 50, 0.7, 1.9
+    c = oracle.contract(oracle.moments(m, th, ph, o), oracle.deltas(m, th, ph, o, tn, pn))
+    oo, ov, vv = c[0].real, c[1], c[3].real
+    got = oracle.mixed_moments(m, th, ph, o, tn, pn).real
+    assert np.abs(got[0] - oo).max() < 1e-12
+    assert np.abs(got[1] - vv).max() < 1e-12
+    assert np.abs(got[2] - (oo + vv + 2 * ov.real)).max() < 1e-12
+    assert np.abs(got[3] - (oo + vv - 2 * ov.imag)).max() < 1e-12
+
+
+@pytest.mark.parametrize("kernel,K", [(0, 0), (1, 0), (0, 256)])
+def test_mixed_vector_delta_seff_equals_site_vector_form(kernel, K):
+    # the paper's G_ov / G_vo from mixed diagonal elements give the same Delta S
+    # as the cross moments (exact up to rounding); a sign slip in either formula
+    # changes Delta S at O(1)
+    m = oracle.Model(L=4, M=128, K=K, beta=20.0, kernel=kernel)
+    th, ph = synth.random_angles(m.N, 25)
+    for o, tn, pn in [(5, 2.0, 0.3), (33, 0.2, 5.5), (60, 3.0, 2.0)]:
+        ref = oracle.delta_seff(m, th, ph, o, tn, pn)
+        got = oracle.delta_seff_mixed(m, th, ph, o, tn, pn)
+        assert abs(got - ref) < 1e-11 * max(1.0, abs(ref)), (o, got, ref)
+    assert oracle.delta_seff_mixed(m, th, ph, 12, th[12], ph[12]) == 0.0
