@@ -77,8 +77,17 @@ typedef enum { GFMC_INIT_RANDOM = 0, GFMC_INIT_FM = 1, GFMC_INIT_FM_PLUS_RANDOM 
 /* Start vectors of the recursion: the 7 unit vectors of o and its neighbours
  * (all 7x7 local moments), or the pair {|o>, |v> = Delta|o>} (only the three
  * series mu^{oo}, mu^{vv}, mu^{ov} that the 2x2 determinant needs; 2/7 of the
- * vector work per proposal). */
-typedef enum { GFMC_VECTORS_SITES = 0, GFMC_VECTORS_OV = 1 } gfmc_vectors;
+ * vector work per proposal), or the paper's mixed vectors {|o>, |v>, |o>+|v>,
+ * |o>+i|v>} (Section 2.2: G_ov and G_vo formed from the diagonal Green's
+ * functions of the mixed vectors).  On the bipartite lattice |o> and |v> never
+ * share a sublattice at any step, so the mixed vectors' diagonal moments are
+ * exact linear combinations of the pair's sums: GFMC_VECTORS_MIXED runs the
+ * pair recursion and differs only in the reconstruction. */
+typedef enum {
+  GFMC_VECTORS_SITES = 0,
+  GFMC_VECTORS_OV = 1,
+  GFMC_VECTORS_MIXED = 2
+} gfmc_vectors;
 /* Hopping amplitudes in the Chebyshev step: recomputed from the per-site
  * spinor cache (16 B/site FP32), or read from a stored table of 6 amplitudes
  * per site (48 B/site FP32; the paper stores H in ELLPACK form).  Both give
@@ -163,9 +172,17 @@ gfmc_status gfmc_moments(gfmc_chain* chain, int32_t site, double* mu);
 /* Moments of the pair {|o>, |v>} for moving the spin at `site` to
  * (theta_new, phi_new), no state change: mu[n][s][2] with s = 0: <o|T_n|o>,
  * 1: <v|T_n|v>, 2: <o|T_n|v>, |v> = sum_d Delta_{n_d,o} |n_d>.  Chains created
- * with GFMC_VECTORS_OV only (ESTATE otherwise). */
+ * with GFMC_VECTORS_OV or GFMC_VECTORS_MIXED only (ESTATE otherwise). */
 gfmc_status gfmc_pair_moments(gfmc_chain* chain, int32_t site, double theta_new, double phi_new,
                               double* mu);
+
+/* Diagonal moments of the paper's mixed start vectors (Section 2.2) for moving
+ * the spin at `site` to (theta_new, phi_new), no state change: mu[s][n] (host,
+ * real, 4*M values) = <a_s|T_n(Ht)|a_s> with a_0 = |o>, a_1 = |v>,
+ * a_2 = |o>+|v>, a_3 = |o>+i|v>, |v> = sum_d Delta_{n_d,o} |n_d>.  Chains
+ * created with GFMC_VECTORS_OV or GFMC_VECTORS_MIXED only (ESTATE otherwise). */
+gfmc_status gfmc_mixed_moments(gfmc_chain* chain, int32_t site, double theta_new,
+                               double phi_new, double* mu);
 
 /* Delta S_eff for moving the spin at `site` to (theta_new, phi_new), no state
  * change.  phase_top may be NULL. */

@@ -23,7 +23,7 @@ FP64, FP32_ACC64 = 0, 1
 JACKSON, LORENTZ = 0, 1
 PROPOSE_SPHERE, PROPOSE_CONE = 0, 1
 INIT_RANDOM, INIT_FM, INIT_FM_PLUS_RANDOM = 0, 1, 2
-VECTORS_SITES, VECTORS_OV = 0, 1
+VECTORS_SITES, VECTORS_OV, VECTORS_MIXED = 0, 1, 2
 HOP_RECOMPUTE, HOP_STORED = 0, 1
 
 
@@ -81,6 +81,7 @@ _SIGS = {
     "gfmc_moments": [_vp, _i32, _P(_d)],
     "gfmc_delta_seff": [_vp, _i32, _d, _d, _P(_d), _P(_d)],
     "gfmc_pair_moments": [_vp, _i32, _d, _d, _P(_d)],
+    "gfmc_mixed_moments": [_vp, _i32, _d, _d, _P(_d)],
     "gfmc_step": [_vp, _i32, _P(StepRecord)],
     "gfmc_sweep": [_vp, _i32, _P(_d), _P(_i64)],
     "gfmc_sync": [_vp],
@@ -254,6 +255,12 @@ class Chain:
         out = np.zeros((self.p.M, 3, 2))
         _check(lib().gfmc_pair_moments(self.h, site, theta_new, phi_new, _dptr(out)))
         return out[..., 0] + 1j * out[..., 1]
+
+    def mixed_moments(self, site: int, theta_new: float, phi_new: float) -> np.ndarray:
+        """(4, M) real: <a|T_n|a> for a = |o>, |v>, |o>+|v>, |o>+i|v>."""
+        out = np.zeros((4, self.p.M))
+        _check(lib().gfmc_mixed_moments(self.h, site, theta_new, phi_new, _dptr(out)))
+        return out
 
     def delta_seff(self, site: int, theta_new: float, phi_new: float, with_phase_top=False):
         ds, top = ctypes.c_double(), ctypes.c_double()

@@ -46,7 +46,8 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   if (p->proposal == GFMC_PROPOSE_CONE && !(p->cone_angle > 0 && p->cone_angle <= M_PI))
     return fail(GFMC_EINVAL, "cone_angle must be in (0, pi]");
   if (p->kernel == GFMC_LORENTZ && p->lorentz_lambda < 0) return fail(GFMC_EINVAL, "lambda < 0");
-  if (p->vectors != GFMC_VECTORS_SITES && p->vectors != GFMC_VECTORS_OV)
+  if (p->vectors != GFMC_VECTORS_SITES && p->vectors != GFMC_VECTORS_OV &&
+      p->vectors != GFMC_VECTORS_MIXED)
     return fail(GFMC_EINVAL, "unknown start-vector form");
   if (p->hoppings != GFMC_HOP_RECOMPUTE && p->hoppings != GFMC_HOP_STORED)
     return fail(GFMC_EINVAL, "unknown hopping mode");
@@ -62,7 +63,7 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   while ((1 << d.log2K) < K) ++d.log2K;
   d.nblk = (d.half + kStepThreads - 1) / kStepThreads;
   d.fp32 = p->precision == GFMC_FP32_ACC64;
-  d.ov = p->vectors == GFMC_VECTORS_OV;
+  d.ov = p->vectors == GFMC_VECTORS_OV || p->vectors == GFMC_VECTORS_MIXED;   // pair recursion
   d.hops = p->hoppings == GFMC_HOP_STORED;
   d.a = p->scale_a > 0 ? p->scale_a : 6.0 * p->t / (1.0 - 0.01);
   d.lambda = p->lorentz_lambda > 0 ? p->lorentz_lambda : 4.0;
@@ -444,6 +445,22 @@ gfmc_status gfmc_pair_moments(gfmc_chain* c, int32_t site, double tn, double pn,
   CHK(set_mode(c, 1, site, tn, pn));
   CHK(enqueue_proposal(c->plan, nullptr, nullptr, false));
   HIPCHK(hipMemcpyAsync(mu, c->desc.mom, (size_t)c->d.M * 3 * 16, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return set_mode(c, 0, 0, 0.0, 0.0);
+}
+
+gfmc_status gfmc_mixed_moments(gfmc_chain* c, int32_t site, double tn, double pn, double* mu) {
+  CHK(check_chain(c));
+  if (site < 0 || site >= c->d.N) return fail(GFMC_EINVAL, "site out of range");
+  if (!std::isfinite(tn) || !std::isfinite(pn)) return fail(GFMC_EINVAL, "angles not finite");
+  if (!mu) return fail(GFMC_EINVAL, "mu is NULL");
+  if (!c->d.ov) return fail(GFMC_ESTATE, "chain uses the 7 site start vectors");
+  CHK(set_mode(c, 1, site, tn, pn));
+  CHK(enqueue_proposal(c->plan, nullptr, nullptr, false));
+  // the four series go to the chain's reconstruction scratch ([4][K][2] >= 4 M)
+  HIPCHK(launch_mixed_series(c->plan.d_desc, c->d.M, c->desc.gscr, c->stream));
+  HIPCHK(hipMemcpyAsync(mu, c->desc.gscr, (size_t)4 * c->d.M * 8, hipMemcpyDeviceToHost,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return set_mode(c, 0, 0, 0.0, 0.0);

@@ -22,6 +22,7 @@ hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st);
 hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st);
 hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t st);
 hipError_t launch_tables(const Desc* d, int kmax, hipStream_t st);
+hipError_t launch_mixed_series(const Desc* d, int M, double* out, hipStream_t st);
 }  // namespace gfmc
 
 using namespace gfmc;

@@ -996,6 +996,25 @@ __global__ void k_tables(const Desc* __restrict__ descs) {
 
 // One block per chain.  mode 0: proposal from the counter (Metropolis,
 // update, counter advance); mode 1/2: evaluation only.
+// Diagonal moment n of the mixed start vector q (0 |o>, 1 |v>, 2 |o>+|v>,
+// 3 |o>+i|v>) from the pair moments m3 = (mu^{oo}, mu^{vv}, mu^{ov}) of
+// order n: <o+v|T|o+v> = mu^{oo} + mu^{vv} + 2 Re mu^{ov},
+// <o+iv|T|o+iv> = mu^{oo} + mu^{vv} - 2 Im mu^{ov}.
+__device__ inline double mixed_series(const double2* m3, int q) {
+  const double s = m3[0].x + m3[1].x;
+  return (q == 0) ? m3[0].x : (q == 1) ? m3[1].x : (q == 2) ? s + 2.0 * m3[2].x
+                                                            : s - 2.0 * m3[2].y;
+}
+
+// out[q][n] = mixed_series(mom[n], q) for one chain, n < M.
+__global__ void k_mixed_series(const Desc* __restrict__ descs, double* __restrict__ out) {
+  const Desc& D = descs[0];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 4 * D.M) return;
+  const int q = i / D.M, n = i % D.M;
+  out[i] = mixed_series((const double2*)D.mom + (size_t)n * 3, q);
+}
+
 __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict__ descs,
                                                          const int32_t* __restrict__ force,
                                                          gfmc_step_record* __restrict__ recs) {
@@ -1020,6 +1039,7 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
 
   // Four real series: 0 mu^{oo}, 1 mu^{vv}, 2 Re mu^{ov}, 3 Im mu^{ov};
   // mu^{vo} = conj(mu^{ov}) (Hermitian moments), so G_vo uses the same series.
+  // Mixed start vectors: 0 mu^{oo}, 1 mu^{vv}, 2 mu^{o+v}, 3 mu^{o+iv}.
   for (int q = 0; q < 4; ++q) {
     for (int m = tid; m < K; m += kReconThreads) {
       double val = 0.0;
@@ -1028,6 +1048,8 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
         if (D.vectors == GFMC_VECTORS_OV) {
           const double2* m3 = mom + (size_t)m * 3;
           x = (q == 0) ? m3[0].x : (q == 1) ? m3[1].x : (q == 2) ? m3[2].x : m3[2].y;
+        } else if (D.vectors == GFMC_VECTORS_MIXED) {
+          x = mixed_series(mom + (size_t)m * 3, q);
         } else {
         const double2* mm = mom + (size_t)m * 49;
         if (q == 0) {
@@ -1091,8 +1113,19 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
   for (int k = tid; k < K; k += kReconThreads) {
     const double2 goo = gs[k], gvv = gs[(size_t)K + k], R = gs[2 * (size_t)K + k],
                   I = gs[3 * (size_t)K + k];
-    const double2 p = make_double2(1.0 + ia * (R.x - I.y), ia * (R.y + I.x));   // 1 + G_ov
-    const double2 m = make_double2(1.0 + ia * (R.x + I.y), ia * (R.y - I.x));   // 1 + G_vo
+    double2 p, m;
+    if (D.vectors == GFMC_VECTORS_MIXED) {
+      // G_ov = [A + i (S - G_{o+iv})] / 2, G_vo = [A + i (G_{o+iv} - S)] / 2 with
+      // S = G_oo + G_vv, A = G_{o+v} - S (Section 2.2, mixed diagonal elements)
+      const double2 S = make_double2(goo.x + gvv.x, goo.y + gvv.y);
+      const double2 A = make_double2(R.x - S.x, R.y - S.y);
+      const double2 B = make_double2(I.x - S.x, I.y - S.y);   // G_{o+iv} - S
+      p = make_double2(1.0 + 0.5 * ia * (A.x + B.y), 0.5 * ia * (A.y - B.x));   // 1 + G_ov
+      m = make_double2(1.0 + 0.5 * ia * (A.x - B.y), 0.5 * ia * (A.y + B.x));   // 1 + G_vo
+    } else {
+      p = make_double2(1.0 + ia * (R.x - I.y), ia * (R.y + I.x));   // 1 + G_ov
+      m = make_double2(1.0 + ia * (R.x + I.y), ia * (R.y - I.x));   // 1 + G_vo
+    }
     const double2 pm = cmul(p, m);
     const double2 gg = cmul(goo, gvv);
     buf[k] = make_double2(pm.x - ia * ia * gg.x, pm.y - ia * ia * gg.y);
@@ -1283,6 +1316,11 @@ __global__ void k_magnetization(const Desc* __restrict__ descs, double* __restri
 }
 
 // ------------------------------------------------------------ launchers ---
+hipError_t launch_mixed_series(const Desc* d, int M, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mixed_series, dim3((4 * M + 255) / 256), dim3(256), 0, st, d, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_propose(const Desc* d, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_propose, dim3((n + 63) / 64), dim3(64), 0, st, d, n);
   return hipGetLastError();

@@ -36,7 +36,8 @@ def _bytes(**kw):
                                 dict(L=4, scale_b=0.1), dict(L=4, scale_a=1.0),
                                 dict(L=4, proposal=1, cone_angle=0.0), dict(L=4, precision=5),
                                 dict(L=4, M=16384), dict(L=4, vectors=1, hoppings=1),
-                                dict(L=4, vectors=2), dict(L=4, hoppings=3)])
+                                dict(L=4, vectors=3), dict(L=4, vectors=2, hoppings=1),
+                                dict(L=4, hoppings=3)])
 def test_invalid_parameters_are_rejected(kw):
     import paper_1303_6016_amd as g
     with pytest.raises(g.GfmcError) as e:

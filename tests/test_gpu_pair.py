@@ -104,3 +104,86 @@ def test_pair_batch_alone_vs_mix(g):
         for i in range(len(specs)):
             r, a = recs[q][i], alone[i][q]
             assert (r.site, r.accepted, r.dseff) == (a.site, a.accepted, a.dseff)
+
+
+# ------------------------------------------- the paper's mixed start vectors --
+def mixed(g, L, M, prec, **kw):
+    ch = g.Chain(g.Params(L=L, M=M, precision=prec, vectors=g.VECTORS_MIXED, **kw))
+    m = oracle.Model(L=L, M=M, **{k: v for k, v in kw.items()
+                                  if k in ("beta", "seed", "chain_id", "K", "kernel")})
+    return ch, m
+
+
+@pytest.mark.parametrize("L,M", [(4, 256), (8, 256)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+def test_mixed_moments_match_literal_oracle(g, L, M, prec, tol):
+    # the oracle runs four full-vector recursions on |o>, |v>, |o>+|v>, |o>+i|v>;
+    # the device forms the four series from the pair recursion's sums
+    ch, m = mixed(g, L, M, prec)
+    th, ph = synth.random_angles(m.N, L + 11)
+    ch.set_spins(th, ph)
+    rng = np.random.default_rng(L + 1)
+    for _ in range(2):
+        o = int(rng.integers(m.N))
+        tn, pn = float(np.arccos(rng.uniform(-1, 1))), float(rng.uniform(0, 2 * np.pi))
+        got = ch.mixed_moments(o, tn, pn)
+        ref = oracle.mixed_moments(m, th, ph, o, tn, pn).real
+        scale = np.maximum(1.0, ref[:, :1])          # moments of |v>-weighted vectors vs <a|a>
+        err = (np.abs(got - ref) / scale).max(axis=1)
+        print(f"mixed L={L} M={M} prec={prec} site={o}: err per vector {err}", flush=True)
+        assert err.max() < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
+@pytest.mark.parametrize("kernel,K", [(0, 0), (1, 1024)])
+def test_mixed_delta_seff_matches_literal_oracle(g, prec, tol, kernel, K):
+    ch, m = mixed(g, 8, 512, prec, beta=20.0, kernel=kernel, K=K)
+    th, ph = synth.random_angles(m.N, 6)
+    ch.set_spins(th, ph)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        o = int(rng.integers(m.N))
+        tn, pn = float(np.arccos(rng.uniform(-1, 1))), float(rng.uniform(0, 2 * np.pi))
+        got = ch.delta_seff(o, tn, pn)
+        ref = oracle.delta_seff_mixed(m, th, ph, o, tn, pn)
+        print(f"mixed prec={prec} kernel={kernel} K={K} dS={ref:.6f} err={got - ref:.2e}",
+              flush=True)
+        assert abs(got - ref) < tol
+    assert ch.delta_seff(7, th[7], ph[7]) == 0.0
+
+
+def test_mixed_trajectory_4cubed(g):
+    # teacher-forced trajectory: the mixed reconstruction drives the same chain
+    ch, m = mixed(g, 4, 256, 0, beta=20.0, seed=3)
+    th, ph = oracle.init_spins(m, 0)
+    ch.set_spins(th, ph)
+    for idx in range(m.N):
+        ro = oracle.step(m, th, ph, idx)
+        rg = ch.step(force=ro.accepted)
+        assert rg.site == ro.site and rg.u == ro.u
+        assert abs(rg.dseff - ro.dseff) < 1e-10
+    gth, gph = ch.get_spins()
+    assert np.abs(gth - th).max() < 1e-13 and np.abs(gph - ph).max() < 1e-13
+
+
+def test_mixed_and_pair_chains_in_one_batch(g):
+    # both forms share the pair recursion (one launch per step for the batch)
+    # and differ only in the reconstruction; each equals its alone run
+    specs = [(4, 256, 1), (6, 128, 2), (8, 64, 2), (4, 64, 1)]
+
+    def build():
+        out = []
+        for i, (L, M, vec) in enumerate(specs):
+            ch = g.Chain(g.Params(L=L, M=M, precision=1, vectors=vec, seed=12, chain_id=i,
+                                  beta=10.0))
+            ch.init_spins(g.INIT_RANDOM)
+            out.append(ch)
+        return out
+    alone = [[ch.step() for _ in range(3)] for ch in build()]
+    b = g.Batch(build())
+    recs = b.step(3, records=True)
+    b.close()
+    for q in range(3):
+        for i in range(len(specs)):
+            r, a = recs[q][i], alone[i][q]
+            assert (r.site, r.accepted, r.dseff) == (a.site, a.accepted, a.dseff)
