@@ -175,6 +175,18 @@ def test_trajectory_16cubed_prefix_cone(g):
     print(f"16^3 prefix: forced {forced}", flush=True)
 
 
+@pytest.mark.parametrize("L,M,K", [(4, 256, 512), (10, 256, 1024)])
+def test_trajectory_lorentz_fine_grid(g, L, M, K):
+    # Lorentz kernel (lambda = 4) with a zero-padded K > M energy grid, end to
+    # end: draws, Delta S, Metropolis decisions and spin updates; L = 4 runs the
+    # LDS-resident kernel, L = 10 the multi-block one
+    ch, m = make(g, L, M, 0, seed=8, beta=20.0, K=K, kernel=1, lorentz_lambda=4.0)
+    th, ph = oracle.init_spins(m, 0)
+    ch.set_spins(th, ph)
+    forced = run_forced(g, ch, m, th, ph, 64 if L == 4 else 16, 0)
+    print(f"Lorentz L={L} K={K}: forced {forced}", flush=True)
+
+
 def test_trajectory_fp32(g):
     ch, m = make(g, 8, 256, 1, seed=4, beta=10.0)
     th, ph = synth.random_angles(m.N, 4)

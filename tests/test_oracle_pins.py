@@ -459,3 +459,30 @@ def test_mixed_vector_delta_seff_equals_site_vector_form(kernel, K):
         got = oracle.delta_seff_mixed(m, th, ph, o, tn, pn)
         assert abs(got - ref) < 1e-11 * max(1.0, abs(ref)), (o, got, ref)
     assert oracle.delta_seff_mixed(m, th, ph, 12, th[12], ph[12]) == 0.0
+
+
+# --------------------------------------- damping kernel and energy grid ----
+def test_jackson_beats_lorentz_and_finer_grid_helps_at_large_m():
+    # Method fidelity against ED on 6^3 (beta = 20): the Jackson kernel closes
+    # the phase at the band top and tracks ED several times better than Lorentz
+    # (lambda = 4), whose phase stays open by ~0.2-0.3 rad; K = 4M sharpens the
+    # Jackson integral once M resolves the spectrum (M = 1024)
+    L, beta = 6, 20.0
+    th, ph = synth.random_angles(L ** 3, 1)
+    props = [(17, 0.6, 2.0), (150, 2.5, 4.4)]
+    ex = [ed.exact_dseff(L, th, ph, o, tn, pn, beta) for o, tn, pn in props]
+
+    def err(M, K, kernel):
+        m = oracle.Model(L=L, M=M, K=K, beta=beta, kernel=kernel)
+        e, top = 0.0, 0.0
+        for (o, tn, pn), x in zip(props, ex):
+            ds, t = oracle.delta_seff(m, th, ph, o, tn, pn, with_phase_top=True)
+            e, top = max(e, abs(ds - x)), max(top, abs(t))
+        return e, top
+    ej, tj = err(256, 0, 0)
+    el, tl = err(256, 0, 1)
+    assert tj < 1e-4 and tl > 0.1
+    assert ej < 0.5 * el
+    e1, _ = err(1024, 0, 0)
+    e4, _ = err(1024, 4096, 0)
+    assert e4 < 0.5 * e1
