@@ -141,3 +141,38 @@ def test_64cubed_with_eight_32cubed_chains_in_one_batch(g):
     for r, a in zip(recs, alone):
         assert (r.site, r.u, r.accepted) == (a.site, a.u, a.accepted)
         assert r.dseff == a.dseff
+
+
+@pytest.mark.parametrize("vectors", [0, 1])
+def test_benchmark_batch_sampled_against_oracle(g, vectors):
+    # The benchmark's launch configuration: 64 chains of 32^3, M = 2048, FP32
+    # recursion, T = 0.02..0.2 t, uniform-sphere starts drawn on the device
+    # (seed 7, chain_id = chain index), autotuned launch shape.  One batched
+    # proposal; sampled chains are checked against the oracle one proposal at
+    # a time, the decisions of the sampled chains taken from the oracle.
+    import synth
+    L, M, n = 32, 2048, 64
+    temps = synth.temperature_ladder(n, 0.02, 0.2)
+    chs = [g.Chain(g.Params(L=L, M=M, beta=1.0 / temps[c], precision=1, seed=7, chain_id=c,
+                            vectors=vectors))
+           for c in range(n)]
+    for ch in chs:
+        ch.init_spins(g.INIT_RANDOM)
+    b = g.Batch(chs)
+    ppt = b.autotune(16)
+    sample = [0, 37, 63] if vectors == 0 else [11, 50]
+    force = np.full(n, -1, dtype=np.int32)
+    ref = {}
+    for c in sample:
+        m = oracle.Model(L=L, M=M, beta=1.0 / temps[c], seed=7, chain_id=c)
+        th, ph = oracle.init_spins(m, 0)
+        ref[c] = oracle.step(m, th, ph, 0)
+        force[c] = ref[c].accepted
+    recs = b.step(1, force=force, records=True)[0]
+    b.close()
+    for c in sample:
+        r, o = recs[c], ref[c]
+        print(f"bench batch vectors={vectors} shape={ppt} chain {c}: dS={o.dseff:.8f} "
+              f"err={r.dseff - o.dseff:.2e}", flush=True)
+        assert r.site == o.site and r.u == o.u and r.accepted == o.accepted
+        assert abs(r.dseff - o.dseff) < 2e-5
