@@ -31,12 +31,12 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE (one counter per run), each scaled by what the same counter reads
 # for a plain 1 GiB device copy (FETCH x 1.99996, WRITE x 1.0); valid only for
 # the kernel source they were taken with (sha256 below), else reported as null.
-TRAFFIC_KERNEL_SHA256 = "7dba44969514031a44e285ccff6e0ed4fd1a217b9221b7179cd10bbde5a4d912"
-TRAFFIC_BYTES = {("k_step<float>", 1): 213184216,
-                 ("k_step<float>", 2): 217178558,
+TRAFFIC_KERNEL_SHA256 = "602fbdcd648369b0385e7d8e5b8098be06bf9bef5a915fe3ddcfb0926cf59e46"
+TRAFFIC_BYTES = {("k_step<float>", 1): 213417890,
+                 ("k_step<float>", 2): 217169054,
                  ("k_step_ov<float>", 1): 84127550,
-                 ("k_step_ov<float>", 2): 85344865,
-                 ("k_step<float> stored rows", 2): 286712490}
+                 ("k_step_ov<float>", 2): 85321378,
+                 ("k_step<float> stored rows", 2): 286662123}
 
 
 def parse():
@@ -51,6 +51,8 @@ def parse():
                     help="also time the {o, v} start-vector form on the same workload")
     ap.add_argument("--stored-hops", type=int, default=1,
                     help="also time the stored-hopping A/B variant of the step kernel")
+    ap.add_argument("--small", type=int, default=1,
+                    help="also time the 4^3 and 16^3 FP64 workloads (oracle beside them)")
     ap.add_argument("--mixed", type=int, default=1,
                     help="also time one 64^3 chain with eight 32^3 chains in one batch")
     ap.add_argument("--chain-sweep", action="store_true",
@@ -132,6 +134,71 @@ def cpu_baseline(max_threads: int = 16):
                             "mc_spin_updates_per_s": 1.0 / dt1,
                             "sample": f"1 proposal of one 32^3 M=2048 chain, {dt1:.1f} s"},
             "host": host_cpu()}
+
+
+def small_configs(g, torch, dev):
+    """The two small workloads, FP64, each with the single-thread oracle timed
+    beside it on a few proposals:
+    4^3, M = 256, beta = 20, uniform-sphere starts and proposals, seeds 1-3,
+    two sweeps each (three chains in one batch, LDS-resident kernel);
+    16^3, M = 1024, T = 0.05, ferromagnet with floor(0.1 N) = 409 random
+    sites (seed 42), cap proposals of 0.3 rad: 256 proposals timed, the ten
+    sweeps (40 960 proposals) extrapolated."""
+    import oracle
+    out = {}
+    chs = [g.Chain(g.Params(L=4, M=256, beta=20.0, precision=g.FP64, seed=s, chain_id=0),
+                   device=dev) for s in (1, 2, 3)]
+    for ch in chs:
+        ch.init_spins(g.INIT_RANDOM)
+    b = g.Batch(chs)
+    b.step(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.sweep(2)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3
+    b.close()
+    m = oracle.Model(L=4, M=256, beta=20.0, seed=1, chain_id=0)
+    th, ph = oracle.init_spins(m, 0)
+    t0 = time.perf_counter()
+    for idx in range(32):
+        oracle.step(m, th, ph, idx)
+    do = (time.perf_counter() - t0) / 32
+    svu = 64 * 7 * 128
+    out["4cubed_M256_fp64"] = {
+        "chains": 3, "proposals_per_chain": 128, "wall_s": dt,
+        "proposals_per_s": 3 * 128 / dt, "svu_per_s": 3 * 128 * svu / dt,
+        "oracle_1_thread": {"proposals_per_s": 1 / do, "svu_per_s": svu / do,
+                            "sample": "32 proposals of seed 1"}}
+    ch = g.Chain(g.Params(L=16, M=1024, beta=20.0, precision=g.FP64, seed=42, chain_id=0,
+                          proposal=g.PROPOSE_CONE, cone_angle=0.3), device=dev)
+    ch.init_spins(g.INIT_FM_PLUS_RANDOM, 0.1)
+    b = g.Batch([ch])
+    b.autotune(8)
+    b.step(2)
+    torch.cuda.synchronize()
+    n2 = 256
+    e0.record(b.stream)
+    b.step(n2)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3
+    b.close()
+    m = oracle.Model(L=16, M=1024, beta=20.0, seed=42, chain_id=0, proposal=1, cone=0.3)
+    th, ph = oracle.init_spins(m, 2, 0.1)
+    t0 = time.perf_counter()
+    for idx in range(3):
+        oracle.step(m, th, ph, idx)
+    do = (time.perf_counter() - t0) / 3
+    svu = 4096 * 7 * 512
+    out["16cubed_M1024_fp64_cone"] = {
+        "proposals_timed": n2, "proposals_per_s": n2 / dt, "svu_per_s": n2 * svu / dt,
+        "ten_sweeps_s": 40960 * dt / n2, "ten_sweeps_note": "extrapolated from the timed proposals",
+        "oracle_1_thread": {"proposals_per_s": 1 / do, "svu_per_s": svu / do,
+                            "sample": "3 proposals"}}
+    return out
 
 
 def mixed_batch(g, torch, dev, n_prop: int = 2):
@@ -236,11 +303,11 @@ def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
 
 
 def copy_sweep(torch):
-    """Read + write bandwidth of a plain device copy whose source and
-    destination together span 16 MiB .. 2 GiB: below the 256 MB last-level
-    cache the repeated copy is served partly from that cache."""
+    """Bandwidth of a plain device copy (read + write) and of a read-only
+    reduction (torch sum) over working sets of 16 MiB .. 2 GiB: below the
+    256 MB last-level cache the repeated passes are served partly from it."""
     for mib in (16, 32, 64, 128, 192, 256, 384, 512, 1024, 2048):
-        n = (mib << 20) // 8                  # float32 elements per buffer (half the span)
+        n = (mib << 20) // 8                  # float32 elements per copy buffer (half the span)
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -253,9 +320,23 @@ def copy_sweep(torch):
         c1.record()
         torch.cuda.synchronize()
         s = c0.elapsed_time(c1) / 1e3
-        print(json.dumps({"mode": "copy_sweep", "span_MiB": mib, "reps": reps,
-                          "GBs": reps * 2 * 4 * n / s / 1e9}), flush=True)
         del src, dst
+        # read-only: one buffer spanning the whole working set
+        buf = torch.ones(2 * n, dtype=torch.float32, device="cuda:0")
+        out = torch.empty((), dtype=torch.float32, device="cuda:0")
+        for _ in range(3):
+            torch.sum(buf, dim=(0,), out=out)
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record()
+        for _ in range(reps):
+            torch.sum(buf, dim=(0,), out=out)
+        r1.record()
+        torch.cuda.synchronize()
+        sr = r0.elapsed_time(r1) / 1e3
+        print(json.dumps({"mode": "copy_sweep", "span_MiB": mib, "reps": reps,
+                          "copy_GBs": reps * 2 * 4 * n / s / 1e9,
+                          "read_only_GBs": reps * 8 * n / sr / 1e9}), flush=True)
+        del buf, out
 
 
 def chain_sweep(g, torch):
@@ -488,6 +569,8 @@ def main():
 
     if args.mixed:
         out["mixed_64cubed_plus_8x32cubed"] = mixed_batch(g, torch, dev)
+    if args.small:
+        out["small_configs"] = small_configs(g, torch, dev)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
