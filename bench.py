@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--stored-hops", type=int, default=1,
                     help="also time the stored-hopping A/B variant of the step kernel")
     ap.add_argument("--small", type=int, default=1,
-                    help="also time the 4^3 and 16^3 FP64 workloads (oracle beside them)")
+                    help="also time the 4^3 and 16^3 FP64 workloads")
     ap.add_argument("--mixed", type=int, default=1,
                     help="also time one 64^3 chain with eight 32^3 chains in one batch")
     ap.add_argument("--chain-sweep", action="store_true",
@@ -93,7 +93,8 @@ def cpu_baseline(max_threads: int = 16):
     """The FP64 oracle on a bounded sample of the same workload (32^3,
     M = 2048, uniform-sphere starts, seed 7): one proposal on one thread,
     then one independent chain per host core (at most max_threads), one
-    proposal each, run concurrently -- the chain-per-core decomposition.
+    proposal each, run concurrently -- the chain-per-core decomposition;
+    plus a few single-thread proposals of the 4^3 and 16^3 workloads.
     The oracle is C called through ctypes, which releases the GIL, so the
     threads run in parallel."""
     import threading
@@ -126,6 +127,21 @@ def cpu_baseline(max_threads: int = 16):
     for t in threads:
         t.join()
     dtn = time.perf_counter() - t0
+    # the small workloads, single thread, a few proposals each
+    per = {}
+    for key, kw, mode, frac, nprop in (
+            ("4cubed_M256", dict(L=4, M=256, beta=20.0, seed=1, chain_id=0), 0, 0.0, 32),
+            ("16cubed_M1024_cone", dict(L=16, M=1024, beta=20.0, seed=42, chain_id=0, proposal=1,
+                                        cone=0.3), 2, 0.1, 3)):
+        mk = oracle.Model(**kw)
+        tk, pk = oracle.init_spins(mk, mode, frac)
+        t0 = time.perf_counter()
+        for idx in range(nprop):
+            oracle.step(mk, tk, pk, idx)
+        dk = (time.perf_counter() - t0) / nprop
+        sv = mk.N * 7 * (mk.M // 2)
+        per[key] = {"proposals_per_s": 1.0 / dk, "svu_per_s": sv / dk, "cores": 1,
+                    "sample": f"{nprop} proposals"}
     return {"value": nthr * svu / dtn, "unit": "svu/s", "cores": nthr, "kind": "oracle",
             "sample": f"{nthr} independent 32^3 M=2048 chains, one FP64 proposal each on its "
                       f"own host thread, {dtn:.1f} s wall; svu counted as N*7*M/2 per proposal",
@@ -133,18 +149,18 @@ def cpu_baseline(max_threads: int = 16):
             "single_core": {"value": svu / dt1, "unit": "svu/s", "cores": 1,
                             "mc_spin_updates_per_s": 1.0 / dt1,
                             "sample": f"1 proposal of one 32^3 M=2048 chain, {dt1:.1f} s"},
+            "small_workloads_1_thread": per,
             "host": host_cpu()}
 
 
 def small_configs(g, torch, dev):
-    """The two small workloads, FP64, each with the single-thread oracle timed
-    beside it on a few proposals:
+    """The two small workloads, FP64 (the oracle's figures for them are in
+    the cpu_baseline leg):
     4^3, M = 256, beta = 20, uniform-sphere starts and proposals, seeds 1-3,
     two sweeps each (three chains in one batch, LDS-resident kernel);
     16^3, M = 1024, T = 0.05, ferromagnet with floor(0.1 N) = 409 random
     sites (seed 42), cap proposals of 0.3 rad: 256 proposals timed, the ten
     sweeps (40 960 proposals) extrapolated."""
-    import oracle
     out = {}
     chs = [g.Chain(g.Params(L=4, M=256, beta=20.0, precision=g.FP64, seed=s, chain_id=0),
                    device=dev) for s in (1, 2, 3)]
@@ -160,18 +176,10 @@ def small_configs(g, torch, dev):
     torch.cuda.synchronize()
     dt = e0.elapsed_time(e1) / 1e3
     b.close()
-    m = oracle.Model(L=4, M=256, beta=20.0, seed=1, chain_id=0)
-    th, ph = oracle.init_spins(m, 0)
-    t0 = time.perf_counter()
-    for idx in range(32):
-        oracle.step(m, th, ph, idx)
-    do = (time.perf_counter() - t0) / 32
     svu = 64 * 7 * 128
     out["4cubed_M256_fp64"] = {
         "chains": 3, "proposals_per_chain": 128, "wall_s": dt,
-        "proposals_per_s": 3 * 128 / dt, "svu_per_s": 3 * 128 * svu / dt,
-        "oracle_1_thread": {"proposals_per_s": 1 / do, "svu_per_s": svu / do,
-                            "sample": "32 proposals of seed 1"}}
+        "proposals_per_s": 3 * 128 / dt, "svu_per_s": 3 * 128 * svu / dt}
     ch = g.Chain(g.Params(L=16, M=1024, beta=20.0, precision=g.FP64, seed=42, chain_id=0,
                           proposal=g.PROPOSE_CONE, cone_angle=0.3), device=dev)
     ch.init_spins(g.INIT_FM_PLUS_RANDOM, 0.1)
@@ -186,18 +194,10 @@ def small_configs(g, torch, dev):
     torch.cuda.synchronize()
     dt = e0.elapsed_time(e1) / 1e3
     b.close()
-    m = oracle.Model(L=16, M=1024, beta=20.0, seed=42, chain_id=0, proposal=1, cone=0.3)
-    th, ph = oracle.init_spins(m, 2, 0.1)
-    t0 = time.perf_counter()
-    for idx in range(3):
-        oracle.step(m, th, ph, idx)
-    do = (time.perf_counter() - t0) / 3
     svu = 4096 * 7 * 512
     out["16cubed_M1024_fp64_cone"] = {
         "proposals_timed": n2, "proposals_per_s": n2 / dt, "svu_per_s": n2 * svu / dt,
-        "ten_sweeps_s": 40960 * dt / n2, "ten_sweeps_note": "extrapolated from the timed proposals",
-        "oracle_1_thread": {"proposals_per_s": 1 / do, "svu_per_s": svu / do,
-                            "sample": "3 proposals"}}
+        "ten_sweeps_s": 40960 * dt / n2, "ten_sweeps_note": "extrapolated from the timed proposals"}
     return out
 
 
