@@ -486,3 +486,22 @@ def test_jackson_beats_lorentz_and_finer_grid_helps_at_large_m():
     e1, _ = err(1024, 0, 0)
     e4, _ = err(1024, 4096, 0)
     assert e4 < 0.5 * e1
+
+
+# ----------------------------------------------------- regression fixture ----
+def test_oracle_reproduces_its_frozen_trajectory():
+    # not a pin: guards the oracle against unnoticed changes of its arithmetic
+    # (tests/golden/make_golden.py wrote the file from the oracle alone)
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_trajectory_4cubed.json")
+    ref = json.load(open(path))
+    m = oracle.Model(L=ref["lattice"], M=ref["M"], beta=ref["beta"], seed=ref["seed"],
+                     chain_id=ref["chain_id"])
+    th, ph = oracle.init_spins(m, 0)
+    for rp in ref["proposals"]:
+        r = oracle.step(m, th, ph, rp["index"])
+        assert (r.site, r.u, r.theta_new, r.phi_new, r.accepted) == \
+            (rp["site"], rp["u"], rp["theta_new"], rp["phi_new"], rp["accepted"])
+        assert abs(r.dseff - rp["dseff"]) < 1e-12
+    assert abs(oracle.magnetization(4, th, ph) - ref["magnetization"]) < 1e-14
