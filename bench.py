@@ -27,16 +27,14 @@ T_LO, T_HI = 0.02, 0.2
 SEED = 7
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per step-kernel launch of this workload from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE (one counter per run), each scaled by what the same counter reads
-# for a plain 1 GiB device copy (FETCH x 1.99996, WRITE x 1.0); valid only for
-# the kernel source they were taken with (sha256 below), else reported as null.
-TRAFFIC_KERNEL_SHA256 = "602fbdcd648369b0385e7d8e5b8098be06bf9bef5a915fe3ddcfb0926cf59e46"
-TRAFFIC_BYTES = {("k_step<float>", 1): 213417890,
-                 ("k_step<float>", 2): 217169054,
-                 ("k_step_ov<float>", 1): 84127550,
-                 ("k_step_ov<float>", 2): 85321378,
-                 ("k_step<float> stored rows", 2): 286662123}
+# HBM bytes per step round of this workload (one Chebyshev step of every chain:
+# one launch, or one per lane; the lanes split the same blocks, so the bytes
+# per round do not depend on them) from rocprofv3 FETCH_SIZE / WRITE_SIZE (one
+# counter per run), each scaled by what the same counter reads for a plain
+# 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); valid only for the kernel
+# source they were taken with (sha256 below), else reported as null.
+TRAFFIC_KERNEL_SHA256 = "none"
+TRAFFIC_BYTES = {}
 
 
 def parse():
@@ -213,7 +211,8 @@ def mixed_batch(g, torch, dev, n_prop: int = 2):
     for ch in chs:
         ch.init_spins(g.INIT_RANDOM)
     b = g.Batch(chs)
-    ppt = b.autotune(4)
+    b.autotune(4)
+    ppt, lanes = b.tuning()
     b.step(1)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -237,8 +236,8 @@ def mixed_batch(g, torch, dev, n_prop: int = 2):
                         "T=0.05, uniform-sphere starts (seed 11)",
             "proposals_per_chain": n_prop, "ms_per_batched_proposal": 1e3 * dt / n_prop,
             "svu_per_s": n_prop * svu / dt, "mc_spin_updates_per_s": n_prop * len(chs) / dt,
-            "pairs_per_thread": ppt,
-            "step_kernel": {"launches": nl_tot, "avg_launch_us": 1e3 * ms_tot / max(nl_tot, 1),
+            "pairs_per_thread": ppt, "lanes": lanes,
+            "step_kernel": {"rounds": nl_tot, "avg_round_us": 1e3 * ms_tot / max(nl_tot, 1),
                             "achieved_GBs": n_prop * step_bytes / (ms_tot / 1e3) / 1e9}}
 
 
@@ -351,16 +350,18 @@ def chain_sweep(g, torch):
                 c.init_spins(g.INIT_RANDOM)
             b = g.Batch(chs)
             bps, _ = chs[0].step_bytes()
-            for ppt in (1, 2):
+            for ppt, lanes in ((1, 1), (2, 1), (1, 2), (2, 2)):
+                b.set_lanes(lanes)
                 b.set_tuning(ppt)
                 b.step(1)
                 b.step(2)
                 ms, nl = b.step_timing()
                 us = ms * 1e3 / nl
                 print(json.dumps({"mode": "chain_sweep", "precision": "f32" if prec else "f64",
-                                  "chains": nch, "pairs_per_thread": ppt, "avg_launch_us": us,
+                                  "chains": nch, "pairs_per_thread": ppt,
+                                  "lanes": b.tuning()[1], "avg_round_us": us,
                                   "achieved_GBs": nch * bps / (us * 1e-6) / 1e9,
-                                  "bytes_per_launch": nch * bps}), flush=True)
+                                  "bytes_per_round": nch * bps}), flush=True)
             b.close()
             del chs
             torch.cuda.empty_cache()
@@ -406,7 +407,8 @@ def main():
         ch.init_spins(g.INIT_RANDOM)
         chains.append(ch)
     batch = g.Batch(chains)
-    ppt = batch.autotune(16)
+    batch.autotune(16)
+    ppt, lanes = batch.tuning()
     if args.graph:
         batch.use_graph(True)
     stream = batch.stream
@@ -437,14 +439,19 @@ def main():
     ms_per_step = 1e3 * total_s / args.steps
     value = args.steps * NCHAIN * svu_per_prop / total_s
 
-    # dominant kernel: the Chebyshev step, averaged over every launch in the timed region
-    avg_launch_s = step_ms_total / 1e3 / max(launches_total, 1)
-    bytes_per_launch = NCHAIN * bytes_per_step
-    achieved = bytes_per_launch / avg_launch_s / 1e9
+    # dominant kernel: the Chebyshev step, averaged over every step round in the
+    # timed region (a round is one step of all 64 chains: one launch of
+    # k_step, or with two lanes one launch per lane, the two running at once)
+    avg_round_s = step_ms_total / 1e3 / max(launches_total, 1)
+    bytes_per_round = NCHAIN * bytes_per_step
+    achieved = bytes_per_round / avg_round_s / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes("k_step<float>", ppt),
-            "kernel": "k_step<float>", "avg_launch_us": avg_launch_s * 1e6,
-            "bytes_per_launch": bytes_per_launch}
+            "kernel": "k_step<float>", "lanes": lanes,
+            "round": "one Chebyshev step of all chains" +
+                     (": two concurrent k_step launches, one per lane" if lanes == 2 else
+                      ": one k_step launch"),
+            "avg_round_us": avg_round_s * 1e6, "bytes_per_round": bytes_per_round}
 
     # measured copy bandwidth on this machine (1 GiB device copy, read + write)
     src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
@@ -469,7 +476,7 @@ def main():
         "config": {"workload": "32^3 lattice x 64 chains, M=2048, FP32 recursion / FP64 moment "
                                "sums, T=0.02..0.2 t, uniform-sphere starts (seed 7)",
                    "L": L, "M": M, "chains": NCHAIN, "graph": bool(args.graph),
-                   "pairs_per_thread": ppt},
+                   "pairs_per_thread": ppt, "lanes": lanes},
         "mc_spin_updates_per_s": args.steps * NCHAIN / total_s,
         "step_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "sweep_latency_s": {"p50": float(np.percentile(lat, 50)) * N,
@@ -489,7 +496,8 @@ def main():
             ch.init_spins(g.INIT_RANDOM)
             pch.append(ch)
         pb = g.Batch(pch)
-        pppt = pb.autotune(16)
+        pb.autotune(16)
+        pppt, plan = pb.tuning()
         pb.step(1)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -509,13 +517,13 @@ def main():
         out["pair_form"] = {
             "mc_spin_updates_per_s": nps * NCHAIN / dt,
             "svu_per_s": nps * NCHAIN * N * 2 * (M // 2) / dt,
-            "ms_per_step": 1e3 * dt / nps, "pairs_per_thread": pppt,
+            "ms_per_step": 1e3 * dt / nps, "pairs_per_thread": pppt, "lanes": plan,
             "roofline": {"bound": "hbm", "achieved": NCHAIN * pbytes / pavg / 1e9,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": NCHAIN * pbytes / pavg / 1e9 / HBM_PEAK_GBS,
                          "traffic": traffic_bytes("k_step_ov<float>", pppt),
-                         "kernel": "k_step_ov<float>", "avg_launch_us": pavg * 1e6,
-                         "bytes_per_launch": NCHAIN * pbytes}}
+                         "kernel": "k_step_ov<float>", "lanes": plan,
+                         "avg_round_us": pavg * 1e6, "bytes_per_round": NCHAIN * pbytes}}
         pb.close()
         del pch
 
@@ -530,6 +538,7 @@ def main():
             hch.append(ch)
         hb = g.Batch(hch)
         hb.set_tuning(ppt)
+        hb.set_lanes(lanes)
         hb.step(1)
         torch.cuda.synchronize()
         nps = max(2, args.steps // 4)
@@ -542,10 +551,10 @@ def main():
         hbytes, _ = hch[0].step_bytes()
         havg = ms_tot / 1e3 / max(nl_tot, 1)
         out["stored_hoppings_ab"] = {
-            "kernel": "k_step<float> with stored rows", "avg_launch_us": havg * 1e6,
-            "bytes_per_launch": NCHAIN * hbytes,
+            "kernel": "k_step<float> with stored rows", "pairs_per_thread": ppt, "lanes": lanes,
+            "avg_round_us": havg * 1e6, "bytes_per_round": NCHAIN * hbytes,
             "achieved_GBs": NCHAIN * hbytes / havg / 1e9,
-            "slowdown_vs_recompute": havg / avg_launch_s,
+            "slowdown_vs_recompute": havg / avg_round_s,
             "traffic": traffic_bytes("k_step<float> stored rows", ppt)}
         hb.close()
         del hch

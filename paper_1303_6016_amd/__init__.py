@@ -94,6 +94,8 @@ _SIGS = {
     "gfmc_batch_use_graph": [_vp, _i32],
     "gfmc_batch_step_timing": [_vp, _P(_d), _P(_i64)],
     "gfmc_batch_set_tuning": [_vp, _i32],
+    "gfmc_batch_set_lanes": [_vp, _i32],
+    "gfmc_batch_get_tuning": [_vp, _P(_i32), _P(_i32)],
     "gfmc_batch_autotune": [_vp, _i32, _P(_i32)],
     "gfmc_engine_create": [ctypes.c_int, _sz, _i32, _P(_vp)],
     "gfmc_engine_submit": [_vp, _P(ChainParams), _i32, _d, _i32, _P(ctypes.c_uint64)],
@@ -343,6 +345,16 @@ class Batch:
 
     def set_tuning(self, pairs_per_thread: int):
         _check(lib().gfmc_batch_set_tuning(self.h, pairs_per_thread))
+
+    def set_lanes(self, lanes: int):
+        """1 or 2 step lanes (2: the chains' steps on two forked streams)."""
+        _check(lib().gfmc_batch_set_lanes(self.h, lanes))
+
+    def tuning(self):
+        """(launch shape, lanes) in effect."""
+        ppt, lanes = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().gfmc_batch_get_tuning(self.h, ctypes.byref(ppt), ctypes.byref(lanes)))
+        return ppt.value, lanes.value
 
     def autotune(self, trial_steps: int = 16) -> int:
         v = ctypes.c_int32()

@@ -142,6 +142,10 @@ gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
                         P.stream));
   HIPCHK(hipMemcpyAsync(P.d_blkoff, P.blkoff.data(), P.blkoff.size() * sizeof(int),
                         hipMemcpyHostToDevice, P.stream));
+  if (P.lanes_on == 2)
+    for (int l = 0; l < 2; ++l)
+      HIPCHK(hipMemcpyAsync(P.d_lane_blkoff[l], P.lane_blkoff[l].data(),
+                            P.lane_blkoff[l].size() * sizeof(int), hipMemcpyHostToDevice, P.stream));
   HIPCHK(hipStreamSynchronize(P.stream));
   return GFMC_OK;
 }
@@ -165,6 +169,85 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
     P.kmax = std::max(P.kmax, sorted[i]->d.K);
     P.nmax = std::max(P.nmax, sorted[i]->d.N);
   }
+  // lanes: split at the chain where the work (steps x blocks) passes half
+  P.lanes_on = (P.lanes == 2 && P.n >= 2 && !P.resident && P.d_lane_blkoff[0]) ? 2 : 1;
+  int cut = P.n;
+  if (P.lanes_on == 2) {
+    double tot = 0, acc = 0;
+    for (int i = 0; i < P.n; ++i) tot += (double)P.S[i] * (P.blkoff[i + 1] - P.blkoff[i]);
+    cut = 1;
+    for (int i = 0; i < P.n - 1; ++i) {
+      acc += (double)P.S[i] * (P.blkoff[i + 1] - P.blkoff[i]);
+      cut = i + 1;
+      if (acc >= 0.5 * tot) break;
+    }
+  }
+  P.lane_first[0] = 0;
+  P.lane_n[0] = cut;
+  P.lane_first[1] = cut;
+  P.lane_n[1] = P.n - cut;
+  // both lane tables live in one region of n + 2 ints (batches only)
+  if (P.d_lane_blkoff[0]) P.d_lane_blkoff[1] = P.d_lane_blkoff[0] + P.lane_n[0] + 1;
+  for (int l = 0; l < 2; ++l) {
+    P.lane_blkoff[l].assign(P.lane_n[l] + 1, 0);
+    for (int i = 0; i < P.lane_n[l]; ++i)
+      P.lane_blkoff[l][i + 1] = P.blkoff[P.lane_first[l] + i + 1] - P.blkoff[P.lane_first[l]];
+  }
+}
+
+// The Chebyshev steps s_first..s_last of every chain still stepping: one
+// launch per step on the plan stream, or per lane on the two lane streams.
+gfmc_status enqueue_steps(Plan& P, int s_first, int s_last) {
+  if (P.lanes_on < 2) {
+    int nact = P.n;
+    for (int s = s_first; s <= s_last; ++s) {
+      while (nact > 0 && P.S[nact - 1] < s) --nact;
+      if (nact == 0) break;
+      HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact],
+                         s, P.stream));
+    }
+    return GFMC_OK;
+  }
+  HIPCHK(hipEventRecord(P.fork, P.stream));
+  for (int l = 0; l < 2; ++l) HIPCHK(hipStreamWaitEvent(P.lane_stream[l], P.fork, 0));
+  int nact[2] = {P.lane_n[0], P.lane_n[1]};
+  for (int s = s_first; s <= s_last; ++s)
+    for (int l = 0; l < 2; ++l) {
+      const int f = P.lane_first[l];
+      while (nact[l] > 0 && P.S[f + nact[l] - 1] < s) --nact[l];
+      if (nact[l] == 0) continue;
+      HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc + f, P.d_lane_blkoff[l], nact[l],
+                         P.lane_blkoff[l][nact[l]], s, P.lane_stream[l]));
+    }
+  for (int l = 0; l < 2; ++l) {
+    HIPCHK(hipEventRecord(P.join[l], P.lane_stream[l]));
+    HIPCHK(hipStreamWaitEvent(P.stream, P.join[l], 0));
+  }
+  return GFMC_OK;
+}
+
+// Streams and events of the lanes (default priority), created once.
+static gfmc_status ensure_lanes(Plan& P) {
+  for (int l = 0; l < 2; ++l)
+    if (!P.lane_stream[l]) HIPCHK(hipStreamCreateWithFlags(&P.lane_stream[l], hipStreamNonBlocking));
+  if (!P.fork) HIPCHK(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
+  for (int l = 0; l < 2; ++l)
+    if (!P.join[l]) HIPCHK(hipEventCreateWithFlags(&P.join[l], hipEventDisableTiming));
+  return GFMC_OK;
+}
+
+void release_lanes(Plan& P) {
+  for (int l = 0; l < 2; ++l) {
+    if (P.lane_stream[l]) {
+      (void)hipStreamSynchronize(P.lane_stream[l]);
+      (void)hipStreamDestroy(P.lane_stream[l]);
+    }
+    if (P.join[l]) (void)hipEventDestroy(P.join[l]);
+    P.lane_stream[l] = nullptr;
+    P.join[l] = nullptr;
+  }
+  if (P.fork) (void)hipEventDestroy(P.fork);
+  P.fork = nullptr;
 }
 
 // ------------------------------------------------- one proposal (launches) --
@@ -178,12 +261,7 @@ gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* 
   if (P.resident) {
     HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
   } else {
-    int nact = P.n;
-    for (int s = 1; s <= P.smax; ++s) {
-      while (nact > 0 && P.S[nact - 1] < s) --nact;
-      HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, nact,
-                         P.blkoff[nact], s, P.stream));
-    }
+    CHK(enqueue_steps(P, 1, P.smax));
   }
   if (tm) {
     HIPCHK(hipEventRecord(P.ev[P.ev_used + 1], P.stream));
@@ -559,6 +637,7 @@ gfmc_status gfmc_chain_step_bytes(gfmc_chain* c, double* bytes_per_step, int32_t
 // ---------------------------------------------------------------- batches
 static size_t batch_bytes(int n) {
   return align256((size_t)n * sizeof(Desc)) + align256((size_t)(n + 1) * sizeof(int)) +
+         align256((size_t)(n + 2) * sizeof(int)) +
          align256((size_t)kRecCap * n * sizeof(int32_t)) +
          align256((size_t)kRecCap * n * sizeof(gfmc_step_record)) +
          align256((size_t)kMagCap * n * sizeof(double));
@@ -604,6 +683,8 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
   P.hops = chains[0]->d.hops;
   P.d_desc = (Desc*)w; w += align256((size_t)n * sizeof(Desc));
   P.d_blkoff = (int*)w; w += align256((size_t)(n + 1) * sizeof(int));
+  P.d_lane_blkoff[0] = (int*)w;   // the two lane tables, n + 2 ints (split in plan_shape)
+  w += align256((size_t)(n + 2) * sizeof(int));
   P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * n * sizeof(int32_t));
   P.d_rec = (gfmc_step_record*)w; w += align256((size_t)kRecCap * n * sizeof(gfmc_step_record));
   P.d_mag = (double*)w;
@@ -627,6 +708,7 @@ gfmc_status gfmc_batch_destroy(gfmc_batch* b) {
   if (b->plan.gexec) (void)hipGraphExecDestroy(b->plan.gexec);
   if (b->plan.graph) (void)hipGraphDestroy(b->plan.graph);
   for (hipEvent_t e : b->plan.ev) (void)hipEventDestroy(e);
+  release_lanes(b->plan);
   for (auto* c : b->chains) c->in_batch = false;
   delete b;
   return GFMC_OK;
@@ -761,9 +843,32 @@ gfmc_status gfmc_batch_set_tuning(gfmc_batch* b, int32_t pairs_per_thread) {
   return GFMC_OK;
 }
 
+gfmc_status gfmc_batch_set_lanes(gfmc_batch* b, int32_t lanes) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  if (lanes != 1 && lanes != 2) return fail(GFMC_EINVAL, "lanes must be 1 or 2");
+  Plan& P = b->plan;
+  HIPCHK(hipStreamSynchronize(P.stream));
+  if (lanes == 2) CHK(ensure_lanes(P));
+  P.lanes = lanes;
+  plan_shape(P, b->sorted);
+  CHK(upload_plan(P, b->sorted));
+  const bool g = b->use_graph;
+  drop_graph(P);
+  b->use_graph = false;
+  if (g) return gfmc_batch_use_graph(b, 1);
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_get_tuning(gfmc_batch* b, int32_t* pairs_per_thread, int32_t* lanes) {
+  if (!b || !pairs_per_thread || !lanes) return fail(GFMC_EINVAL, "NULL argument");
+  *pairs_per_thread = b->plan.resident ? 0 : b->plan.ppt;
+  *lanes = b->plan.lanes_on;
+  return GFMC_OK;
+}
+
 // Tuning cache keyed by the batch shape: (precision, number of chains, and
-// the (L, M) of every chain in plan order).
-static std::vector<std::pair<std::vector<int>, int>> g_tune_cache;
+// the (L, M) of every chain in plan order) -> (pairs per thread, lanes).
+static std::vector<std::pair<std::vector<int>, std::pair<int, int>>> g_tune_cache;
 
 gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* chosen) {
   if (!b) return fail(GFMC_EINVAL, "batch is NULL");
@@ -773,12 +878,13 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   for (auto* c : b->sorted) { key.push_back(c->d.L); key.push_back(c->d.M); }
   for (auto& kv : g_tune_cache)
     if (kv.first == key) {
-      if (chosen) *chosen = kv.second;
-      return gfmc_batch_set_tuning(b, kv.second);
+      if (chosen) *chosen = kv.second.first;
+      CHK(gfmc_batch_set_tuning(b, kv.second.first));
+      return gfmc_batch_set_lanes(b, kv.second.second);
     }
   // The step kernel only touches per-proposal scratch (vectors, partials), so
   // trial launches between proposals leave the chains' state unchanged.
-  int best = 1;
+  int best = 1, best_lanes = 1;
   float best_ms = 1e30f;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -787,42 +893,38 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   for (auto* c : b->sorted) all_res = all_res && resident_fits(c->d);
   for (int ppt : {0, 1, 2}) {
     if (ppt == 0 && !all_res) continue;
-    CHK(gfmc_batch_set_tuning(b, ppt));
-    if (ppt == 0) {   // the resident kernel runs every step of a proposal in one launch
-      HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
-      HIPCHK(hipEventRecord(e0, P.stream));
-      HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
-      HIPCHK(hipEventRecord(e1, P.stream));
-      HIPCHK(hipEventSynchronize(e1));
+    for (int lanes : {1, 2}) {
+      if (lanes == 2 && (ppt == 0 || P.n < 2)) continue;
+      CHK(gfmc_batch_set_lanes(b, lanes));
+      CHK(gfmc_batch_set_tuning(b, ppt));
       float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      ms = ms / std::max(1, P.smax) * std::min(P.smax - 1, trial_steps);
-      if (ms < best_ms) { best_ms = ms; best = 0; }
-      continue;
+      if (ppt == 0) {   // the resident kernel runs every step of a proposal in one launch
+        HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
+        HIPCHK(hipEventRecord(e0, P.stream));
+        HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
+        HIPCHK(hipEventRecord(e1, P.stream));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        ms = ms / std::max(1, P.smax) * std::min(P.smax - 1, trial_steps);
+      } else {
+        // a proposal state for the trial (the counter only advances in k_recon)
+        HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
+        CHK(enqueue_steps(P, 1, 1));
+        const int smax = std::max(2, std::min(P.smax, trial_steps + 1));
+        HIPCHK(hipEventRecord(e0, P.stream));
+        CHK(enqueue_steps(P, 2, smax));
+        HIPCHK(hipEventRecord(e1, P.stream));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      }
+      if (ms < best_ms) { best_ms = ms; best = ppt; best_lanes = lanes; }
     }
-    // a proposal state for the trial (the counter only advances in k_recon)
-    HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
-    HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, P.n, P.blkoff[P.n], 1,
-                       P.stream));
-    const int smax = std::max(2, std::min(P.smax, trial_steps + 1));
-    int nact = P.n;
-    HIPCHK(hipEventRecord(e0, P.stream));
-    for (int s = 2; s <= smax; ++s) {
-      while (nact > 0 && P.S[nact - 1] < s) --nact;
-      if (nact == 0) break;
-      HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact],
-                         s, P.stream));
-    }
-    HIPCHK(hipEventRecord(e1, P.stream));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) { best_ms = ms; best = ppt; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  g_tune_cache.push_back({key, best});
+  g_tune_cache.push_back({key, {best, best_lanes}});
   if (chosen) *chosen = best;
+  CHK(gfmc_batch_set_lanes(b, best_lanes));
   return gfmc_batch_set_tuning(b, best);
 }
 

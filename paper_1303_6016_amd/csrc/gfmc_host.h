@@ -72,6 +72,18 @@ struct Plan {
   double* d_mag = nullptr;             // [kMagCap][n]
   std::vector<int> S, blkoff;          // per sorted chain; blkoff has n+1 entries
   hipStream_t stream = nullptr;
+  // Step lanes: with lanes == 2 the sorted chains are split into two
+  // contiguous ranges of about equal work whose Chebyshev steps run on two
+  // streams of the plan, forked from `stream` before the steps and joined
+  // back after them, so that one range's launches fill the other's ramp-up
+  // and tail.  Everything else of a proposal stays on `stream`.
+  int lanes = 1;                       // requested: 1 or 2
+  int lanes_on = 1;                    // in effect (2 only for >= 2 chains, multi-block)
+  int lane_first[2] = {0, 0}, lane_n[2] = {0, 0};
+  std::vector<int> lane_blkoff[2];     // block offsets within each lane (lane_n + 1)
+  int* d_lane_blkoff[2] = {nullptr, nullptr};
+  hipStream_t lane_stream[2] = {nullptr, nullptr};   // created on first use, owned
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
   // timing of the step launches
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
@@ -112,6 +124,8 @@ Layout layout_of(const Derived& d);
 void fill_desc(gfmc_chain* c);
 gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted);
 void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted);
+gfmc_status enqueue_steps(Plan& P, int s_first, int s_last);
+void release_lanes(Plan& P);
 gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* d_rec,
                              bool with_recon);
 gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived& d, void* ws,

@@ -289,6 +289,62 @@ def test_batch_graph_replay_matches_direct(g):
         assert x.get_counter() == y.get_counter() == 5
 
 
+LANE_SPECS = [(16, 256, 0.05), (12, 128, 0.1), (10, 256, 0.2), (14, 64, 0.02), (10, 128, 0.1)]
+
+
+def lane_chains(g):
+    out = []
+    for i, (L, M, T) in enumerate(LANE_SPECS):
+        ch, _ = make(g, L, M, 1, seed=21, chain_id=i, beta=1.0 / T)
+        ch.init_spins(g.INIT_RANDOM)
+        out.append(ch)
+    return out
+
+
+@pytest.mark.parametrize("ppt", [1, 2])
+def test_batch_two_lanes_equal_single_chains(g, ppt):
+    # multi-block chains of five sizes split over two step lanes (streams):
+    # with one site pair per thread the blocks are those of the single chain,
+    # so every record is bit-identical; with two the sums are regrouped
+    alone = [[ch.step() for _ in range(3)] for ch in lane_chains(g)]
+    mixed = lane_chains(g)
+    b = g.Batch(mixed)
+    b.set_tuning(ppt)
+    b.set_lanes(2)
+    assert b.tuning() == (ppt, 2)
+    recs = b.step(3, records=True)
+    for q in range(3):
+        for i in range(len(LANE_SPECS)):
+            r, a = recs[q][i], alone[i][q]
+            assert (r.site, r.u) == (a.site, a.u)
+            if ppt == 1:
+                assert (r.accepted, r.dseff) == (a.accepted, a.dseff)
+            else:
+                assert abs(r.dseff - a.dseff) < 1e-5
+    b.close()
+
+
+def test_batch_graph_replay_with_two_lanes(g):
+    # the captured proposal contains both lane streams (fork and join events);
+    # every replay, with host synchronisation between them, equals direct launches
+    a, b = lane_chains(g), lane_chains(g)
+    ba, bb = g.Batch(a), g.Batch(b)
+    for x in (ba, bb):
+        x.set_tuning(1)
+        x.set_lanes(2)
+    ba.step(4)
+    bb.use_graph(True)
+    for _ in range(4):
+        bb.step(1)
+        bb.chains[0].stream.synchronize()
+    assert bb.tuning() == (1, 2)
+    ba.close()
+    bb.close()
+    for x, y in zip(a, b):
+        assert np.array_equal(x.get_spins()[0], y.get_spins()[0])
+        assert x.get_counter() == y.get_counter() == 4
+
+
 @pytest.mark.parametrize("shape", [1, 2])
 @pytest.mark.parametrize("L,M,prec", [(2, 32, 0), (4, 256, 0), (6, 128, 1)])
 def test_step_kernel_shapes_on_small_lattices(g, shape, L, M, prec):
