@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-single", action="store_true")
     ap.add_argument("--graph", type=int, default=0, help="replay one proposal as a HIP graph")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="PPT,LANES: fix the launch shape and step lanes instead of autotuning")
     ap.add_argument("--pair", type=int, default=1,
                     help="also time the {o, v} start-vector form on the same workload")
     ap.add_argument("--stored-hops", type=int, default=1,
@@ -66,6 +68,16 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def tune(batch, fixed: str):
+    """Autotune the batch, or fix (pairs per thread, lanes) from "PPT,LANES"."""
+    if fixed:
+        ppt, lanes = (int(v) for v in fixed.split(","))
+        batch.set_lanes(lanes)
+        batch.set_tuning(ppt)
+    else:
+        batch.autotune(16)
 
 
 def traffic_bytes(kernel: str, ppt: int):
@@ -411,7 +423,7 @@ def main():
         ch.init_spins(g.INIT_RANDOM)
         chains.append(ch)
     batch = g.Batch(chains)
-    batch.autotune(16)
+    tune(batch, args.tuning)
     ppt, lanes = batch.tuning()
     if args.graph:
         batch.use_graph(True)
@@ -500,7 +512,7 @@ def main():
             ch.init_spins(g.INIT_RANDOM)
             pch.append(ch)
         pb = g.Batch(pch)
-        pb.autotune(16)
+        tune(pb, args.tuning)
         pppt, plan = pb.tuning()
         pb.step(1)
         torch.cuda.synchronize()

@@ -170,7 +170,8 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
     P.nmax = std::max(P.nmax, sorted[i]->d.N);
   }
   // lanes: split at the chain where the work (steps x blocks) passes half
-  P.lanes_on = (P.lanes == 2 && P.n >= 2 && !P.resident && P.d_lane_blkoff[0]) ? 2 : 1;
+  P.lanes_on =
+      (P.lanes == 2 && P.n >= 2 && !P.resident && P.d_lane_blkoff[0] && P.lane_stream[1]) ? 2 : 1;
   int cut = P.n;
   if (P.lanes_on == 2) {
     double tot = 0, acc = 0;
