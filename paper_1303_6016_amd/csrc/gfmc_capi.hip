@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -869,7 +870,9 @@ gfmc_status gfmc_batch_get_tuning(gfmc_batch* b, int32_t* pairs_per_thread, int3
 
 // Tuning cache keyed by the batch shape: (precision, number of chains, and
 // the (L, M) of every chain in plan order) -> (pairs per thread, lanes).
+// Shared by all batches of the process; guarded for callers on several threads.
 static std::vector<std::pair<std::vector<int>, std::pair<int, int>>> g_tune_cache;
+static std::mutex g_tune_mu;
 
 gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* chosen) {
   if (!b) return fail(GFMC_EINVAL, "batch is NULL");
@@ -877,19 +880,31 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   Plan& P = b->plan;
   std::vector<int> key = {P.fp32, P.ov, P.hops, P.n};
   for (auto* c : b->sorted) { key.push_back(c->d.L); key.push_back(c->d.M); }
-  for (auto& kv : g_tune_cache)
-    if (kv.first == key) {
-      if (chosen) *chosen = kv.second.first;
-      CHK(gfmc_batch_set_tuning(b, kv.second.first));
-      return gfmc_batch_set_lanes(b, kv.second.second);
-    }
+  std::pair<int, int> hit(-1, -1);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : g_tune_cache)
+      if (kv.first == key) hit = kv.second;
+  }
+  if (hit.first >= 0) {
+    if (chosen) *chosen = hit.first;
+    CHK(gfmc_batch_set_lanes(b, hit.second));
+    return gfmc_batch_set_tuning(b, hit.first);
+  }
   // The step kernel only touches per-proposal scratch (vectors, partials), so
   // trial launches between proposals leave the chains' state unchanged.
   int best = 1, best_lanes = 1;
   float best_ms = 1e30f;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  struct Events {   // destroyed on every return path
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  HIPCHK(hipEventCreate(&ev.a));
+  HIPCHK(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   bool all_res = true;
   for (auto* c : b->sorted) all_res = all_res && resident_fits(c->d);
   for (int ppt : {0, 1, 2}) {
@@ -921,9 +936,10 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
       if (ms < best_ms) { best_ms = ms; best = ppt; best_lanes = lanes; }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  g_tune_cache.push_back({key, {best, best_lanes}});
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.push_back({key, {best, best_lanes}});
+  }
   if (chosen) *chosen = best;
   CHK(gfmc_batch_set_lanes(b, best_lanes));
   return gfmc_batch_set_tuning(b, best);
