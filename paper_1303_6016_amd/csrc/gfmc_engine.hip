@@ -1,14 +1,18 @@
 // gfmc_engine.hip -- serving engine of the C ABI (include/gfmc.h, "serving"):
 // continuous batching of independent chain requests on one device.
 //
-// A host worker thread owns the device stream.  Each iteration it (1) admits
-// queued requests in arrival order while a slot and a large enough block of
-// the HBM budget are free, (2) retires cancelled requests, (3) rebuilds the
-// launch plan when the set of running chains changed, (4) advances every
-// running chain by one proposal with one batched launch sequence (one launch
-// per Chebyshev step over all chains that still need that step), and (5) at
-// each chain's sweep boundary measures |m| and records the sweep's wall time.
-// Per-chain arithmetic does not depend on which chains share the plan.
+// A host worker thread owns the device streams.  Running chains are grouped
+// by precision x start-vector form x hopping mode x kernel shape (LDS-resident
+// or multi-block); each group has a launch plan and a stream of its own, so
+// groups run side by side.  Each iteration the worker (1) admits queued
+// requests in arrival order while a slot and a large enough block of the HBM
+// budget are free, (2) retires cancelled requests, (3) re-uploads the plans
+// when the set of running chains changed, (4) advances every group by a
+// number of proposals inversely proportional to the estimated device time of
+// one of its proposals (capped, and never past a member's sweep boundary),
+// each proposal one batched launch sequence over the group's chains, and
+// (5) at each chain's sweep boundary measures |m| and records the sweep's wall
+// time.  Per-chain arithmetic does not depend on which chains share a plan.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
