@@ -19,11 +19,16 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gfmc_oracle.c")
-_LIB = os.path.join(_HERE, "libgfmc_oracle.so")
+# GFMC_ORACLE_LIB names an already built library to load instead (the pins'
+# mutation test loads deliberately broken copies this way); build() then
+# leaves it alone.
+_LIB = os.environ.get("GFMC_ORACLE_LIB") or os.path.join(_HERE, "libgfmc_oracle.so")
 
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, single-threaded)."""
+    if os.environ.get("GFMC_ORACLE_LIB"):
+        return _LIB
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-Wall",

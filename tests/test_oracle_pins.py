@@ -505,3 +505,32 @@ def test_oracle_reproduces_its_frozen_trajectory():
             (rp["site"], rp["u"], rp["theta_new"], rp["phi_new"], rp["accepted"])
         assert abs(r.dseff - rp["dseff"]) < 1e-12
     assert abs(oracle.magnetization(4, th, ph) - ref["magnetization"]) < 1e-14
+
+
+def test_magnetization_closed_forms():
+    # |sum_i S_i| / N for configurations with a known result
+    L = 4
+    N = L ** 3
+    half = np.arange(N) < N // 2
+    assert abs(oracle.magnetization(L, np.full(N, np.pi / 2), np.zeros(N)) - 1.0) < 1e-15
+    assert abs(oracle.magnetization(L, np.full(N, np.pi / 2), np.full(N, np.pi / 2)) - 1.0) < 1e-15
+    assert abs(oracle.magnetization(L, np.where(half, 0.0, np.pi), np.zeros(N))) < 1e-15
+    assert abs(oracle.magnetization(L, np.full(N, np.pi / 2), np.where(half, 0.0, np.pi / 2))
+               - math.sqrt(0.5)) < 1e-15
+    ring = 2 * np.pi * np.arange(N) / N
+    assert abs(oracle.magnetization(L, np.full(N, np.pi / 2), ring)) < 1e-14
+
+
+@pytest.mark.parametrize("t,a", [(0.7, 0.0), (0.7, 8.0), (1.3, 9.5)])
+def test_moments_hopping_scale_and_rescaling(t, a):
+    # moments of Ht = H/a with H = -t t_ij for t != 1 and explicit a (a = 0
+    # means the default 6t/(1 - 0.01)): the spinor-built H times t, divided
+    # by the same a, diagonalised
+    L, M = 4, 96
+    m = oracle.Model(L=L, M=M, t=t, a=a)
+    th, ph = synth.random_angles(m.N, 29)
+    o = 18
+    s = oracle.start_sites(L, o)
+    ref = ed.cheb_moments_ed(ed.hamiltonian(L, th, ph, t) / m.scale_a(), s, s, M)
+    assert np.abs(oracle.moments(m, th, ph, o) - ref).max() < 1e-12
+    assert (m.scale_a() == a) if a else abs(m.scale_a() - 6 * t / 0.99) < 1e-15
