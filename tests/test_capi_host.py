@@ -52,3 +52,23 @@ def test_workspace_size_follows_layout():
     N = 32 ** 3
     assert b64 - b32 >= 7 * N * 8 + 2 * N * 4 * 2
     assert b64 > 7 * N * 16
+
+
+def test_null_handles_and_bad_arguments_are_rejected_on_the_host():
+    # these return before any device call, so they run without a GPU
+    import paper_1303_6016_amd as g
+    L = g.lib()
+    i32, d = ctypes.c_int32(), ctypes.c_double()
+    buf = (ctypes.c_double * 8)()
+    EINVAL = g.GFMC_EINVAL
+    assert L.gfmc_batch_set_lanes(None, 2) == EINVAL
+    assert L.gfmc_batch_get_tuning(None, ctypes.byref(i32), ctypes.byref(i32)) == EINVAL
+    assert L.gfmc_batch_set_tuning(None, 1) == EINVAL
+    assert L.gfmc_batch_autotune(None, 4, ctypes.byref(i32)) == EINVAL
+    assert L.gfmc_batch_step(None, 1, None, None) == EINVAL
+    assert L.gfmc_mixed_moments(None, 0, 1.0, 1.0, buf) == EINVAL
+    assert L.gfmc_pair_moments(None, 0, 1.0, 1.0, buf) == EINVAL
+    assert L.gfmc_delta_seff(None, 0, 1.0, 1.0, ctypes.byref(d), ctypes.byref(d)) == EINVAL
+    assert L.gfmc_engine_submit(None, None, 0, 0.0, 1, None) == EINVAL
+    assert L.gfmc_chain_destroy(None) == g.GFMC_OK and L.gfmc_batch_destroy(None) == g.GFMC_OK
+    assert L.gfmc_last_error()

@@ -324,6 +324,20 @@ def test_batch_two_lanes_equal_single_chains(g, ppt):
     b.close()
 
 
+def test_lane_arguments(g):
+    ch, _ = make(g, 10, 64, 1, seed=3)
+    ch.init_spins(g.INIT_RANDOM)
+    b = g.Batch([ch])
+    for bad in (0, 3):
+        with pytest.raises(g.GfmcError) as e:
+            b.set_lanes(bad)
+        assert e.value.status == g.GFMC_EINVAL
+    b.set_lanes(2)                  # a single chain cannot be split: one lane in effect
+    assert b.tuning() == (1, 1)
+    b.step(1)
+    b.close()
+
+
 def test_batch_graph_replay_with_two_lanes(g):
     # the captured proposal contains both lane streams (fork and join events);
     # every replay, with host synchronisation between them, equals direct launches
