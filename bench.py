@@ -64,6 +64,8 @@ def parse():
                     help="step-kernel bandwidth for 8..128 chains of 32^3 (cache residency)")
     ap.add_argument("--serving", type=float, default=0.0,
                     help="run the serving engine for this many seconds of Poisson arrivals")
+    ap.add_argument("--physics", action="store_true",
+                    help="magnetization against temperature on 4^3, 6^3 and 8^3 (M = 256, mu = 0)")
     ap.add_argument("--copy-sweep", action="store_true",
                     help="device-copy bandwidth for working sets of 16 MiB .. 2 GiB")
     ap.add_argument("--copy-probe", action="store_true",
@@ -355,6 +357,34 @@ def copy_sweep(torch):
         del buf, out
 
 
+def physics(g, torch, warm: int = 50, sweeps: int = 200):
+    """Magnetization |m| against temperature (the paper's validation: M = 256,
+    mu = 0): ten temperatures per lattice size, ferromagnetic starts, FP64
+    recursion, one batch per size; `warm` sweeps discarded, then the mean of
+    |m| over `sweeps` sweeps with the error from 10 blocks, and the
+    acceptance rate."""
+    import numpy as np
+    temps = [0.02, 0.03, 0.05, 0.07, 0.1, 0.15, 0.2, 0.3, 0.5, 1.0]
+    for Lk in (4, 6, 8):
+        t0 = time.perf_counter()
+        chs = [g.Chain(g.Params(L=Lk, M=256, beta=1.0 / T, mu=0.0, precision=g.FP64, seed=2013,
+                                chain_id=i)) for i, T in enumerate(temps)]
+        for ch in chs:
+            ch.init_spins(g.INIT_FM)
+        b = g.Batch(chs)
+        b.autotune(4)
+        b.sweep(warm)
+        mags, acc = b.sweep(sweeps)
+        b.close()
+        blocks = mags.reshape(len(temps), 10, -1).mean(axis=2)
+        print(json.dumps({
+            "mode": "physics", "L": Lk, "M": 256, "mu": 0.0, "warmup_sweeps": warm,
+            "sweeps": sweeps, "T": temps, "m_mean": [float(v) for v in mags.mean(axis=1)],
+            "m_err": [float(v) for v in blocks.std(axis=1, ddof=1) / np.sqrt(10)],
+            "acceptance": [float(a) / (sweeps * Lk ** 3) for a in acc],
+            "wall_s": time.perf_counter() - t0}), flush=True)
+
+
 def chain_sweep(g, torch):
     """Step-kernel time and algorithmic bandwidth of 32^3, M = 2048 batches of
     8..128 chains (FP32 and FP64), both launch shapes: shows where the chains'
@@ -411,6 +441,9 @@ def main():
         return
     if args.chain_sweep:
         chain_sweep(g, torch)
+        return
+    if args.physics:
+        physics(g, torch)
         return
 
     dev = torch.device("cuda:0")
