@@ -239,20 +239,20 @@ gfmc_status gfmc_batch_use_graph(gfmc_batch* batch, int32_t enable);
  * (L <= 8), else shape 1. */
 gfmc_status gfmc_batch_set_tuning(gfmc_batch* batch, int32_t pairs_per_thread);
 
-/* Step lanes: 1 (every Chebyshev step one launch on the batch stream) or 2
- * (the chains, in plan order, split into two ranges of about equal work whose
- * steps run on two streams owned by the batch, forked from the batch stream
+/* Step lanes: 1 (every Chebyshev step one launch on the batch stream) to 4
+ * (the chains, in plan order, split into that many ranges of about equal work
+ * whose steps run on streams owned by the batch, forked from the batch stream
  * before the steps of a proposal and joined back after them; the launches of
- * one range fill the ramp-up and tail of the other's).  Work stays ordered on
- * the batch stream; per-chain results do not depend on the lanes.  Two lanes
- * need at least two chains and a multi-block shape (1 or 2), otherwise one
- * lane is used. */
+ * one range fill the ramp-up and tail of the others').  Work stays ordered on
+ * the batch stream; per-chain results do not depend on the lanes.  Lanes need
+ * a multi-block shape (1 or 2) and at most one lane per chain is used.
+ * EINVAL outside 1..4. */
 gfmc_status gfmc_batch_set_lanes(gfmc_batch* batch, int32_t lanes);
 
 /* Launch shape (0, 1, 2) and number of step lanes in effect. */
 gfmc_status gfmc_batch_get_tuning(gfmc_batch* batch, int32_t* pairs_per_thread, int32_t* lanes);
 
-/* Time each step-kernel launch shape with one and two lanes over
+/* Time each step-kernel launch shape with one to four lanes over
  * `trial_steps` Chebyshev steps on the batch's current spins (no change of
  * chain state), keep the fastest, and remember it for later batches of the
  * same shape (precision, number of chains, L and M of each chain).  chosen

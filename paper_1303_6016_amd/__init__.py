@@ -347,7 +347,7 @@ class Batch:
         _check(lib().gfmc_batch_set_tuning(self.h, pairs_per_thread))
 
     def set_lanes(self, lanes: int):
-        """1 or 2 step lanes (2: the chains' steps on two forked streams)."""
+        """1 to 4 step lanes (>= 2: the chains' steps on that many forked streams)."""
         _check(lib().gfmc_batch_set_lanes(self.h, lanes))
 
     def tuning(self):

@@ -143,8 +143,8 @@ gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
                         P.stream));
   HIPCHK(hipMemcpyAsync(P.d_blkoff, P.blkoff.data(), P.blkoff.size() * sizeof(int),
                         hipMemcpyHostToDevice, P.stream));
-  if (P.lanes_on == 2)
-    for (int l = 0; l < 2; ++l)
+  if (P.lanes_on >= 2)
+    for (int l = 0; l < P.lanes_on; ++l)
       HIPCHK(hipMemcpyAsync(P.d_lane_blkoff[l], P.lane_blkoff[l].data(),
                             P.lane_blkoff[l].size() * sizeof(int), hipMemcpyHostToDevice, P.stream));
   HIPCHK(hipStreamSynchronize(P.stream));
@@ -170,30 +170,34 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
     P.kmax = std::max(P.kmax, sorted[i]->d.K);
     P.nmax = std::max(P.nmax, sorted[i]->d.N);
   }
-  // lanes: split at the chain where the work (steps x blocks) passes half
-  P.lanes_on =
-      (P.lanes == 2 && P.n >= 2 && !P.resident && P.d_lane_blkoff[0] && P.lane_stream[1]) ? 2 : 1;
-  int cut = P.n;
-  if (P.lanes_on == 2) {
-    double tot = 0, acc = 0;
-    for (int i = 0; i < P.n; ++i) tot += (double)P.S[i] * (P.blkoff[i + 1] - P.blkoff[i]);
-    cut = 1;
-    for (int i = 0; i < P.n - 1; ++i) {
-      acc += (double)P.S[i] * (P.blkoff[i + 1] - P.blkoff[i]);
-      cut = i + 1;
-      if (acc >= 0.5 * tot) break;
+  // lanes: k contiguous ranges, each closed once the work (steps x blocks)
+  // reaches its share, every lane at least one chain
+  int k = std::min(P.lanes, P.n);
+  if (k < 2 || P.resident || !P.d_lane_blkoff[0] || !P.lane_stream[k - 1]) k = 1;
+  P.lanes_on = k;
+  std::vector<double> work(P.n);
+  double tot = 0;
+  for (int i = 0; i < P.n; ++i) tot += work[i] = (double)P.S[i] * (P.blkoff[i + 1] - P.blkoff[i]);
+  int i = 0;
+  double acc = 0;
+  for (int l = 0; l < k; ++l) {
+    P.lane_first[l] = i;
+    if (l == k - 1) {
+      i = P.n;
+    } else {
+      do {
+        acc += work[i];
+        ++i;
+      } while (i < P.n - (k - 1 - l) && acc < (l + 1) * tot / k);
     }
+    P.lane_n[l] = i - P.lane_first[l];
   }
-  P.lane_first[0] = 0;
-  P.lane_n[0] = cut;
-  P.lane_first[1] = cut;
-  P.lane_n[1] = P.n - cut;
-  // both lane tables live in one region of n + 2 ints (batches only)
-  if (P.d_lane_blkoff[0]) P.d_lane_blkoff[1] = P.d_lane_blkoff[0] + P.lane_n[0] + 1;
-  for (int l = 0; l < 2; ++l) {
+  // the lane tables live in one region of n + kMaxLanes ints (batches only)
+  for (int l = 0; l < k; ++l) {
+    if (P.d_lane_blkoff[0]) P.d_lane_blkoff[l] = P.d_lane_blkoff[0] + P.lane_first[l] + l;
     P.lane_blkoff[l].assign(P.lane_n[l] + 1, 0);
-    for (int i = 0; i < P.lane_n[l]; ++i)
-      P.lane_blkoff[l][i + 1] = P.blkoff[P.lane_first[l] + i + 1] - P.blkoff[P.lane_first[l]];
+    for (int j = 0; j < P.lane_n[l]; ++j)
+      P.lane_blkoff[l][j + 1] = P.blkoff[P.lane_first[l] + j + 1] - P.blkoff[P.lane_first[l]];
   }
 }
 
@@ -210,36 +214,39 @@ gfmc_status enqueue_steps(Plan& P, int s_first, int s_last) {
     }
     return GFMC_OK;
   }
+  const int k = P.lanes_on;
   HIPCHK(hipEventRecord(P.fork, P.stream));
-  for (int l = 0; l < 2; ++l) HIPCHK(hipStreamWaitEvent(P.lane_stream[l], P.fork, 0));
-  int nact[2] = {P.lane_n[0], P.lane_n[1]};
+  for (int l = 0; l < k; ++l) HIPCHK(hipStreamWaitEvent(P.lane_stream[l], P.fork, 0));
+  int nact[kMaxLanes];
+  for (int l = 0; l < k; ++l) nact[l] = P.lane_n[l];
   for (int s = s_first; s <= s_last; ++s)
-    for (int l = 0; l < 2; ++l) {
+    for (int l = 0; l < k; ++l) {
       const int f = P.lane_first[l];
       while (nact[l] > 0 && P.S[f + nact[l] - 1] < s) --nact[l];
       if (nact[l] == 0) continue;
       HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc + f, P.d_lane_blkoff[l], nact[l],
                          P.lane_blkoff[l][nact[l]], s, P.lane_stream[l]));
     }
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < k; ++l) {
     HIPCHK(hipEventRecord(P.join[l], P.lane_stream[l]));
     HIPCHK(hipStreamWaitEvent(P.stream, P.join[l], 0));
   }
   return GFMC_OK;
 }
 
-// Streams and events of the lanes (default priority), created once.
-static gfmc_status ensure_lanes(Plan& P) {
-  for (int l = 0; l < 2; ++l)
-    if (!P.lane_stream[l]) HIPCHK(hipStreamCreateWithFlags(&P.lane_stream[l], hipStreamNonBlocking));
-  if (!P.fork) HIPCHK(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
-  for (int l = 0; l < 2; ++l)
+// Streams and events of `k` lanes (default priority), created once.
+static gfmc_status ensure_lanes(Plan& P, int k) {
+  for (int l = 0; l < k; ++l) {
+    if (!P.lane_stream[l])
+      HIPCHK(hipStreamCreateWithFlags(&P.lane_stream[l], hipStreamNonBlocking));
     if (!P.join[l]) HIPCHK(hipEventCreateWithFlags(&P.join[l], hipEventDisableTiming));
+  }
+  if (!P.fork) HIPCHK(hipEventCreateWithFlags(&P.fork, hipEventDisableTiming));
   return GFMC_OK;
 }
 
 void release_lanes(Plan& P) {
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < kMaxLanes; ++l) {
     if (P.lane_stream[l]) {
       (void)hipStreamSynchronize(P.lane_stream[l]);
       (void)hipStreamDestroy(P.lane_stream[l]);
@@ -639,7 +646,7 @@ gfmc_status gfmc_chain_step_bytes(gfmc_chain* c, double* bytes_per_step, int32_t
 // ---------------------------------------------------------------- batches
 static size_t batch_bytes(int n) {
   return align256((size_t)n * sizeof(Desc)) + align256((size_t)(n + 1) * sizeof(int)) +
-         align256((size_t)(n + 2) * sizeof(int)) +
+         align256((size_t)(n + kMaxLanes) * sizeof(int)) +
          align256((size_t)kRecCap * n * sizeof(int32_t)) +
          align256((size_t)kRecCap * n * sizeof(gfmc_step_record)) +
          align256((size_t)kMagCap * n * sizeof(double));
@@ -685,8 +692,8 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
   P.hops = chains[0]->d.hops;
   P.d_desc = (Desc*)w; w += align256((size_t)n * sizeof(Desc));
   P.d_blkoff = (int*)w; w += align256((size_t)(n + 1) * sizeof(int));
-  P.d_lane_blkoff[0] = (int*)w;   // the two lane tables, n + 2 ints (split in plan_shape)
-  w += align256((size_t)(n + 2) * sizeof(int));
+  P.d_lane_blkoff[0] = (int*)w;   // the lane tables, n + kMaxLanes ints (split in plan_shape)
+  w += align256((size_t)(n + kMaxLanes) * sizeof(int));
   P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * n * sizeof(int32_t));
   P.d_rec = (gfmc_step_record*)w; w += align256((size_t)kRecCap * n * sizeof(gfmc_step_record));
   P.d_mag = (double*)w;
@@ -847,10 +854,10 @@ gfmc_status gfmc_batch_set_tuning(gfmc_batch* b, int32_t pairs_per_thread) {
 
 gfmc_status gfmc_batch_set_lanes(gfmc_batch* b, int32_t lanes) {
   if (!b) return fail(GFMC_EINVAL, "batch is NULL");
-  if (lanes != 1 && lanes != 2) return fail(GFMC_EINVAL, "lanes must be 1 or 2");
+  if (lanes < 1 || lanes > kMaxLanes) return fail(GFMC_EINVAL, "lanes must be 1 to 4");
   Plan& P = b->plan;
   HIPCHK(hipStreamSynchronize(P.stream));
-  if (lanes == 2) CHK(ensure_lanes(P));
+  if (lanes >= 2) CHK(ensure_lanes(P, lanes));
   P.lanes = lanes;
   plan_shape(P, b->sorted);
   CHK(upload_plan(P, b->sorted));
@@ -909,8 +916,8 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   for (auto* c : b->sorted) all_res = all_res && resident_fits(c->d);
   for (int ppt : {0, 1, 2}) {
     if (ppt == 0 && !all_res) continue;
-    for (int lanes : {1, 2}) {
-      if (lanes == 2 && (ppt == 0 || P.n < 2)) continue;
+    for (int lanes = 1; lanes <= kMaxLanes; ++lanes) {
+      if (lanes >= 2 && (ppt == 0 || P.n < lanes)) continue;
       CHK(gfmc_batch_set_lanes(b, lanes));
       CHK(gfmc_batch_set_tuning(b, ppt));
       float ms = 0;

@@ -44,6 +44,8 @@ gfmc_status gfmc_fail(gfmc_status s, const std::string& msg);
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int kMaxLanes = 4;   // step lanes (streams) of a batch
+
 // ------------------------------------------------------- chain layout ----
 struct Derived {
   int L, N, half, M, S, K, log2K, nblk, fp32, ov, hops;
@@ -72,18 +74,18 @@ struct Plan {
   double* d_mag = nullptr;             // [kMagCap][n]
   std::vector<int> S, blkoff;          // per sorted chain; blkoff has n+1 entries
   hipStream_t stream = nullptr;
-  // Step lanes: with lanes == 2 the sorted chains are split into two
-  // contiguous ranges of about equal work whose Chebyshev steps run on two
+  // Step lanes: with lanes = k >= 2 the sorted chains are split into k
+  // contiguous ranges of about equal work whose Chebyshev steps run on k
   // streams of the plan, forked from `stream` before the steps and joined
-  // back after them, so that one range's launches fill the other's ramp-up
-  // and tail.  Everything else of a proposal stays on `stream`.
-  int lanes = 1;                       // requested: 1 or 2
-  int lanes_on = 1;                    // in effect (2 only for >= 2 chains, multi-block)
-  int lane_first[2] = {0, 0}, lane_n[2] = {0, 0};
-  std::vector<int> lane_blkoff[2];     // block offsets within each lane (lane_n + 1)
-  int* d_lane_blkoff[2] = {nullptr, nullptr};
-  hipStream_t lane_stream[2] = {nullptr, nullptr};   // created on first use, owned
-  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+  // back after them, so that one range's launches fill the ramp-up and tail
+  // of the others'.  Everything else of a proposal stays on `stream`.
+  int lanes = 1;                       // requested: 1 .. kMaxLanes
+  int lanes_on = 1;                    // in effect (<= number of chains; 1 for shape 0)
+  int lane_first[kMaxLanes] = {}, lane_n[kMaxLanes] = {};
+  std::vector<int> lane_blkoff[kMaxLanes];   // block offsets within each lane (lane_n + 1)
+  int* d_lane_blkoff[kMaxLanes] = {};
+  hipStream_t lane_stream[kMaxLanes] = {};  // created on first use, owned
+  hipEvent_t fork = nullptr, join[kMaxLanes] = {};
   // timing of the step launches
   std::vector<hipEvent_t> ev;
   int ev_used = 0;
