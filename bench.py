@@ -80,7 +80,7 @@ def tune(batch, fixed: str):
         batch.set_lanes(lanes)
         batch.set_tuning(ppt)
     else:
-        batch.autotune(16)
+        batch.autotune(64)
 
 
 def traffic_bytes(kernel: str, ppt: int):

@@ -930,15 +930,21 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         ms = ms / std::max(1, P.smax) * std::min(P.smax - 1, trial_steps);
       } else {
-        // a proposal state for the trial (the counter only advances in k_recon)
+        // a proposal state for the trial (the counter only advances in k_recon);
+        // the steps are timed twice and the faster pass counts
         HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
         CHK(enqueue_steps(P, 1, 1));
         const int smax = std::max(2, std::min(P.smax, trial_steps + 1));
-        HIPCHK(hipEventRecord(e0, P.stream));
-        CHK(enqueue_steps(P, 2, smax));
-        HIPCHK(hipEventRecord(e1, P.stream));
-        HIPCHK(hipEventSynchronize(e1));
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIPCHK(hipEventRecord(e0, P.stream));
+          CHK(enqueue_steps(P, 2, smax));
+          HIPCHK(hipEventRecord(e1, P.stream));
+          HIPCHK(hipEventSynchronize(e1));
+          float t = 0;
+          HIPCHK(hipEventElapsedTime(&t, e0, e1));
+          ms = std::min(ms, t);
+        }
       }
       if (ms < best_ms) { best_ms = ms; best = ppt; best_lanes = lanes; }
     }
