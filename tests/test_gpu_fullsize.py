@@ -176,3 +176,26 @@ def test_benchmark_batch_sampled_against_oracle(g, vectors):
               f"err={r.dseff - o.dseff:.2e}", flush=True)
         assert r.site == o.site and r.u == o.u and r.accepted == o.accepted
         assert abs(r.dseff - o.dseff) < 2e-5
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 2e-5)])
+def test_64cubed_delta_seff_against_stored_oracle(g, prec, tol):
+    # The oracle's first two proposals of a 64^3, M = 4096 chain (beta = 20,
+    # seed 11), stored by tests/golden/make_golden.py: the oracle needs
+    # minutes per proposal at this size.  Same starts (the oracle's own
+    # initial spins), decisions forced to the oracle's.
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_dseff_64cubed.json")
+    ref = json.load(open(path))
+    m = oracle.Model(L=64, M=4096, beta=20.0, seed=11, chain_id=0)
+    th, ph = oracle.init_spins(m, 0)
+    ch = g.Chain(g.Params(L=64, M=4096, beta=20.0, precision=prec, seed=11, chain_id=0))
+    ch.set_spins(th, ph)
+    for rp in ref["proposals"]:
+        r = ch.step(force=rp["accepted"])
+        print(f"64^3 prec={prec} proposal {rp['index']}: dS={rp['dseff']:.9f} "
+              f"err={r.dseff - rp['dseff']:.2e}", flush=True)
+        assert (r.index, r.site, r.u) == (rp["index"], rp["site"], rp["u"])
+        assert abs(r.theta_new - rp["theta_new"]) <= 4 * np.spacing(max(rp["theta_new"], 1.0))
+        assert abs(r.dseff - rp["dseff"]) < tol
