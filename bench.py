@@ -230,7 +230,7 @@ def mixed_batch(g, torch, dev, n_prop: int = 2):
     for ch in chs:
         ch.init_spins(g.INIT_RANDOM)
     b = g.Batch(chs)
-    b.autotune(4)
+    b.autotune(32)
     ppt, lanes = b.tuning()
     b.step(1)
     torch.cuda.synchronize()
