@@ -64,6 +64,8 @@ def parse():
                     help="step-kernel bandwidth for 8..128 chains of 32^3 (cache residency)")
     ap.add_argument("--serving", type=float, default=0.0,
                     help="run the serving engine for this many seconds of Poisson arrivals")
+    ap.add_argument("--serving-mix", type=str, default="small", choices=sorted(SERVING_MIXES),
+                    help="lattice-size mix of the serving run")
     ap.add_argument("--physics", action="store_true",
                     help="magnetization against temperature on 4^3, 6^3 and 8^3 (M = 256, mu = 0)")
     ap.add_argument("--copy-sweep", action="store_true",
@@ -260,40 +262,63 @@ def mixed_batch(g, torch, dev, n_prop: int = 2):
                             "achieved_GBs": n_prop * step_bytes / (ms_tot / 1e3) / 1e9}}
 
 
-SERVING_L = (4, 6, 8, 12, 16)
-SERVING_P = (0.3, 0.25, 0.25, 0.15, 0.05)
+# serving mixes: lattice sizes, their probabilities, default arrival rate (1/s)
+SERVING_MIXES = {
+    # small chains: L <= 8 on the LDS-resident kernel, 12 and 16 multi-block
+    "small": ((4, 6, 8, 12, 16), (0.3, 0.25, 0.25, 0.15, 0.05), 6.0),
+    # the survey's sizes that can finish a sweep within minutes on one GPU
+    "survey": ((8, 16, 24, 32), (0.4, 0.3, 0.2, 0.1), 0.3),
+}
 
 
-def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
-    """Continuous-batching serving run: Poisson arrivals (rate per second,
-    seeded) of chains with L in {4, 6, 8, 12, 16} (probabilities 0.3, 0.25,
-    0.25, 0.15, 0.05), M = 64 L (K the next power of two), T uniform in
-    [0.02, 0.2], FP32 recursion, 2 sweeps each; arrivals stop after
-    `seconds`, then the engine drains.  L <= 12 runs the LDS-resident kernel,
-    L = 16 the multi-block one.  Reports per-sweep latency percentiles
-    overall and per L, queueing delay and throughput."""
+def serving(g, seconds: float, mix: str = "small", seed: int = 2024):
+    """Continuous-batching serving run: Poisson arrivals (seeded) of chains
+    from a mix of lattice sizes, M = min(2048, 64 L) (K the next power of
+    two), T uniform in [0.02, 0.2], FP32 recursion, 2 sweeps per request for
+    L <= 24 and 1 above; arrivals stop after `seconds`, then the engine
+    drains.  Prints a progress line every 30 s and one JSON line with the
+    per-sweep latency percentiles overall and per L, the queueing delay and
+    the throughput."""
     import numpy as np
+    sizes, probs, rate = SERVING_MIXES[mix]
     rng = np.random.default_rng(seed)
     eng = g.Engine(0, hbm_budget_bytes=16 << 30, max_slots=64)
     t0 = time.perf_counter()
-    t_next, k, meta = rng.exponential(1.0 / rate), 0, {}
+    t_next, k, meta, t_print = rng.exponential(1.0 / rate), 0, {}, 30.0
+
+    def progress(now):
+        st = eng.status()
+        print(json.dumps({"mode": "serving_progress", "t_s": round(now, 1), "submitted": k,
+                          **st}), flush=True)
+
     while True:
         now = time.perf_counter() - t0
         if now >= seconds:
             break
+        if now >= t_print:
+            progress(now)
+            t_print += 30.0
         if now >= t_next:
-            Lk = int(rng.choice(SERVING_L, p=SERVING_P))
-            Mk = 64 * Lk
+            Lk = int(rng.choice(sizes, p=probs))
+            Mk = min(2048, 64 * Lk)
             Kk = 1 << (Mk - 1).bit_length()
             T = float(rng.uniform(0.02, 0.2))
             rid = eng.submit(g.Params(L=Lk, M=Mk, K=Kk, beta=1.0 / T, precision=g.FP32_ACC64,
-                                      seed=seed, chain_id=k), init=g.INIT_RANDOM, nsweeps=2)
+                                      seed=seed, chain_id=k), init=g.INIT_RANDOM,
+                             nsweeps=2 if Lk <= 24 else 1)
             meta[rid] = Lk
             k += 1
             t_next += rng.exponential(1.0 / rate)
         else:
-            time.sleep(min(0.01, t_next - now))
-    eng.drain(1800)
+            time.sleep(min(0.01, max(0.0, t_next - now)))
+    while True:   # drain, reporting progress
+        try:
+            eng.drain(30.0)
+            break
+        except g.GfmcError as e:
+            if e.status != g.GFMC_EBUSY:
+                raise
+            progress(time.perf_counter() - t0)
     wall = time.perf_counter() - t0
     res = eng.poll(1 << 16)
     lat, ids = eng.sweep_latencies()
@@ -301,22 +326,23 @@ def serving(g, seconds: float, rate: float = 6.0, seed: int = 2024):
     props = sum(r.proposals for r in res)
     svu = sum(r.proposals * (r.L ** 3) * 7 * (r.M // 2) for r in res)
     per_L = {}
-    for Lk in SERVING_L:
+    for Lk in sizes:
         sel = np.array([meta.get(int(i)) == Lk for i in ids], dtype=bool)
         if sel.any():
             per_L[str(Lk)] = {"p50_s": float(np.percentile(lat[sel], 50)),
                               "p99_s": float(np.percentile(lat[sel], 99)), "sweeps": int(sel.sum())}
     wait = np.array([r.t_admit - r.t_submit for r in res])
     print(json.dumps({
-        "mode": "serving", "requests": k, "completed": sum(r.status == 0 for r in res),
+        "mode": "serving", "mix": mix, "requests": k,
+        "completed": sum(r.status == 0 for r in res),
         "arrival_rate_per_s": rate, "arrival_window_s": seconds, "wall_s": wall,
         "sweep_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                             "per_L": per_L, "sweeps": int(len(lat))},
         "queue_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
         "mc_spin_updates_per_s": props / wall, "svu_per_s": svu / wall,
-        "config": {"workload": "Poisson arrivals, L in {4,6,8,12,16} w.p. 0.3/0.25/0.25/0.15/0.05, "
-                               "M = 64 L, T ~ U[0.02, 0.2], FP32 recursion, 2 sweeps per request, "
-                               "16 GiB budget, 64 slots"}}),
+        "config": {"workload": f"Poisson arrivals ({rate}/s), L in {set(sizes)} w.p. {probs}, "
+                               "M = min(2048, 64 L), T ~ U[0.02, 0.2], FP32 recursion, 2 sweeps "
+                               "per request for L <= 24 and 1 above, 16 GiB budget, 64 slots"}}),
         flush=True)
 
 
@@ -437,7 +463,7 @@ def main():
     import paper_1303_6016_amd as g
     import synth
     if args.serving > 0:
-        serving(g, args.serving)
+        serving(g, args.serving, args.serving_mix)
         return
     if args.chain_sweep:
         chain_sweep(g, torch)
