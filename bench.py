@@ -68,6 +68,8 @@ def parse():
                     help="lattice-size mix of the serving run")
     ap.add_argument("--physics", action="store_true",
                     help="magnetization against temperature on 4^3, 6^3 and 8^3 (M = 256, mu = 0)")
+    ap.add_argument("--fp32-accuracy", action="store_true",
+                    help="FP32-recursion error against the FP64 path for L = 4..32, M = 512..8192")
     ap.add_argument("--copy-sweep", action="store_true",
                     help="device-copy bandwidth for working sets of 16 MiB .. 2 GiB")
     ap.add_argument("--copy-probe", action="store_true",
@@ -411,6 +413,34 @@ def physics(g, torch, warm: int = 50, sweeps: int = 200):
             "wall_s": time.perf_counter() - t0}), flush=True)
 
 
+def fp32_accuracy(g, sites: int = 8):
+    """Error of the FP32 recursion (FP64 sums) against the FP64 recursion, per
+    lattice size and moment count: max |d mu| over the 7x7 moments and max /
+    mean |d Delta S| over `sites` seeded sites and moves (beta = 20, uniform
+    random spins).  The FP64 path itself matches the oracle to 1e-12 / 1e-10."""
+    import numpy as np
+    import synth
+    for Lk in (4, 8, 16, 32):
+        th, ph = synth.random_angles(Lk ** 3, 5)
+        for Mk in (512, 1024, 2048, 4096, 8192):
+            c32, c64 = (g.Chain(g.Params(L=Lk, M=Mk, beta=20.0, precision=p))
+                        for p in (g.FP32_ACC64, g.FP64))
+            for c in (c32, c64):
+                c.set_spins(th, ph)
+            rng = np.random.default_rng(Lk * 100003 + Mk)
+            dmu, dds = 0.0, []
+            for _ in range(sites):
+                o = int(rng.integers(Lk ** 3))
+                tn, pn = float(np.arccos(rng.uniform(-1, 1))), float(rng.uniform(0, 2 * np.pi))
+                dmu = max(dmu, float(np.abs(c32.moments(o) - c64.moments(o)).max()))
+                dds.append(abs(c32.delta_seff(o, tn, pn) - c64.delta_seff(o, tn, pn)))
+            c32.close()
+            c64.close()
+            print(json.dumps({"mode": "fp32_accuracy", "L": Lk, "M": Mk, "sites": sites,
+                              "max_dmu": dmu, "max_dds": max(dds),
+                              "mean_dds": float(np.mean(dds))}), flush=True)
+
+
 def chain_sweep(g, torch):
     """Step-kernel time and algorithmic bandwidth of 32^3, M = 2048 batches of
     8..128 chains (FP32 and FP64), both launch shapes: shows where the chains'
@@ -470,6 +500,9 @@ def main():
         return
     if args.physics:
         physics(g, torch)
+        return
+    if args.fp32_accuracy:
+        fp32_accuracy(g)
         return
 
     dev = torch.device("cuda:0")

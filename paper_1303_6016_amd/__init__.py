@@ -295,6 +295,8 @@ class Batch:
 
     def __init__(self, chains: Sequence[Chain], stream: Optional[torch.cuda.Stream] = None):
         self.chains = list(chains)
+        if not self.chains:   # the library rejects an empty batch (GFMC_EINVAL)
+            _check(lib().gfmc_batch_workspace_bytes(None, 0, ctypes.byref(ctypes.c_size_t())))
         dev = self.chains[0].device
         with torch.cuda.device(dev):
             # a stream of its own: the legacy default stream cannot be captured

@@ -768,13 +768,11 @@ gfmc_status gfmc_batch_step(gfmc_batch* b, int32_t nprop, const int32_t* force,
   std::vector<gfmc_step_record> r(recs ? (size_t)nprop * n : 0);
   if (b->use_graph && !force && !recs) {
     HIPCHK(hipStreamSynchronize(P.stream));
-    const int tev = std::min(nprop, 4096);
     CHK(timing_begin(P, 1));
     HIPCHK(hipEventRecord(P.ev[0], P.stream));
     for (int q = 0; q < nprop; ++q) HIPCHK(hipGraphLaunch(P.gexec, P.stream));
     HIPCHK(hipEventRecord(P.ev[1], P.stream));
     P.ev_used = 2;
-    (void)tev;
     CHK(timing_end(P));
     // whole proposals were timed: report the per-proposal time spread over the steps
     P.step_launches = (int64_t)nprop * P.smax;

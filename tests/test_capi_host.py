@@ -70,5 +70,11 @@ def test_null_handles_and_bad_arguments_are_rejected_on_the_host():
     assert L.gfmc_pair_moments(None, 0, 1.0, 1.0, buf) == EINVAL
     assert L.gfmc_delta_seff(None, 0, 1.0, 1.0, ctypes.byref(d), ctypes.byref(d)) == EINVAL
     assert L.gfmc_engine_submit(None, None, 0, 0.0, 1, None) == EINVAL
+    sz, h = ctypes.c_size_t(), ctypes.c_void_p()
+    assert L.gfmc_batch_workspace_bytes(None, 0, ctypes.byref(sz)) == EINVAL
+    assert L.gfmc_batch_create(None, 0, None, 0, None, ctypes.byref(h)) == EINVAL
+    with pytest.raises(g.GfmcError) as e:
+        g.Batch([])
+    assert e.value.status == EINVAL
     assert L.gfmc_chain_destroy(None) == g.GFMC_OK and L.gfmc_batch_destroy(None) == g.GFMC_OK
     assert L.gfmc_last_error()

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -199,3 +200,32 @@ def test_64cubed_delta_seff_against_stored_oracle(g, prec, tol):
         assert (r.index, r.site, r.u) == (rp["index"], rp["site"], rp["u"])
         assert abs(r.theta_new - rp["theta_new"]) <= 4 * np.spacing(max(rp["theta_new"], 1.0))
         assert abs(r.dseff - rp["dseff"]) < tol
+
+
+def test_largest_lattice_256cubed_against_oracle(g):
+    # L = 256 is the largest lattice the library accepts (N = 2^24 sites,
+    # 32768 blocks of the step kernel): moments at the last site (every
+    # neighbour wraps around) against the oracle in both precisions, and the
+    # closed forms of mu_0, mu_1, mu_2^{oo} at sites across the lattice
+    L, M = 256, 4
+    m = oracle.Model(L=L, M=M, seed=0)
+    th, ph = synth.random_angles(m.N, 296)
+    o = m.N - 1
+    ref = oracle.moments(m, th, ph, o)
+    a = 6.0 / 0.99
+    S = lambda t, p: np.array([np.sin(t) * np.cos(p), np.sin(t) * np.sin(p), np.cos(t)])
+    for prec, tol in ((0, 1e-12), (1, 1e-5)):
+        ch = g.Chain(g.Params(L=L, M=M, precision=prec, seed=0))
+        ch.set_spins(th, ph)
+        err = np.abs(ch.moments(o) - ref).max()
+        print(f"256^3 M=4 prec={prec} site {o}: max|dmu|={err:.2e}", flush=True)
+        assert err < tol
+        for x in (0, 1 << 23, 12345677, m.N - L * L):
+            mu = ch.moments(x)
+            s = oracle.start_sites(L, x)
+            assert np.abs(mu[0] - np.eye(7)).max() == 0
+            h = [-oracle.hopping(th[x], ph[x], th[n], ph[n]) / a for n in s[1:]]
+            assert np.abs(mu[1, 0, 1:] - h).max() < (1e-15 if prec == 0 else 1e-7)
+            t2 = sum((1 + S(th[x], ph[x]) @ S(th[n], ph[n])) / 2 for n in s[1:])
+            assert abs(mu[2, 0, 0] - (2 * t2 / a ** 2 - 1)) < (1e-14 if prec == 0 else 1e-6)
+        ch.close()

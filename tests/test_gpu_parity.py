@@ -3,6 +3,9 @@
 Tolerances (absolute; |mu| <= 1):
   moments     FP64 1e-12, FP32 recursion / FP64 sums 1e-5
   Delta S     FP64 1e-10, FP32 2e-5
+  The FP32 bounds hold for M <= 1024 on every lattice and at the benchmark
+  sizes (32^3 with M = 2048, 64^3 with M = 4096); on small lattices the FP32
+  error grows with M beyond them (bench.py --fp32-accuracy measures it).
   RNG, sites, Metropolis draws: bit-exact; new angles within a few ulp
   (device and host libm may round acos/atan2 differently).
 """
@@ -101,8 +104,11 @@ def test_moment_invariants_on_device(g):
 
 
 # ----------------------------------------------------------------- Delta S --
+# includes the extremes M = 2 (mu_0 and mu_1 only), M = 4, and K = 8192 nodes
+# zero-padded over M = 64 on the 2^3 lattice (doubled bonds)
 @pytest.mark.parametrize("L,M,K,beta", [(4, 256, 0, 20.0), (6, 256, 512, 5.0), (8, 512, 0, 20.0),
-                                        (4, 64, 0, 0.5)])
+                                        (4, 64, 0, 0.5), (4, 2, 0, 5.0), (6, 4, 0, 5.0),
+                                        (2, 64, 8192, 20.0)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_delta_seff(g, L, M, K, beta, prec):
     ch, m = make(g, L, M, prec, beta=beta, K=K)
@@ -120,6 +126,27 @@ def test_delta_seff(g, L, M, K, beta, prec):
         assert abs(got - ref) < tol
         # top-edge phase: a diagnostic amplified by 1/sin(th) at the band edge
         assert abs(top - rtop) < (1e-8 if prec == 0 else 1e-2)
+
+
+def test_delta_seff_largest_moment_count(g):
+    # M = K = 8192, the largest the library accepts: the reconstruction block
+    # holds 8192 nodes in LDS; one oracle evaluation serves both precisions.
+    # The FP32 recursion's error grows with M and is largest on small lattices,
+    # where each vector covers few sites: on 4^3 at M = 4096 and 8192 it
+    # reaches 1e-4 to 1e-3 in Delta S, beyond the FP32 bound, so FP32 is only
+    # checked against gross failure (a wrong node count or table gives errors
+    # of order one)
+    m = oracle.Model(L=4, M=8192, beta=20.0)
+    th, ph = synth.random_angles(m.N, 5)
+    ref, rtop = oracle.delta_seff(m, th, ph, 3, 1.0, 2.0, with_phase_top=True)
+    for prec, tol in ((0, FP64_DS), (1, 1e-3)):
+        ch, _ = make(g, 4, 8192, prec, beta=20.0)
+        ch.set_spins(th, ph)
+        got, top = ch.delta_seff(3, 1.0, 2.0, with_phase_top=True)
+        print(f"M=K=8192 prec={prec} dS={ref:.6f} err={got - ref:.2e} top={top:.2e}", flush=True)
+        assert abs(got - ref) < tol
+        if prec == 0:   # FP32 noise, times 1/sin th at the outermost nodes, moves the top phase
+            assert abs(top - rtop) < 1e-8
 
 
 def test_delta_seff_lorentz_and_identity(g):
@@ -375,3 +402,56 @@ def test_step_kernel_shapes_on_small_lattices(g, shape, L, M, prec):
         assert rg.site == ro.site and rg.accepted == ro.accepted
         assert abs(rg.dseff - ro.dseff) < tol, (idx, rg.dseff, ro.dseff)
     b.close()
+
+
+@pytest.mark.parametrize("L,M", [(10, 128), (14, 64)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+def test_multiblock_moments_several_blocks_ragged_tail(g, L, M, prec, tol):
+    # single chains of these sizes run the multi-block step kernel: L = 10 has
+    # 500 site pairs (2 blocks, the last partial), L = 14 has 1372 (6 blocks)
+    ch, m = make(g, L, M, prec)
+    th, ph = synth.random_angles(m.N, L + 40)
+    ch.set_spins(th, ph)
+    for o in (0, m.N // 2 + 3, m.N - 1):
+        err = np.abs(ch.moments(o) - oracle.moments(m, th, ph, o)).max()
+        print(f"L={L} M={M} prec={prec} site={o}: max|dmu|={err:.1e}", flush=True)
+        assert err < tol
+
+
+@pytest.mark.parametrize("ppt", [1, 2])
+def test_multiblock_delta_seff_several_blocks_ragged_tail(g, ppt):
+    # both launch shapes through a batch of two ragged-size chains, FP64
+    specs = [(14, 64, 0.05), (10, 128, 0.1)]
+    chs, ms, sts = [], [], []
+    for i, (L, M, T) in enumerate(specs):
+        ch, m = make(g, L, M, 0, seed=31, chain_id=i, beta=1.0 / T)
+        th, ph = oracle.init_spins(m, 0)
+        ch.set_spins(th, ph)
+        chs.append(ch)
+        ms.append(m)
+        sts.append([th, ph])
+    b = g.Batch(chs)
+    b.set_tuning(ppt)
+    for idx in range(3):
+        ro = [oracle.step(m, s[0], s[1], idx) for m, s in zip(ms, sts)]
+        recs = b.step(1, force=np.array([r.accepted for r in ro]), records=True)[0]
+        for r, o in zip(recs, ro):
+            assert (r.site, r.u) == (o.site, o.u)
+            assert abs(r.dseff - o.dseff) < FP64_DS
+    b.close()
+
+
+def test_zero_counts_change_nothing(g):
+    # zero sweeps and zero proposals are valid calls that launch nothing
+    ch, m = make(g, 4, 64, 0, seed=2)
+    ch.init_spins(g.INIT_RANDOM)
+    th, ph = ch.get_spins()
+    mag, acc = ch.sweep(0)
+    assert mag.shape == (0,) and acc == 0
+    b = g.Batch([ch])
+    assert b.step(0, records=True) == []
+    mag, acc = b.sweep(0)
+    assert mag.shape == (1, 0) and acc.tolist() == [0]
+    b.close()
+    th2, ph2 = ch.get_spins()
+    assert np.array_equal(th, th2) and np.array_equal(ph, ph2) and ch.get_counter() == 0
