@@ -178,7 +178,8 @@ def small_configs(g, torch, dev):
     """The two small workloads, FP64 (the oracle's figures for them are in
     the cpu_baseline leg):
     4^3, M = 256, beta = 20, uniform-sphere starts and proposals, seeds 1-3,
-    two sweeps each (three chains in one batch, LDS-resident kernel);
+    two sweeps each (three chains in one batch, LDS-resident kernel: the
+    shape a new batch of chains that fit LDS starts in);
     16^3, M = 1024, T = 0.05, ferromagnet with floor(0.1 N) = 409 random
     sites (seed 42), cap proposals of 0.3 rad: 256 proposals timed, the ten
     sweeps (40 960 proposals) extrapolated."""
@@ -188,6 +189,7 @@ def small_configs(g, torch, dev):
     for ch in chs:
         ch.init_spins(g.INIT_RANDOM)
     b = g.Batch(chs)
+    assert b.tuning()[0] == 0
     b.step(1)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

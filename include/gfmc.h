@@ -232,11 +232,11 @@ gfmc_status gfmc_batch_use_graph(gfmc_batch* batch, int32_t enable);
 /* Launch shape of the Chebyshev steps: 1 or 2 site pairs per thread of the
  * multi-block step kernel (one launch per step), or 0 for one LDS-resident
  * workgroup per chain that runs all M/2 steps in a single launch (every
- * chain must fit: 72 B/site FP32, 144 B/site FP64 within 140 KB, i.e. up to
- * 12^3 FP32 / 8^3 FP64, 7 site start vectors, recomputed hoppings).  Results
- * do not depend on the shape beyond the order of the moment partial sums.
- * Single chains use shape 0 when they fit and have at most 256 site pairs
- * (L <= 8), else shape 1. */
+ * chain must fit: 128 B/site FP32, 232 B/site FP64 within 140 KB, i.e. up
+ * to 10^3 FP32 / 8^3 FP64, 7 site start vectors, recomputed hoppings).
+ * Results do not depend on the shape beyond the order of the moment partial
+ * sums.  Single chains, and new batches whose chains all fit, use shape 0;
+ * otherwise shape 1. */
 gfmc_status gfmc_batch_set_tuning(gfmc_batch* batch, int32_t pairs_per_thread);
 
 /* Step lanes: 1 (every Chebyshev step one launch on the batch stream) to 4

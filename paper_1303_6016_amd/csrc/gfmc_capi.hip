@@ -122,16 +122,17 @@ static int blocks_of(const Derived& d, int ppt) {
   return (d.half + per - 1) / per;
 }
 
-// The LDS-resident kernel holds spinors and the 7 bipartite vectors of a
-// chain: 72 B per site (FP32) or 144 B (FP64).
-static size_t resident_lds(const Derived& d) { return (size_t)d.N * (d.fp32 ? 72 : 144); }
+// The LDS-resident kernel holds, per site, the 7 bipartite vector slots, the
+// six hopping amplitudes and the six neighbour indices of a chain: 128 B per
+// site (FP32) or 232 B (FP64).
+static size_t resident_lds(const Derived& d) { return (size_t)d.N * (d.fp32 ? 128 : 232); }
 bool resident_fits(const Derived& d) {
   return !d.ov && !d.hops && resident_lds(d) <= (size_t)kResidentLds;
 }
-// Preferred (single chains, serving groups) only while one pass of the
-// workgroup covers the lattice: at more site pairs the multi-block kernel,
-// spread over many CUs, is faster per step than one workgroup looping.
-bool resident_ok(const Derived& d) { return resident_fits(d) && d.half <= kStepThreads; }
+// Preferred for single chains and serving groups wherever it fits: one
+// workgroup's step (1.5-3.9 us from 4^3 to 10^3) is faster than a step
+// launch of the multi-block kernel (about 6 us for a lone small chain).
+bool resident_ok(const Derived& d) { return resident_fits(d); }
 
 gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   std::vector<Desc> ds(sorted.size());
@@ -697,6 +698,10 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
   P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * n * sizeof(int32_t));
   P.d_rec = (gfmc_step_record*)w; w += align256((size_t)kRecCap * n * sizeof(gfmc_step_record));
   P.d_mag = (double*)w;
+  // the single-chain policy: LDS-resident when every chain fits
+  bool all_res = true;
+  for (auto* c : sorted) all_res = all_res && resident_ok(c->d);
+  P.ppt = all_res ? 0 : 1;
   plan_shape(P, sorted);
   b->sorted = sorted;
   // chains' own streams may hold pending work

@@ -9,6 +9,7 @@
 namespace gfmc {
 
 constexpr int kStepThreads = 256;   // threads per block of the Chebyshev step kernel
+constexpr int kResThreads = 1024;   // threads of the LDS-resident workgroup (4 waves per SIMD)
 constexpr int kNP = 49;             // moment partial sums per block and step (7 site vectors)
 constexpr int kNP2 = 4;             // ... for the pair {o, v}
 constexpr int kReconThreads = 256;  // threads of the reconstruction block (one per chain)

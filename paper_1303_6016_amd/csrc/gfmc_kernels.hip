@@ -506,149 +506,134 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   if (t < kNP) D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo(gsum, t);
 }
 
-// Small lattices: one workgroup runs all M/2 steps of one chain with its
-// spinors and the 7 bipartite vectors resident in LDS (72 B per site FP32,
-// 144 B FP64), so a proposal costs one launch instead of M/2.  Same
-// arithmetic and Gram sums as k_step; the block partial of step s is the
-// whole-lattice sum (one block per chain).
+// Small lattices: one workgroup runs all M/2 steps of one chain out of LDS,
+// so a proposal costs one launch instead of M/2.  Same arithmetic as k_step
+// (sum over the six directions in order, a_{s+1} over a_{s-1} in place, the
+// same 49 Gram sums per step on the FP64 matrix core), organised for latency
+// rather than bandwidth, since a small lattice gives a step only a few
+// hundred site pairs:
+//  * the hopping amplitudes t_{i, n_d(i)} and the neighbours' half-row
+//    indices are tabulated once per proposal (the spins do not change within
+//    one), so a step reads them instead of recomputing them;
+//  * a step is 7 x half independent items (vector j, site pair h) spread over
+//    all threads, each a six-term sum, instead of one thread forming all
+//    seven vectors of a site pair in sequence;
+//  * the Gram operands are read straight from the LDS planes.
+// LDS planes (index par * half + h for parity par, half-row index h):
+//   hp[d]  t_{i, n_d(i)} of site i = (par, h), d = 0..5
+//   vo     the o-vector slot,  vn[e] the slot of neighbour vector e = 0..5
+//   nb[d]  half-row index of n_d(i) (parity par ^ 1)
+// 13 complex values and 6 indices per site: 128 B (FP32), 232 B (FP64).
 template <typename T>
-__global__ __launch_bounds__(kStepThreads) void k_resident(const Desc* __restrict__ descs) {
+__global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict__ descs) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  __shared__ double xs[4][16][17];
   __shared__ double gsum[4][256];
   const Desc& D = descs[blockIdx.x];
   const int L = D.L, hx = L >> 1, half = D.half, N = D.N;
-  spn<T>* sp = (spn<T>*)smem;                 // [2][half]
-  cpx<T>* vo = (cpx<T>*)(sp + N);             // o-slots [2][half]
-  six<T>* vn = (six<T>*)(vo + N);             // n-slots [2][half]
+  cpx<T>* hp = (cpx<T>*)smem;                 // [6][2][half]
+  cpx<T>* vo = hp + 6 * N;                    // [2][half]
+  cpx<T>* vn = vo + N;                        // [6][2][half]
+  int* nb = (int*)(vn + 6 * N);               // [6][2][half]
   const Ctl* ctl = D.ctl;
   const int pO = ctl->parity_o, o_half = ctl->o_half;
   int sh[6];
 #pragma unroll
   for (int e = 0; e < 6; ++e) sh[e] = ctl->start_half[1 + e];
-  const spn<T>* gsp = (const spn<T>*)D.spin;
-  for (int i = threadIdx.x; i < N; i += kStepThreads) sp[i] = gsp[i];
+  const GLOBAL spn<T>* gsp = (const GLOBAL spn<T>*)D.spin;
+  // global (not flat) stores of the step partials: a flat store counts against
+  // the LDS wait counter, so every barrier would wait for its write to memory
+  GLOBAL double* part = (GLOBAL double*)D.part;
+
+  // tables, and the start vectors a_0 = e_o (o-slots, parity of o) and
+  // e_{n_e} (n-slots, the other parity); every other slot starts at zero
+  for (int q = threadIdx.x; q < N; q += kResThreads) {
+    const int par = (q >= half) ? 1 : 0, h = q - par * half;
+    const int k = h % hx, r = h / hx, y = r % L, z = r / L;
+    const int x = 2 * k + ((y + z + par) & 1);
+    const spn<T> si = ld(gsp + q);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      const int nh = nb_half(x, y, z, d, L);
+      T hr, hi_;
+      hop_spinor(si, ld(gsp + (size_t)(par ^ 1) * half + nh), hr, hi_);
+      hp[d * N + q] = cpx<T>{hr, hi_};
+      nb[d * N + q] = nh;
+      vn[d * N + q] = cpx<T>{(par != pO && h == sh[d]) ? (T)1 : (T)0, (T)0};
+    }
+    vo[q] = cpx<T>{(par == pO && h == o_half) ? (T)1 : (T)0, (T)0};
+  }
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int iters = (half + kStepThreads - 1) / kStepThreads;
+  const int items = 7 * half, chunks = (half + 3) >> 2;
+  const float inv_half = 1.0f / (float)half;
+  // two barriers per step: after the items (the Gram reads see them) and after
+  // the Gram sums (the next step may overwrite what they read)
+  __syncthreads();
   for (int s = 1; s <= D.S; ++s) {
-    __syncthreads();   // the previous step's vectors (and the spinors) are in place
-    const bool first = (s == 1);
-    const int po = pO ^ (s & 1), pn = po ^ 1;
-    const T c1 = first ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
-    d4v acc = {0.0, 0.0, 0.0, 0.0};
-    for (int it = 0; it < iters; ++it) {
-      const int h = it * kStepThreads + (int)threadIdx.x;
-      double x[16];
+    const int po = pO ^ (s & 1), pn = po ^ 1;   // parities that carry a^o_s, a^n_s
+    const T c1 = (s == 1) ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
+    // item (j, h): j = 0 forms a^o_s at the o-site (po, h), j >= 1 forms
+    // a^{n_{j-1}}_s at the n-site (pn, h); at s = 1 the slot being
+    // overwritten holds zero, so subtracting it is exact
+    for (int q = threadIdx.x; q < items; q += kResThreads) {
+      const int j = (int)(((float)q + 0.5f) * inv_half), h = q - j * half;
+      const int par = j ? pn : po;
+      const int row = par * half + h;
+      const cpx<T>* src = j ? vn + (size_t)(j - 1) * N + (par ^ 1) * half : vo + (par ^ 1) * half;
+      cpx<T>* dst = (j ? vn + (size_t)(j - 1) * N : vo) + row;
+      int nh[6];
+      cpx<T> hv[6], an[6];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) x[i] = 0.0;
-      if (h < half) {
-        const int k = h % hx, r = h / hx, y = r % L, z = r / L;
-        const int xo = 2 * k + ((y + z + po) & 1);
-        const int xn = 2 * k + ((y + z + pn) & 1);
-        {
-          const spn<T> si = sp[po * half + h];
-          T ar = 0, ai = 0;
+      for (int d = 0; d < 6; ++d) nh[d] = nb[d * N + row];
 #pragma unroll
-          for (int d = 0; d < 6; ++d) {
-            const int nh = nb_half(xo, y, z, d, L);
-            T hr, hi_;
-            hop_spinor(si, sp[pn * half + nh], hr, hi_);
-            cpx<T> an;
-            if (first) { an.x = (nh == o_half) ? (T)1 : (T)0; an.y = 0; }
-            else an = vo[pn * half + nh];
-            ar += hr * an.x - hi_ * an.y;
-            ai += hr * an.y + hi_ * an.x;
-          }
-          cpx<T> ao;
-          ao.x = c1 * ar;
-          ao.y = c1 * ai;
-          if (!first) {
-            const cpx<T> pr = vo[po * half + h];
-            ao.x -= pr.x;
-            ao.y -= pr.y;
-          }
-          vo[po * half + h] = ao;
-          x[14] = (double)ao.x;
-          x[15] = (double)ao.y;
-        }
-        {
-          const spn<T> si = sp[pn * half + h];
-          T accr[6], acci[6];
+      for (int d = 0; d < 6; ++d) hv[d] = hp[d * N + row];
+      const cpx<T> pr = *dst;
 #pragma unroll
-          for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
+      for (int d = 0; d < 6; ++d) an[d] = src[nh[d]];
+      // every load of the item is issued before the arithmetic: two LDS round
+      // trips (indices, then values) instead of one per direction
+      __builtin_amdgcn_sched_barrier(0);
+      T ar = 0, ai = 0;
 #pragma unroll
-          for (int d = 0; d < 6; ++d) {
-            const int nh = nb_half(xn, y, z, d, L);
-            T hr, hi_;
-            hop_spinor(si, sp[po * half + nh], hr, hi_);
-            six<T> an;
-            if (first) {
-#pragma unroll
-              for (int e = 0; e < 6; ++e) { an.v[e].x = (nh == sh[e]) ? (T)1 : (T)0; an.v[e].y = 0; }
-            } else {
-              an = vn[po * half + nh];
-            }
-#pragma unroll
-            for (int e = 0; e < 6; ++e) {
-              accr[e] += hr * an.v[e].x - hi_ * an.v[e].y;
-              acci[e] += hr * an.v[e].y + hi_ * an.v[e].x;
-            }
-          }
-          six<T> out;
-          six<T> prev;
-          if (!first) prev = vn[pn * half + h];
-#pragma unroll
-          for (int e = 0; e < 6; ++e) {
-            out.v[e].x = c1 * accr[e];
-            out.v[e].y = c1 * acci[e];
-            if (!first) {
-              out.v[e].x -= prev.v[e].x;
-              out.v[e].y -= prev.v[e].y;
-            }
-            x[2 * e] = (double)out.v[e].x;
-            x[2 * e + 1] = (double)out.v[e].y;
-          }
-          vn[pn * half + h] = out;
-          cpx<T> aop;
-          if (first) {
-            aop.x = (h == o_half) ? (T)1 : (T)0;
-            aop.y = 0;
-            vo[pn * half + h] = aop;
-            six<T> u;
-#pragma unroll
-            for (int e = 0; e < 6; ++e) { u.v[e].x = (h == sh[e]) ? (T)1 : (T)0; u.v[e].y = 0; }
-            vn[po * half + h] = u;
-          } else {
-            aop = vo[pn * half + h];
-          }
-          x[12] = (double)aop.x;
-          x[13] = (double)aop.y;
-        }
+      for (int d = 0; d < 6; ++d) {
+        ar += hv[d].x * an[d].x - hv[d].y * an[d].y;
+        ai += hv[d].x * an[d].y + hv[d].y * an[d].x;
       }
+      *dst = cpx<T>{c1 * ar - pr.x, c1 * ai - pr.y};
+    }
+    __syncthreads();
+    // Gram matrix of the 16-vector of every site pair h,
+    //   (Re/Im a^{n_0..5}_s at (pn, h), Re/Im a^o_{s-1} at (pn, h), Re/Im a^o_s at (po, h)),
+    // on the FP64 matrix core: v_mfma_f64_16x16x4 with A = B, four site pairs
+    // per instruction (lane: component lane % 16 of pair lane / 16)
+    d4v acc = {0.0, 0.0, 0.0, 0.0};
+    if (w < 4) {   // the first four waves
+      const int comp = lane & 15;
+      const T* base = (const T*)((comp < 12) ? vn + (size_t)(comp >> 1) * N + pn * half
+                                              : vo + ((comp < 14) ? pn : po) * half) + (comp & 1);
+      // four chunks of four site pairs per round, loads ahead of the products
+      for (int c0 = w; c0 < chunks; c0 += 16) {
+        double val[4];
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        if ((lane >> 4) == rr) {
-#pragma unroll
-          for (int i = 0; i < 16; ++i) xs[w][lane & 15][i] = x[i];
+        for (int u = 0; u < 4; ++u) {
+          const int h = 4 * (c0 + 4 * u) + (lane >> 4);
+          const double v = (double)base[2 * min(h, half - 1)];   // unconditional load
+          val[u] = (h < half) ? v : 0.0;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const double val = xs[w][4 * m + (lane >> 4)][lane & 15];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int u = 0; u < 4; ++u)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val[u], val[u], acc, 0, 0, 0);
       }
     }
+    // result layout of v_mfma_f64_16x16x4: lane l, register r holds entry
+    // (4r + l/16, l%16) of the 16x16 product
+    if (w < 4) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) gsum[w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
+      for (int r = 0; r < 4; ++r) gsum[w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
+    }
     __syncthreads();
     const int t = threadIdx.x;
-    if (t < kNP) D.part[(size_t)(s - 1) * kNP + t] = gram_combo(gsum, t);
+    if (t < kNP) part[(size_t)(s - 1) * kNP + t] = gram_combo(gsum, t);
   }
 }
 
@@ -1430,8 +1415,8 @@ hipError_t launch_resident(int fp32, const Desc* d, int n, size_t lds, hipStream
                hipSuccess;
   }();
   (void)attr_done;
-  if (fp32) hipLaunchKernelGGL(k_resident<float>, dim3(n), dim3(kStepThreads), lds, st, d);
-  else hipLaunchKernelGGL(k_resident<double>, dim3(n), dim3(kStepThreads), lds, st, d);
+  if (fp32) hipLaunchKernelGGL(k_resident<float>, dim3(n), dim3(kResThreads), lds, st, d);
+  else hipLaunchKernelGGL(k_resident<double>, dim3(n), dim3(kResThreads), lds, st, d);
   return hipGetLastError();
 }
 }  // namespace gfmc

@@ -84,10 +84,11 @@ def test_engine_budget_and_cancel(g):
     eng.close()
 
 
-MIXED = [  # L, M, T, precision: LDS-resident (L <= 12 FP32, L <= 8 FP64) and multi-block chains
+MIXED = [  # L, M, T, precision: LDS-resident (L <= 10 FP32, L <= 8 FP64) and multi-block chains
     (4, 128, 0.05, 1),
     (10, 64, 0.1, 0),
     (12, 64, 0.2, 1),
+    (10, 64, 0.15, 1),
     (16, 64, 0.05, 1),
     (6, 64, 0.02, 0),
 ]

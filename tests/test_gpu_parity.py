@@ -331,9 +331,15 @@ def lane_chains(g):
 @pytest.mark.parametrize("ppt", [1, 2])
 def test_batch_two_lanes_equal_single_chains(g, ppt):
     # multi-block chains of five sizes split over two step lanes (streams):
-    # with one site pair per thread the blocks are those of the single chain,
-    # so every record is bit-identical; with two the sums are regrouped
-    alone = [[ch.step() for _ in range(3)] for ch in lane_chains(g)]
+    # with one site pair per thread the blocks are those of the chain run
+    # alone in that shape, so every record is bit-identical; with two the sums
+    # are regrouped
+    alone = []
+    for ch in lane_chains(g):
+        one = g.Batch([ch])
+        one.set_tuning(1)   # a lone 10^3 FP32 chain would otherwise run LDS-resident
+        alone.append([r[0] for r in one.step(3, records=True)])
+        one.close()
     mixed = lane_chains(g)
     b = g.Batch(mixed)
     b.set_tuning(ppt)
@@ -355,6 +361,8 @@ def test_lane_arguments(g):
     ch, _ = make(g, 10, 64, 1, seed=3)
     ch.init_spins(g.INIT_RANDOM)
     b = g.Batch([ch])
+    assert b.tuning() == (0, 1)     # a new batch of chains that fit LDS starts resident
+    b.set_tuning(1)
     for bad in (0, 5):
         with pytest.raises(g.GfmcError) as e:
             b.set_lanes(bad)
