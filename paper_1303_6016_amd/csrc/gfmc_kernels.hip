@@ -41,6 +41,11 @@ __device__ inline void philox(uint64_t c0, uint64_t c1, uint64_t k0, uint64_t k1
   out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
+// Global address space: loads and stores through such pointers are global,
+// not flat, instructions (a flat access also counts against the LDS wait
+// counter).
+#define GLOBAL __attribute__((address_space(1)))
+
 __device__ inline double u01(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
 
 __device__ inline void site_xyz(int i, int L, int& x, int& y, int& z) {
@@ -121,17 +126,39 @@ __global__ void k_propose(const Desc* __restrict__ descs, int n) {
   if (c >= n) return;
   const Desc& D = descs[c];
   Ctl* ctl = D.ctl;
+  const GLOBAL double* th = (const GLOBAL double*)D.theta;
+  const GLOBAL double* ph = (const GLOBAL double*)D.phi;
+  const int mode = ctl->mode;
   int o;
-  double tn, pn, u = 0.0;
-  if (ctl->mode == 0) {
+  double tn = 0.0, pn = 0.0, u = 0.0, ua = 0.0, ub = 0.0;
+  if (mode == 0) {
     uint64_t r[4];
     philox((uint64_t)ctl->index, 1ULL, D.seed, D.chain_id, r);
     o = (int)__umul64hi(r[0], (uint64_t)D.N);
-    const double ua = u01(r[1]), ub = u01(r[2]);
+    ua = u01(r[1]);
+    ub = u01(r[2]);
     u = u01(r[3]);
+  } else {
+    o = ctl->site;
+    tn = ctl->th_new;
+    pn = ctl->ph_new;
+  }
+  // every angle the proposal needs is loaded before the first store (a store
+  // to the control block could alias them, which would serialise the loads)
+  const int L = D.L;
+  int nbs[6];
+  double tj[6], pj[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) nbs[d] = neighbor_site(o, d, L);
+  const double to = th[o], po = ph[o];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    tj[d] = th[nbs[d]];
+    pj[d] = ph[nbs[d]];
+  }
+  if (mode == 0) {
     if (D.proposal == GFMC_PROPOSE_CONE) {
-      const double t0 = D.theta[o], p0 = D.phi[o];
-      const double st = sin(t0), ct = cos(t0), sp = sin(p0), cp = cos(p0);
+      const double st = sin(to), ct = cos(to), sp = sin(po), cp = cos(po);
       const double S[3] = {st * cp, st * sp, ct};
       const double e1[3] = {ct * cp, ct * sp, -st};
       const double e2[3] = {-sp, cp, 0.0};
@@ -152,38 +179,31 @@ __global__ void k_propose(const Desc* __restrict__ descs, int n) {
     ctl->th_new = tn;
     ctl->ph_new = pn;
     ctl->u = u;
-  } else {
-    o = ctl->site;
-    tn = ctl->th_new;
-    pn = ctl->ph_new;
   }
-  const int L = D.L;
   int x, y, z;
   site_xyz(o, L, x, y, z);
   ctl->parity_o = (x + y + z) & 1;
   ctl->o_half = half_index(x, y, z, L);
   ctl->start_site[0] = o;
-  ctl->start_half[0] = ctl->o_half;
-  const double to = D.theta[o], po = D.phi[o];
+  ctl->start_half[0] = half_index(x, y, z, L);
   ctl->th_old = to;
   ctl->ph_old = po;
+#pragma unroll
   for (int d = 0; d < 6; ++d) {
-    const int nb = neighbor_site(o, d, L);
     int a, b, cc;
-    site_xyz(nb, L, a, b, cc);
-    ctl->start_site[1 + d] = nb;
+    site_xyz(nbs[d], L, a, b, cc);
+    ctl->start_site[1 + d] = nbs[d];
     ctl->start_half[1 + d] = half_index(a, b, cc, L);
     // Delta_{n,o} = H'_{n,o} - H_{n,o} = -t (t'_{n o} - t_{n o})
     double r1, i1, r0, i0;
-    hop_angles(D.theta[nb], D.phi[nb], tn, pn, r1, i1);
-    hop_angles(D.theta[nb], D.phi[nb], to, po, r0, i0);
+    hop_angles(tj[d], pj[d], tn, pn, r1, i1);
+    hop_angles(tj[d], pj[d], to, po, r0, i0);
     ctl->delta[2 * d] = -D.t * (r1 - r0);
     ctl->delta[2 * d + 1] = -D.t * (i1 - i0);
   }
 }
 
 // ------------------------------------------------------------ Chebyshev ---
-#define GLOBAL __attribute__((address_space(1)))
 
 // Six neighbour-vector values of one site, stored contiguously.
 template <typename T>
@@ -985,7 +1005,8 @@ __global__ void k_tables(const Desc* __restrict__ descs) {
 // 3 |o>+i|v>) from the pair moments m3 = (mu^{oo}, mu^{vv}, mu^{ov}) of
 // order n: <o+v|T|o+v> = mu^{oo} + mu^{vv} + 2 Re mu^{ov},
 // <o+iv|T|o+iv> = mu^{oo} + mu^{vv} - 2 Im mu^{ov}.
-__device__ inline double mixed_series(const double2* m3, int q) {
+template <typename P>
+__device__ inline double mixed_series(P m3, int q) {
   const double s = m3[0].x + m3[1].x;
   return (q == 0) ? m3[0].x : (q == 1) ? m3[1].x : (q == 2) ? s + 2.0 * m3[2].x
                                                             : s - 2.0 * m3[2].y;
@@ -1014,13 +1035,15 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
   double dl[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) dl[i] = ctl->delta[i];
-  const double2* __restrict__ mom = (const double2*)D.mom;   // [M][7][7]
-  double2* __restrict__ gs = (double2*)D.gscr;                // [4][K]
-  const double* __restrict__ gtab = D.tab;                    // g[M]
-  const double2* __restrict__ pre = (const double2*)(gtab + M);
-  const double2* __restrict__ tw = pre + K;                   // [K/2]
-  const double* __restrict__ sth = (const double*)(tw + K / 2);
-  const double* __restrict__ wt = sth + K;
+  // global (not flat) pointers: a flat access counts against the LDS wait
+  // counter, so every LDS wait of the transforms would also wait for it
+  const GLOBAL d2v* __restrict__ mom = (const GLOBAL d2v*)D.mom;   // [M][7][7]
+  GLOBAL d2v* __restrict__ gs = (GLOBAL d2v*)D.gscr;               // [4][K]
+  const GLOBAL double* __restrict__ gtab = (const GLOBAL double*)D.tab;   // g[M]
+  const GLOBAL d2v* __restrict__ pre = (const GLOBAL d2v*)(gtab + M);
+  const GLOBAL d2v* __restrict__ tw = pre + K;                     // [K/2]
+  const GLOBAL double* __restrict__ sth = (const GLOBAL double*)(tw + K / 2);
+  const GLOBAL double* __restrict__ wt = sth + K;
 
   // Four real series: 0 mu^{oo}, 1 mu^{vv}, 2 Re mu^{ov}, 3 Im mu^{ov};
   // mu^{vo} = conj(mu^{ov}) (Hermitian moments), so G_vo uses the same series.
@@ -1031,12 +1054,12 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
       if (m < M) {
         double x;
         if (D.vectors == GFMC_VECTORS_OV) {
-          const double2* m3 = mom + (size_t)m * 3;
+          const GLOBAL d2v* m3 = mom + (size_t)m * 3;
           x = (q == 0) ? m3[0].x : (q == 1) ? m3[1].x : (q == 2) ? m3[2].x : m3[2].y;
         } else if (D.vectors == GFMC_VECTORS_MIXED) {
           x = mixed_series(mom + (size_t)m * 3, q);
         } else {
-        const double2* mm = mom + (size_t)m * 49;
+        const GLOBAL d2v* mm = mom + (size_t)m * 49;
         if (q == 0) {
           x = mm[0].x;
         } else if (q == 1) {
@@ -1044,7 +1067,7 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
           for (int d = 0; d < 6; ++d) {
             double sr = 0.0, si = 0.0;   // sum_e delta_e mu^{de}
             for (int e = 0; e < 6; ++e) {
-              const double2 me = mm[(1 + d) * 7 + 1 + e];
+              const d2v me = mm[(1 + d) * 7 + 1 + e];
               sr += dl[2 * e] * me.x - dl[2 * e + 1] * me.y;
               si += dl[2 * e] * me.y + dl[2 * e + 1] * me.x;
             }
@@ -1054,7 +1077,7 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
         } else {
           double sr = 0.0, si = 0.0;
           for (int e = 0; e < 6; ++e) {
-            const double2 me = mm[1 + e];
+            const d2v me = mm[1 + e];
             sr += dl[2 * e] * me.x - dl[2 * e + 1] * me.y;
             si += dl[2 * e] * me.y + dl[2 * e + 1] * me.x;
           }
@@ -1064,7 +1087,7 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
         val = gtab[m] * x;
         if (m == 0) val *= 0.5;
       }
-      const double2 pm = pre[m];   // c_m = mu'_m exp(-i pi m / (2K))
+      const d2v pm = pre[m];   // c_m = mu'_m exp(-i pi m / (2K))
       buf[bitrev(m, lg)] = make_double2(val * pm.x, val * pm.y);
     }
     __syncthreads();
@@ -1074,7 +1097,8 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
       for (int b = tid; b < (K >> 1); b += kReconThreads) {
         const int j = b % hl, base = (b / hl) * len;
         const double2 u = buf[base + j];
-        const double2 t = cmul(buf[base + j + hl], tw[j * (K / len)]);
+        const d2v tv = tw[j * (K / len)];
+        const double2 t = cmul(buf[base + j + hl], make_double2(tv.x, tv.y));
         buf[base + j] = make_double2(u.x + t.x, u.y + t.y);
         buf[base + j + hl] = make_double2(u.x - t.x, u.y - t.y);
       }
@@ -1089,15 +1113,16 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
         chi.y = -chi.y;
       }
       const double st = sth[k];
-      gs[(size_t)q * K + k] = make_double2(-2.0 * chi.y / st, 2.0 * chi.x / st);
+      gs[(size_t)q * K + k] = d2v{-2.0 * chi.y / st, 2.0 * chi.x / st};
     }
     __syncthreads();
   }
   // d_k = (1 + G_ov)(1 + G_vo) - G_oo G_vv with G = Gt / a
   const double ia = 1.0 / a;
   for (int k = tid; k < K; k += kReconThreads) {
-    const double2 goo = gs[k], gvv = gs[(size_t)K + k], R = gs[2 * (size_t)K + k],
-                  I = gs[3 * (size_t)K + k];
+    const d2v g0 = gs[k], g1 = gs[(size_t)K + k], R = gs[2 * (size_t)K + k],
+              I = gs[3 * (size_t)K + k];
+    const double2 goo = make_double2(g0.x, g0.y), gvv = make_double2(g1.x, g1.y);
     double2 p, m;
     if (D.vectors == GFMC_VECTORS_MIXED) {
       // G_ov = [A + i (S - G_{o+iv})] / 2, G_vo = [A + i (G_{o+iv} - S)] / 2 with
