@@ -119,85 +119,89 @@ __device__ inline int xcd_remap(int b, int nb) {
 }
 
 // -------------------------------------------------------------- propose ---
-__global__ void k_propose(const Desc* __restrict__ descs, int n) {
+// One wave per chain: lane 0 draws the proposal (the FP64 trigonometry of a
+// new direction), then lanes 0..5 each form the bond change to one neighbour,
+// so the twelve hopping evaluations run side by side.
+__global__ __launch_bounds__(64) void k_propose(const Desc* __restrict__ descs, int n) {
   // no FMA contraction: an unchanged spin must give Delta_{n,o} = 0 exactly
 #pragma clang fp contract(off)
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.x, lane = threadIdx.x;
   if (c >= n) return;
   const Desc& D = descs[c];
   Ctl* ctl = D.ctl;
   const GLOBAL double* th = (const GLOBAL double*)D.theta;
   const GLOBAL double* ph = (const GLOBAL double*)D.phi;
   const int mode = ctl->mode;
-  int o;
-  double tn = 0.0, pn = 0.0, u = 0.0, ua = 0.0, ub = 0.0;
-  if (mode == 0) {
-    uint64_t r[4];
-    philox((uint64_t)ctl->index, 1ULL, D.seed, D.chain_id, r);
-    o = (int)__umul64hi(r[0], (uint64_t)D.N);
-    ua = u01(r[1]);
-    ub = u01(r[2]);
-    u = u01(r[3]);
-  } else {
-    o = ctl->site;
-    tn = ctl->th_new;
-    pn = ctl->ph_new;
-  }
-  // every angle the proposal needs is loaded before the first store (a store
-  // to the control block could alias them, which would serialise the loads)
   const int L = D.L;
-  int nbs[6];
-  double tj[6], pj[6];
-#pragma unroll
-  for (int d = 0; d < 6; ++d) nbs[d] = neighbor_site(o, d, L);
-  const double to = th[o], po = ph[o];
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
-    tj[d] = th[nbs[d]];
-    pj[d] = ph[nbs[d]];
-  }
-  if (mode == 0) {
-    if (D.proposal == GFMC_PROPOSE_CONE) {
-      const double st = sin(to), ct = cos(to), sp = sin(po), cp = cos(po);
-      const double S[3] = {st * cp, st * sp, ct};
-      const double e1[3] = {ct * cp, ct * sp, -st};
-      const double e2[3] = {-sp, cp, 0.0};
-      const double ca = 1.0 - (1.0 - cos(D.cone)) * ua;
-      const double sa = sqrt(fmax(0.0, (1.0 - ca) * (1.0 + ca)));
-      const double psi = 2.0 * M_PI * ub;
-      const double cs = cos(psi), ss = sin(psi);
-      double Sn[3];
-      for (int q = 0; q < 3; ++q) Sn[q] = ca * S[q] + sa * (cs * e1[q] + ss * e2[q]);
-      tn = atan2(sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1]), Sn[2]);
-      pn = atan2(Sn[1], Sn[0]);
-      if (pn < 0) pn += 2.0 * M_PI;
+  int o = 0;
+  double tn = 0.0, pn = 0.0, to = 0.0, po = 0.0;
+  if (lane == 0) {
+    double u = 0.0, ua = 0.0, ub = 0.0;
+    if (mode == 0) {
+      uint64_t r[4];
+      philox((uint64_t)ctl->index, 1ULL, D.seed, D.chain_id, r);
+      o = (int)__umul64hi(r[0], (uint64_t)D.N);
+      ua = u01(r[1]);
+      ub = u01(r[2]);
+      u = u01(r[3]);
     } else {
-      tn = acos(1.0 - 2.0 * ua);
-      pn = 2.0 * M_PI * ub;
+      o = ctl->site;
+      tn = ctl->th_new;
+      pn = ctl->ph_new;
     }
-    ctl->site = o;
-    ctl->th_new = tn;
-    ctl->ph_new = pn;
-    ctl->u = u;
+    to = th[o];
+    po = ph[o];
+    if (mode == 0) {
+      if (D.proposal == GFMC_PROPOSE_CONE) {
+        const double st = sin(to), ct = cos(to), sp = sin(po), cp = cos(po);
+        const double S[3] = {st * cp, st * sp, ct};
+        const double e1[3] = {ct * cp, ct * sp, -st};
+        const double e2[3] = {-sp, cp, 0.0};
+        const double ca = 1.0 - (1.0 - cos(D.cone)) * ua;
+        const double sa = sqrt(fmax(0.0, (1.0 - ca) * (1.0 + ca)));
+        const double psi = 2.0 * M_PI * ub;
+        const double cs = cos(psi), ss = sin(psi);
+        double Sn[3];
+        for (int q = 0; q < 3; ++q) Sn[q] = ca * S[q] + sa * (cs * e1[q] + ss * e2[q]);
+        tn = atan2(sqrt(Sn[0] * Sn[0] + Sn[1] * Sn[1]), Sn[2]);
+        pn = atan2(Sn[1], Sn[0]);
+        if (pn < 0) pn += 2.0 * M_PI;
+      } else {
+        tn = acos(1.0 - 2.0 * ua);
+        pn = 2.0 * M_PI * ub;
+      }
+    }
+    int x, y, z;
+    site_xyz(o, L, x, y, z);
+    ctl->parity_o = (x + y + z) & 1;
+    ctl->o_half = half_index(x, y, z, L);
+    ctl->start_site[0] = o;
+    ctl->start_half[0] = half_index(x, y, z, L);
+    ctl->th_old = to;
+    ctl->ph_old = po;
+    if (mode == 0) {
+      ctl->site = o;
+      ctl->th_new = tn;
+      ctl->ph_new = pn;
+      ctl->u = u;
+    }
   }
-  int x, y, z;
-  site_xyz(o, L, x, y, z);
-  ctl->parity_o = (x + y + z) & 1;
-  ctl->o_half = half_index(x, y, z, L);
-  ctl->start_site[0] = o;
-  ctl->start_half[0] = half_index(x, y, z, L);
-  ctl->th_old = to;
-  ctl->ph_old = po;
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
+  o = __shfl(o, 0);
+  tn = __shfl(tn, 0);
+  pn = __shfl(pn, 0);
+  to = __shfl(to, 0);
+  po = __shfl(po, 0);
+  if (lane < 6) {
+    const int d = lane, nb = neighbor_site(o, d, L);
+    const double tj = th[nb], pj = ph[nb];
     int a, b, cc;
-    site_xyz(nbs[d], L, a, b, cc);
-    ctl->start_site[1 + d] = nbs[d];
+    site_xyz(nb, L, a, b, cc);
+    ctl->start_site[1 + d] = nb;
     ctl->start_half[1 + d] = half_index(a, b, cc, L);
     // Delta_{n,o} = H'_{n,o} - H_{n,o} = -t (t'_{n o} - t_{n o})
     double r1, i1, r0, i0;
-    hop_angles(tj[d], pj[d], tn, pn, r1, i1);
-    hop_angles(tj[d], pj[d], to, po, r0, i0);
+    hop_angles(tj, pj, tn, pn, r1, i1);
+    hop_angles(tj, pj, to, po, r0, i0);
     ctl->delta[2 * d] = -D.t * (r1 - r0);
     ctl->delta[2 * d + 1] = -D.t * (i1 - i0);
   }
@@ -1023,8 +1027,11 @@ __global__ void k_mixed_series(const Desc* __restrict__ descs, double* __restric
 
 __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict__ descs,
                                                          const int32_t* __restrict__ force,
-                                                         gfmc_step_record* __restrict__ recs) {
-  extern __shared__ double2 buf[];   // [K]
+                                                         gfmc_step_record* __restrict__ recs,
+                                                         int lds_items) {
+  // dynamic LDS: the FFT twiddles [K/2] (when the launch reserved room for
+  // them) and the transform buffer [K]
+  extern __shared__ double2 dyn[];
   __shared__ double red[kReconThreads];
   __shared__ double tot[kReconThreads];
   const int c = blockIdx.x;
@@ -1044,6 +1051,10 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
   const GLOBAL d2v* __restrict__ tw = pre + K;                     // [K/2]
   const GLOBAL double* __restrict__ sth = (const GLOBAL double*)(tw + K / 2);
   const GLOBAL double* __restrict__ wt = sth + K;
+  const bool twl = K + K / 2 <= lds_items;   // twiddles staged in LDS
+  double2* buf = twl ? dyn + K / 2 : dyn;
+  if (twl)
+    for (int i = tid; i < K / 2; i += kReconThreads) dyn[i] = make_double2(tw[i].x, tw[i].y);
 
   // Four real series: 0 mu^{oo}, 1 mu^{vv}, 2 Re mu^{ov}, 3 Im mu^{ov};
   // mu^{vo} = conj(mu^{ov}) (Hermitian moments), so G_vo uses the same series.
@@ -1097,8 +1108,9 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
       for (int b = tid; b < (K >> 1); b += kReconThreads) {
         const int j = b % hl, base = (b / hl) * len;
         const double2 u = buf[base + j];
-        const d2v tv = tw[j * (K / len)];
-        const double2 t = cmul(buf[base + j + hl], make_double2(tv.x, tv.y));
+        const int ti = j * (K / len);
+        const double2 t = cmul(buf[base + j + hl],
+                               twl ? dyn[ti] : make_double2(tw[ti].x, tw[ti].y));
         buf[base + j] = make_double2(u.x + t.x, u.y + t.y);
         buf[base + j + hl] = make_double2(u.x - t.x, u.y - t.y);
       }
@@ -1152,18 +1164,22 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
   };
   double csum = 0.0;
   for (int k = k0; k < k1; ++k) csum += inc(k);
-  tot[tid] = csum;
-  __syncthreads();
-  if (tid == 0) {
-    double acc = 0.0;
-    for (int i = kReconThreads - 1; i >= 0; --i) {
-      const double v = tot[i];
-      tot[i] = acc;   // sum over later chunks
-      acc += v;
-    }
+  // sum over the later chunks (an exclusive suffix sum): inclusive suffix
+  // sums within each wave by shuffles, shifted by one lane, plus the totals
+  // of the later waves
+  const int lane = tid & 63, wv = tid >> 6;
+  double x = csum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double y = __shfl_down(x, off);
+    if (lane + off < 64) x += y;
   }
+  const double after = __shfl_down(x, 1);
+  if (lane == 0) tot[wv] = x;
   __syncthreads();
-  double phi = tot[tid], part = 0.0, ptop = 0.0;
+  double later = (lane < 63) ? after : 0.0;
+  for (int w2 = wv + 1; w2 < kReconThreads / 64; ++w2) later += tot[w2];
+  double phi = later, part = 0.0, ptop = 0.0;
   for (int k = k1 - 1; k >= k0; --k) {
     phi += inc(k);
     part += wt[k] * phi;
@@ -1332,7 +1348,7 @@ hipError_t launch_mixed_series(const Desc* d, int M, double* out, hipStream_t st
 }
 
 hipError_t launch_propose(const Desc* d, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_propose, dim3((n + 63) / 64), dim3(64), 0, st, d, n);
+  hipLaunchKernelGGL(k_propose, dim3(n), dim3(64), 0, st, d, n);
   return hipGetLastError();
 }
 
@@ -1387,8 +1403,10 @@ hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t*
                                kMaxK * (int)sizeof(double2)) == hipSuccess;
   }();
   (void)attr_done;
-  hipLaunchKernelGGL(k_recon, dim3(n), dim3(kReconThreads), (size_t)kmax * sizeof(double2), st,
-                     d, force, recs);
+  // room for the twiddles beside the buffer while that stays within 64K items
+  const int items = (kmax <= kMaxK / 2) ? kmax + kmax / 2 : kmax;
+  hipLaunchKernelGGL(k_recon, dim3(n), dim3(kReconThreads), (size_t)items * sizeof(double2), st,
+                     d, force, recs, items);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (fp32)
