@@ -15,6 +15,7 @@
 // time.  Per-chain arithmetic does not depend on which chains share a plan.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -95,12 +96,11 @@ struct Request {
 // small chains run one launch per proposal while large ones run M/2.
 constexpr int kGroups = 16;
 constexpr int kMaxReps = 64;             // proposals per group and iteration
-constexpr double kConcurrentBlocks = 1024;   // step blocks resident at once (256 CUs)
 struct Group {
   Plan plan;
   std::vector<gfmc_chain*> members;   // plan order (most Chebyshev steps first)
   std::vector<Request*> reqs;         // the members' requests
-  double cost = 0;                    // relative device time of one proposal
+  double cost = 0;                    // estimated device time of one proposal (us)
   int reps = 1;                       // proposals per iteration
 };
 
@@ -108,24 +108,32 @@ static int group_of(const Derived& d) {
   return d.fp32 | (d.ov << 1) | (d.hops << 2) | (resident_ok(d) ? 8 : 0);
 }
 
-// Relative device time of one proposal of a group, counted in passes of one
-// 256-thread block over 256 half-rows for one Chebyshev step: the resident
-// kernel runs one block per chain, side by side, each over all its steps; the
-// multi-block path runs one launch per step over the blocks of the chains
-// still stepping, at least one pass long.
+// Estimated device time of one proposal of a group, in microseconds, from
+// the measured kernel costs on this chip: a fixed ~40 us for the proposal,
+// moment-assembly, reconstruction and spinor launches; the resident kernel
+// runs one workgroup per chain side by side, a step taking about
+// 1.35 + 0.65 x (items per thread) us (1.5 us at 4^3, 2.5 us at 8^3); the
+// multi-block path runs one launch per step over the chains still stepping,
+// about 4.4 us + 0.034 ns (FP32) or 0.069 ns (FP64) per site pair, at least
+// 6 us.
 static double proposal_cost(const Plan& P, const std::vector<gfmc_chain*>& m) {
+  constexpr double kFixed = 40.0;
   double c = 0;
   if (P.resident) {
-    for (auto* ch : m)
-      c = std::max(c, (double)ch->d.S * ((ch->d.half + kStepThreads - 1) / kStepThreads));
-    return c;
+    for (auto* ch : m) {
+      const double items = std::ceil(7.0 * ch->d.half / kResThreads);
+      c = std::max(c, ch->d.S * (1.35 + 0.65 * items));
+    }
+    return kFixed + c;
   }
+  const double per_pair = P.fp32 ? 3.4e-5 : 6.9e-5;
+  const double pairs_per_block = (double)kStepThreads * std::max(P.ppt, 1);
   int nact = P.n;
   for (int s = 1; s <= P.smax; ++s) {
     while (nact > 0 && P.S[nact - 1] < s) --nact;
-    c += std::max(1.0, (double)P.blkoff[nact] / kConcurrentBlocks);
+    c += std::max(6.0, 4.4 + per_pair * pairs_per_block * P.blkoff[nact]);
   }
-  return c;
+  return kFixed + c;
 }
 
 struct gfmc_engine {
