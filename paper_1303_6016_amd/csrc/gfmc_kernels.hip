@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict__ descs) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  __shared__ double gsum[4][256];
+  __shared__ double gsum[2][4][256];   // double-buffered by step parity
   const Desc& D = descs[blockIdx.x];
   const int L = D.L, hx = L >> 1, half = D.half, N = D.N;
   cpx<T>* hp = (cpx<T>*)smem;                 // [6][2][half]
@@ -590,9 +590,15 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
   const int items = 7 * half, chunks = (half + 3) >> 2;
   const float inv_half = 1.0f / (float)half;
   // two barriers per step: after the items (the Gram reads see them) and after
-  // the Gram sums (the next step may overwrite what they read)
+  // the Gram sums (the next step may overwrite what they read, and its
+  // combination of the sums reads them)
   __syncthreads();
+  // the 49 block sums of step s are formed by the last wave during the items
+  // of step s + 1 (off the critical path), from the other gsum buffer
+  const int t49 = (int)threadIdx.x - (kResThreads - 64);
   for (int s = 1; s <= D.S; ++s) {
+    if (s > 1 && t49 >= 0 && t49 < kNP)
+      part[(size_t)(s - 2) * kNP + t49] = gram_combo(gsum[(s - 1) & 1], t49);
     const int po = pO ^ (s & 1), pn = po ^ 1;   // parities that carry a^o_s, a^n_s
     const T c1 = (s == 1) ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
     // item (j, h): j = 0 forms a^o_s at the o-site (po, h), j >= 1 forms
@@ -653,12 +659,12 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
     // (4r + l/16, l%16) of the 16x16 product
     if (w < 4) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) gsum[w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
+      for (int r = 0; r < 4; ++r) gsum[s & 1][w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
     }
     __syncthreads();
-    const int t = threadIdx.x;
-    if (t < kNP) part[(size_t)(s - 1) * kNP + t] = gram_combo(gsum, t);
   }
+  if (t49 >= 0 && t49 < kNP)
+    part[(size_t)(D.S - 1) * kNP + t49] = gram_combo(gsum[D.S & 1], t49);
 }
 
 // Neumaier-compensated sum helper: (sum, comp) += v.
