@@ -33,13 +33,13 @@ HBM_PEAK_GBS = 8000.0
 # counter per run), each scaled by what the same counter reads for a plain
 # 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); valid only for the kernel
 # source they were taken with (sha256 below), else reported as null.
-TRAFFIC_KERNEL_SHA256 = "ecbeab93cfd246d6b4456a42812c9f65c47ae1044f074c47015931b2e4df60d7"
-TRAFFIC_BYTES = {("k_step<float>", 1): 214101843,
-                 ("k_step<float>", 2): 221201830,
+TRAFFIC_KERNEL_SHA256 = "5b415416c93c7418a40e54b4786046f21684fd46565531f14aafb2ea36c0b63c"
+TRAFFIC_BYTES = {("k_step<float>", 1): 214057428,
+                 ("k_step<float>", 2): 221242789,
                  ("k_step_ov<float>", 1): 84205372,
-                 ("k_step_ov<float>", 2): 84211002,
-                 ("k_step<float> stored rows", 1): 282594485,
-                 ("k_step<float> stored rows", 2): 289471692}
+                 ("k_step_ov<float>", 2): 84211258,
+                 ("k_step<float> stored rows", 1): 282592629,
+                 ("k_step<float> stored rows", 2): 289483212}
 
 
 def parse():

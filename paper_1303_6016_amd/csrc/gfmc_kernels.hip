@@ -593,11 +593,16 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
   // the Gram sums (the next step may overwrite what they read, and its
   // combination of the sums reads them)
   __syncthreads();
-  // the 49 block sums of step s are formed by the last wave during the items
-  // of step s + 1 (off the critical path), from the other gsum buffer
-  const int t49 = (int)threadIdx.x - (kResThreads - 64);
+  // On the smallest lattices (at most half the threads have an item) the 49
+  // block sums of step s are formed by the last wave, which has no item,
+  // during the items of step s + 1, from the other gsum buffer: off the
+  // critical path of a step that is mostly latency.  Otherwise the first 49
+  // threads form them right after the Gram sums.
+  const bool defer = items <= kResThreads / 2;
+  const int t49 = defer ? (int)threadIdx.x - (kResThreads - 64) : (int)threadIdx.x;
+  const bool combiner = t49 >= 0 && t49 < kNP;
   for (int s = 1; s <= D.S; ++s) {
-    if (s > 1 && t49 >= 0 && t49 < kNP)
+    if (defer && s > 1 && combiner)
       part[(size_t)(s - 2) * kNP + t49] = gram_combo(gsum[(s - 1) & 1], t49);
     const int po = pO ^ (s & 1), pn = po ^ 1;   // parities that carry a^o_s, a^n_s
     const T c1 = (s == 1) ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
@@ -662,9 +667,9 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
       for (int r = 0; r < 4; ++r) gsum[s & 1][w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
     }
     __syncthreads();
+    if (!defer && combiner) part[(size_t)(s - 1) * kNP + t49] = gram_combo(gsum[s & 1], t49);
   }
-  if (t49 >= 0 && t49 < kNP)
-    part[(size_t)(D.S - 1) * kNP + t49] = gram_combo(gsum[D.S & 1], t49);
+  if (defer && combiner) part[(size_t)(D.S - 1) * kNP + t49] = gram_combo(gsum[D.S & 1], t49);
 }
 
 // Neumaier-compensated sum helper: (sum, comp) += v.
