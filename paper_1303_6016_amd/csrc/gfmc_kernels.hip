@@ -5,6 +5,8 @@
 //   k_step     : one step of the three-term Chebyshev recursion (equation
 //                "recursive") for the 7 start vectors, matrix-free, fused with
 //                the Gram sums that give two moments per step (equation "mu2")
+//   k_resident : the same recursion for small lattices, all steps of a
+//                proposal in one LDS-resident workgroup per chain
 //   k_moments  : deferred, compensated sum of the per-block Gram partials and
 //                assembly of mu_n^{jk}, n < M
 //   k_recon    : contraction to the 2x2 block, damping kernel, node transform
