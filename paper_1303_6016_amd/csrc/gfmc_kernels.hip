@@ -1072,17 +1072,17 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
   // Four real series: 0 mu^{oo}, 1 mu^{vv}, 2 Re mu^{ov}, 3 Im mu^{ov};
   // mu^{vo} = conj(mu^{ov}) (Hermitian moments), so G_vo uses the same series.
   // Mixed start vectors: 0 mu^{oo}, 1 mu^{vv}, 2 mu^{o+v}, 3 mu^{o+iv}.
-  for (int q = 0; q < 4; ++q) {
-    for (int m = tid; m < K; m += kReconThreads) {
-      double val = 0.0;
-      if (m < M) {
-        double x;
-        if (D.vectors == GFMC_VECTORS_OV) {
-          const GLOBAL d2v* m3 = mom + (size_t)m * 3;
-          x = (q == 0) ? m3[0].x : (q == 1) ? m3[1].x : (q == 2) ? m3[2].x : m3[2].y;
-        } else if (D.vectors == GFMC_VECTORS_MIXED) {
-          x = mixed_series(mom + (size_t)m * 3, q);
-        } else {
+  // Transform input c_m = mu'_m exp(-i pi m / (2K)) of series q (zero for m >= M).
+  auto series_at = [&](int q, int m) -> double2 {
+    double val = 0.0;
+    if (m < M) {
+      double x;
+      if (D.vectors == GFMC_VECTORS_OV) {
+        const GLOBAL d2v* m3 = mom + (size_t)m * 3;
+        x = (q == 0) ? m3[0].x : (q == 1) ? m3[1].x : (q == 2) ? m3[2].x : m3[2].y;
+      } else if (D.vectors == GFMC_VECTORS_MIXED) {
+        x = mixed_series(mom + (size_t)m * 3, q);
+      } else {
         const GLOBAL d2v* mm = mom + (size_t)m * 49;
         if (q == 0) {
           x = mm[0].x;
@@ -1107,40 +1107,67 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
           }
           x = (q == 2) ? sr : si;
         }
-        }
-        val = gtab[m] * x;
-        if (m == 0) val *= 0.5;
       }
-      const d2v pm = pre[m];   // c_m = mu'_m exp(-i pi m / (2K))
-      buf[bitrev(m, lg)] = make_double2(val * pm.x, val * pm.y);
+      val = gtab[m] * x;
+      if (m == 0) val *= 0.5;
+    }
+    const d2v pm = pre[m];
+    return make_double2(val * pm.x, val * pm.y);
+  };
+  // radix-2 decimation-in-time FFT stage of half-length hl over bf, butterflies
+  // b0, b0 + step, ...: gamma_n = sum_m c_m exp(-2 pi i m n / K)
+  auto fft_stage = [&](double2* bf, int len, int b0, int step) {
+    const int hl = len >> 1;
+    for (int b = b0; b < (K >> 1); b += step) {
+      const int j = b % hl, base = (b / hl) * len;
+      const double2 u = bf[base + j];
+      const int ti = j * (K / len);
+      const double2 t = cmul(bf[base + j + hl], twl ? dyn[ti] : make_double2(tw[ti].x, tw[ti].y));
+      bf[base + j] = make_double2(u.x + t.x, u.y + t.y);
+      bf[base + j + hl] = make_double2(u.x - t.x, u.y - t.y);
+    }
+  };
+  // chi_{2j} = gamma_j, chi_{2j+1} = conj(gamma_{K-j-1}); Gt_k = 2i chi_k / sin th_k
+  auto store_g = [&](const double2* bf, int q, int k) {
+    const int j = k >> 1;
+    double2 chi = bf[j];
+    if (k & 1) {
+      chi = bf[K - j - 1];
+      chi.y = -chi.y;
+    }
+    const double st = sth[k];
+    gs[(size_t)q * K + k] = d2v{-2.0 * chi.y / st, 2.0 * chi.x / st};
+  };
+  if (4 * K + K / 2 <= lds_items) {
+    // room for all four transforms: one wave per series, side by side, with
+    // wave-level ordering between the stages instead of block barriers
+    double2* B = dyn + K / 2;   // [4][K]
+    for (int idx = tid; idx < 4 * K; idx += kReconThreads) {
+      const int q = idx >> lg, m = idx & (K - 1);
+      B[(size_t)q * K + bitrev(m, lg)] = series_at(q, m);
     }
     __syncthreads();
-    // radix-2 decimation-in-time FFT, gamma_n = sum_m c_m exp(-2 pi i m n / K)
+    const int q = tid >> 6, lane = tid & 63;
+    double2* bq = B + (size_t)q * K;
     for (int len = 2; len <= K; len <<= 1) {
-      const int hl = len >> 1;
-      for (int b = tid; b < (K >> 1); b += kReconThreads) {
-        const int j = b % hl, base = (b / hl) * len;
-        const double2 u = buf[base + j];
-        const int ti = j * (K / len);
-        const double2 t = cmul(buf[base + j + hl],
-                               twl ? dyn[ti] : make_double2(tw[ti].x, tw[ti].y));
-        buf[base + j] = make_double2(u.x + t.x, u.y + t.y);
-        buf[base + j + hl] = make_double2(u.x - t.x, u.y - t.y);
+      fft_stage(bq, len, lane, 64);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    for (int k = lane; k < K; k += 64) store_g(bq, q, k);
+    __syncthreads();
+  } else {
+    for (int q = 0; q < 4; ++q) {
+      for (int m = tid; m < K; m += kReconThreads) buf[bitrev(m, lg)] = series_at(q, m);
+      __syncthreads();
+      for (int len = 2; len <= K; len <<= 1) {
+        fft_stage(buf, len, tid, kReconThreads);
+        __syncthreads();
       }
+      for (int k = tid; k < K; k += kReconThreads) store_g(buf, q, k);
       __syncthreads();
     }
-    // chi_{2j} = gamma_j, chi_{2j+1} = conj(gamma_{K-j-1}); Gt_k = 2i chi_k / sin th_k
-    for (int k = tid; k < K; k += kReconThreads) {
-      const int j = k >> 1;
-      double2 chi = buf[j];
-      if (k & 1) {
-        chi = buf[K - j - 1];
-        chi.y = -chi.y;
-      }
-      const double st = sth[k];
-      gs[(size_t)q * K + k] = d2v{-2.0 * chi.y / st, 2.0 * chi.x / st};
-    }
-    __syncthreads();
   }
   // d_k = (1 + G_ov)(1 + G_vo) - G_oo G_vv with G = Gt / a
   const double ia = 1.0 / a;
@@ -1413,11 +1440,14 @@ hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t*
                         gfmc_step_record* recs, hipStream_t st) {
   static const bool attr_done = [] {   // thread-safe one-time setup
     return hipFuncSetAttribute((const void*)k_recon, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kMaxK * (int)sizeof(double2)) == hipSuccess;
+                               (kMaxK + kMaxK / 8) * (int)sizeof(double2)) == hipSuccess;
   }();
   (void)attr_done;
-  // room for the twiddles beside the buffer while that stays within 64K items
-  const int items = (kmax <= kMaxK / 2) ? kmax + kmax / 2 : kmax;
+  // dynamic LDS in 16-byte items: the twiddles and four transform buffers
+  // side by side up to K = 2048, the twiddles and one buffer up to 4096,
+  // else one buffer
+  const int items = (kmax <= kMaxK / 4) ? 4 * kmax + kmax / 2
+                    : (kmax <= kMaxK / 2) ? kmax + kmax / 2 : kmax;
   hipLaunchKernelGGL(k_recon, dim3(n), dim3(kReconThreads), (size_t)items * sizeof(double2), st,
                      d, force, recs, items);
   hipError_t e = hipGetLastError();
