@@ -327,26 +327,41 @@ __device__ inline Planes<T> planes(void* base, size_t stride) {
 // The 49 real block sums from the per-wave 16x16 Gram matrices in gsum:
 // t = 0: P^{oo}; 1..36: P^{de} (d <= e; diagonal -> Re, off-diagonal -> Re, Im);
 // 37..48: Q^{oe} (Re, Im).
-__device__ inline double gram_combo(const double (*gsum)[256], int t) {
-#define G(i, j) (gsum[0][(i) * 16 + (j)] + gsum[1][(i) * 16 + (j)] + gsum[2][(i) * 16 + (j)] + \
-                 gsum[3][(i) * 16 + (j)])
-  if (t == 0) return G(14, 14) + G(15, 15);
+// Sum t of the 49 as G(p1) + sg G(p2) over entries p = 16 i + j of the Gram
+// matrix, sg = +1 or -1, G(p) = sum of the four waves' entries p.
+struct Combo {
+  int p1, p2;
+  double sg;
+};
+__device__ inline Combo gram_combo_index(int t) {
+  if (t == 0) return {14 * 16 + 14, 15 * 16 + 15, 1.0};
   if (t < 37) {
-    int idx = t - 1, d = 0;
-    while (true) {
-      const int len = 1 + 2 * (5 - d);
-      if (idx < len) break;
-      idx -= len;
-      ++d;
+    // P^{de}, d <= e: group d holds 1 + 2 (5 - d) sums (diagonal, then Re
+    // and Im per e > d); found by an unrolled scan, not a loop
+    const int idx0 = t - 1;
+    int d = 0, base = 0;
+#pragma unroll
+    for (int q = 1; q <= 5; ++q) {
+      const int cum = 12 * q - q * q;   // sums in groups 0 .. q-1
+      if (idx0 >= cum) {
+        base = cum;
+        d = q;
+      }
     }
-    if (idx == 0) return G(2 * d, 2 * d) + G(2 * d + 1, 2 * d + 1);
+    const int idx = idx0 - base;
+    if (idx == 0) return {(2 * d) * 16 + 2 * d, (2 * d + 1) * 16 + 2 * d + 1, 1.0};
     const int e = d + 1 + (idx - 1) / 2;
-    return ((idx - 1) & 1) ? G(2 * d, 2 * e + 1) - G(2 * d + 1, 2 * e)
-                           : G(2 * d, 2 * e) + G(2 * d + 1, 2 * e + 1);
+    return ((idx - 1) & 1) ? Combo{(2 * d) * 16 + 2 * e + 1, (2 * d + 1) * 16 + 2 * e, -1.0}
+                           : Combo{(2 * d) * 16 + 2 * e, (2 * d + 1) * 16 + 2 * e + 1, 1.0};
   }
   const int q = t - 37, e = q >> 1;
-  return (q & 1) ? G(12, 2 * e + 1) - G(13, 2 * e) : G(12, 2 * e) + G(13, 2 * e + 1);
-#undef G
+  return (q & 1) ? Combo{12 * 16 + 2 * e + 1, 13 * 16 + 2 * e, -1.0}
+                 : Combo{12 * 16 + 2 * e, 13 * 16 + 2 * e + 1, 1.0};
+}
+__device__ inline double gram_combo(const double (*gsum)[256], const Combo& k) {
+  const double a = gsum[0][k.p1] + gsum[1][k.p1] + gsum[2][k.p1] + gsum[3][k.p1];
+  const double b = gsum[0][k.p2] + gsum[1][k.p2] + gsum[2][k.p2] + gsum[3][k.p2];
+  return a + k.sg * b;
 }
 
 template <typename T, bool FIRST, int PPT, bool HOPS>
@@ -529,7 +544,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   for (int r = 0; r < 4; ++r) gsum[w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
   __syncthreads();
   const int t = threadIdx.x;
-  if (t < kNP) D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo(gsum, t);
+  if (t < kNP)
+    D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo(gsum, gram_combo_index(t));
 }
 
 // Small lattices: one workgroup runs all M/2 steps of one chain out of LDS,
@@ -603,9 +619,10 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
   const bool defer = items <= kResThreads / 2;
   const int t49 = defer ? (int)threadIdx.x - (kResThreads - 64) : (int)threadIdx.x;
   const bool combiner = t49 >= 0 && t49 < kNP;
+  const Combo cmb = gram_combo_index(combiner ? t49 : 0);
   for (int s = 1; s <= D.S; ++s) {
     if (defer && s > 1 && combiner)
-      part[(size_t)(s - 2) * kNP + t49] = gram_combo(gsum[(s - 1) & 1], t49);
+      part[(size_t)(s - 2) * kNP + t49] = gram_combo(gsum[(s - 1) & 1], cmb);
     const int po = pO ^ (s & 1), pn = po ^ 1;   // parities that carry a^o_s, a^n_s
     const T c1 = (s == 1) ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
     // item (j, h): j = 0 forms a^o_s at the o-site (po, h), j >= 1 forms
@@ -669,9 +686,9 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
       for (int r = 0; r < 4; ++r) gsum[s & 1][w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
     }
     __syncthreads();
-    if (!defer && combiner) part[(size_t)(s - 1) * kNP + t49] = gram_combo(gsum[s & 1], t49);
+    if (!defer && combiner) part[(size_t)(s - 1) * kNP + t49] = gram_combo(gsum[s & 1], cmb);
   }
-  if (defer && combiner) part[(size_t)(D.S - 1) * kNP + t49] = gram_combo(gsum[D.S & 1], t49);
+  if (defer && combiner) part[(size_t)(D.S - 1) * kNP + t49] = gram_combo(gsum[D.S & 1], cmb);
 }
 
 // Neumaier-compensated sum helper: (sum, comp) += v.
