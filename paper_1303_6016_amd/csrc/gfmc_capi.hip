@@ -130,7 +130,7 @@ bool resident_fits(const Derived& d) {
   return !d.ov && !d.hops && resident_lds(d) <= (size_t)kResidentLds;
 }
 // Preferred for single chains and serving groups wherever it fits: one
-// workgroup's step (1.5-3.9 us from 4^3 to 10^3) is faster than a step
+// workgroup's step (1.0-3.9 us from 4^3 to 10^3) is faster than a step
 // launch of the multi-block kernel (about 6 us for a lone small chain).
 bool resident_ok(const Derived& d) { return resident_fits(d); }
 

@@ -112,7 +112,8 @@ static int group_of(const Derived& d) {
 // the measured kernel costs on this chip: a fixed ~40 us for the proposal,
 // moment-assembly, reconstruction and spinor launches; the resident kernel
 // runs one workgroup per chain side by side, a step taking about
-// 1.35 + 0.65 x (items per thread) us (1.5 us at 4^3, 2.5 us at 8^3); the
+// 0.1 + 0.95 x (items per thread) us (1.0 us at 4^3, 2.2-2.6 us at 8^3,
+// 3.9 us at 10^3); the
 // multi-block path runs one launch per step over the chains still stepping,
 // about 4.4 us + 0.034 ns (FP32) or 0.069 ns (FP64) per site pair, at least
 // 6 us.
@@ -122,7 +123,7 @@ static double proposal_cost(const Plan& P, const std::vector<gfmc_chain*>& m) {
   if (P.resident) {
     for (auto* ch : m) {
       const double items = std::ceil(7.0 * ch->d.half / kResThreads);
-      c = std::max(c, ch->d.S * (1.35 + 0.65 * items));
+      c = std::max(c, ch->d.S * (0.1 + 0.95 * items));
     }
     return kFixed + c;
   }
