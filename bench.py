@@ -33,13 +33,13 @@ HBM_PEAK_GBS = 8000.0
 # counter per run), each scaled by what the same counter reads for a plain
 # 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); valid only for the kernel
 # source they were taken with (sha256 below), else reported as null.
-TRAFFIC_KERNEL_SHA256 = "153e866ec94db9908cd2dffc1ee5137c7ea36fa6279ac4249595eaa868368cb1"
-TRAFFIC_BYTES = {("k_step<float>", 1): 214090543,
-                 ("k_step<float>", 2): 221211519,
-                 ("k_step_ov<float>", 1): 84205356,
-                 ("k_step_ov<float>", 2): 84210986,
-                 ("k_step<float> stored rows", 1): 282595488,
-                 ("k_step<float> stored rows", 2): 289519188}
+TRAFFIC_KERNEL_SHA256 = "791bf75ae47c22f5517ac59d2242aba8cddd4d8f383e494d27cc37b44015f55a"
+TRAFFIC_BYTES = {("k_step<float>", 1): 213976854,
+                 ("k_step<float>", 2): 221177766,
+                 ("k_step_ov<float>", 1): 84205372,
+                 ("k_step_ov<float>", 2): 84210746,
+                 ("k_step<float> stored rows", 1): 282614645,
+                 ("k_step<float> stored rows", 2): 289609673}
 
 
 def parse():
