@@ -34,12 +34,17 @@ HBM_PEAK_GBS = 8000.0
 # 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); valid only for the kernel
 # source they were taken with (sha256 below), else reported as null.
 TRAFFIC_KERNEL_SHA256 = "791bf75ae47c22f5517ac59d2242aba8cddd4d8f383e494d27cc37b44015f55a"
-TRAFFIC_BYTES = {("k_step<float>", 1): 213976854,
-                 ("k_step<float>", 2): 221177766,
-                 ("k_step_ov<float>", 1): 84205372,
-                 ("k_step_ov<float>", 2): 84210746,
-                 ("k_step<float> stored rows", 1): 282614645,
-                 ("k_step<float> stored rows", 2): 289609673}
+TRAFFIC_BYTES = {("k_step<float>", 1): 214111406,
+                 ("k_step<float>", 2): 221123713,
+                 ("k_step_ov<float>", 1): 84205356,
+                 ("k_step_ov<float>", 2): 84210730,
+                 ("k_step<float> stored rows", 1): 282612416,
+                 ("k_step<float> stored rows", 2): 289523476}
+
+
+def note(msg: str):
+    """Progress line on stderr (the result is the one JSON line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -64,6 +69,8 @@ def parse():
                     help="step-kernel bandwidth for 8..128 chains of 32^3 (cache residency)")
     ap.add_argument("--serving", type=float, default=0.0,
                     help="run the serving engine for this many seconds of Poisson arrivals")
+    ap.add_argument("--serving-leg", type=int, default=1,
+                    help="also run 30 s of the small serving mix and report its sweep latencies")
     ap.add_argument("--serving-mix", type=str, default="small", choices=sorted(SERVING_MIXES),
                     help="lattice-size mix of the serving run")
     ap.add_argument("--physics", action="store_true",
@@ -275,14 +282,16 @@ SERVING_MIXES = {
 }
 
 
-def serving(g, seconds: float, mix: str = "small", seed: int = 2024):
+def serving(g, seconds: float, mix: str = "small", seed: int = 2024, emit: bool = True):
     """Continuous-batching serving run: Poisson arrivals (seeded) of chains
     from a mix of lattice sizes, M = min(2048, 64 L) (K the next power of
     two), T uniform in [0.02, 0.2], FP32 recursion, 2 sweeps per request for
     L <= 24 and 1 above; arrivals stop after `seconds`, then the engine
     drains.  Prints a progress line every 30 s and one JSON line with the
     per-sweep latency percentiles overall and per L, the queueing delay and
-    the throughput."""
+    the throughput, and returns that record; with emit=False (a leg of the
+    default benchmark) the progress lines go to stderr and nothing else is
+    printed."""
     import numpy as np
     sizes, probs, rate = SERVING_MIXES[mix]
     rng = np.random.default_rng(seed)
@@ -293,7 +302,7 @@ def serving(g, seconds: float, mix: str = "small", seed: int = 2024):
     def progress(now):
         st = eng.status()
         print(json.dumps({"mode": "serving_progress", "t_s": round(now, 1), "submitted": k,
-                          **st}), flush=True)
+                          **st}), file=sys.stdout if emit else sys.stderr, flush=True)
 
     while True:
         now = time.perf_counter() - t0
@@ -336,7 +345,7 @@ def serving(g, seconds: float, mix: str = "small", seed: int = 2024):
             per_L[str(Lk)] = {"p50_s": float(np.percentile(lat[sel], 50)),
                               "p99_s": float(np.percentile(lat[sel], 99)), "sweeps": int(sel.sum())}
     wait = np.array([r.t_admit - r.t_submit for r in res])
-    print(json.dumps({
+    rec = {
         "mode": "serving", "mix": mix, "requests": k,
         "completed": sum(r.status == 0 for r in res),
         "arrival_rate_per_s": rate, "arrival_window_s": seconds, "wall_s": wall,
@@ -346,8 +355,10 @@ def serving(g, seconds: float, mix: str = "small", seed: int = 2024):
         "mc_spin_updates_per_s": props / wall, "svu_per_s": svu / wall,
         "config": {"workload": f"Poisson arrivals ({rate}/s), L in {set(sizes)} w.p. {probs}, "
                                "M = min(2048, 64 L), T ~ U[0.02, 0.2], FP32 recursion, 2 sweeps "
-                               "per request for L <= 24 and 1 above, 16 GiB budget, 64 slots"}}),
-        flush=True)
+                               "per request for L <= 24 and 1 above, 16 GiB budget, 64 slots"}}
+    if emit:
+        print(json.dumps(rec), flush=True)
+    return rec
 
 
 def copy_sweep(torch):
@@ -503,6 +514,13 @@ def main():
     if args.physics:
         physics(g, torch)
         return
+    sv = None
+    if args.serving_leg:
+        # the metric's p50/p99 sweep latency under continuous batching; run
+        # before the other legs, while this process holds no other streams, so
+        # that the engine's group streams get hardware queues of their own
+        note("serving (30 s of Poisson arrivals)")
+        sv = serving(g, 30.0, "small", emit=False)
     if args.fp32_accuracy:
         fp32_accuracy(g)
         return
@@ -598,6 +616,7 @@ def main():
     }
 
     if args.pair:
+        note("pair form")
         # the same workload with the {o, v} start-vector pair (2 vectors per proposal)
         pch = []
         for c in range(NCHAIN):
@@ -639,6 +658,7 @@ def main():
         del pch
 
     if args.stored_hops:
+        note("stored hopping rows")
         # A/B: the same workload with stored hopping rows instead of recomputation
         hch = []
         for c in range(NCHAIN):
@@ -671,6 +691,7 @@ def main():
         del hch
 
     if not args.no_fp64_single:
+        note("plain FP64 single chain")
         p = g.Params(L=L, M=M, beta=1.0 / T_LO, precision=g.FP64, seed=SEED, chain_id=0)
         ch = g.Chain(p, device=dev)
         ch.init_spins(g.INIT_RANDOM)
@@ -688,11 +709,21 @@ def main():
         out["batched_vs_fp64_single_speedup"] = out["mc_spin_updates_per_s"] / (n1 / d1)
 
     if args.mixed:
+        note("64^3 + 8 x 32^3 batch")
         out["mixed_64cubed_plus_8x32cubed"] = mixed_batch(g, torch, dev)
     if args.small:
+        note("4^3 and 16^3 workloads")
         out["small_configs"] = small_configs(g, torch, dev)
+    if sv is not None:
+        out["serving"] = {
+            "mix": "small", "workload": sv["config"]["workload"],
+            "arrival_window_s": sv["arrival_window_s"], "requests": sv["requests"],
+            "completed": sv["completed"], "sweep_latency_s": sv["sweep_latency_s"],
+            "queue_wait_s": sv["queue_wait_s"],
+            "mc_spin_updates_per_s": sv["mc_spin_updates_per_s"]}
 
     if not args.no_cpu_baseline:
+        note("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline()
     batch.close()
     print(json.dumps(out), flush=True)
