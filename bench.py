@@ -277,8 +277,8 @@ def mixed_batch(g, torch, dev, n_prop: int = 2):
 SERVING_MIXES = {
     # small chains: L <= 8 on the LDS-resident kernel, 12 and 16 multi-block
     "small": ((4, 6, 8, 12, 16), (0.3, 0.25, 0.25, 0.15, 0.05), 6.0),
-    # the survey's sizes that can finish a sweep within minutes on one GPU
-    "survey": ((8, 16, 24, 32), (0.4, 0.3, 0.2, 0.1), 0.3),
+    # the serving workload's sizes whose sweeps finish within minutes on one GPU
+    "large": ((8, 16, 24, 32), (0.4, 0.3, 0.2, 0.1), 0.3),
 }
 
 
@@ -486,7 +486,8 @@ def chain_sweep(g, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "runs on one GPU (chains shard across GPUs by process); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch
