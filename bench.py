@@ -521,7 +521,11 @@ def main():
         # before the other legs, while this process holds no other streams, so
         # that the engine's group streams get hardware queues of their own
         note("serving (30 s of Poisson arrivals)")
-        sv = serving(g, 30.0, "small", emit=False)
+        try:
+            sv = serving(g, 30.0, "small", emit=False)
+        except Exception as e:   # the headline must still be reported
+            note(f"serving leg failed: {e}")
+            sv = {"error": str(e)}
     if args.fp32_accuracy:
         fp32_accuracy(g)
         return
@@ -715,7 +719,9 @@ def main():
     if args.small:
         note("4^3 and 16^3 workloads")
         out["small_configs"] = small_configs(g, torch, dev)
-    if sv is not None:
+    if sv is not None and "error" in sv:
+        out["serving"] = sv
+    elif sv is not None:
         out["serving"] = {
             "mix": "small", "workload": sv["config"]["workload"],
             "arrival_window_s": sv["arrival_window_s"], "requests": sv["requests"],
