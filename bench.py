@@ -713,12 +713,20 @@ def main():
                                     "proposals": n1}
         out["batched_vs_fp64_single_speedup"] = out["mc_spin_updates_per_s"] / (n1 / d1)
 
+    def leg(name, fn):
+        # a secondary leg that raises is recorded; the headline line still prints
+        try:
+            return fn()
+        except Exception as e:
+            note(f"{name} failed: {e}")
+            return {"error": str(e)}
+
     if args.mixed:
         note("64^3 + 8 x 32^3 batch")
-        out["mixed_64cubed_plus_8x32cubed"] = mixed_batch(g, torch, dev)
+        out["mixed_64cubed_plus_8x32cubed"] = leg("mixed batch", lambda: mixed_batch(g, torch, dev))
     if args.small:
         note("4^3 and 16^3 workloads")
-        out["small_configs"] = small_configs(g, torch, dev)
+        out["small_configs"] = leg("small workloads", lambda: small_configs(g, torch, dev))
     if sv is not None and "error" in sv:
         out["serving"] = sv
     elif sv is not None:
@@ -731,7 +739,7 @@ def main():
 
     if not args.no_cpu_baseline:
         note("oracle on the host cores")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = leg("oracle baseline", cpu_baseline)
     batch.close()
     print(json.dumps(out), flush=True)
 
