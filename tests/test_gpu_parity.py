@@ -133,7 +133,7 @@ def test_delta_seff_largest_moment_count(g):
     # holds 8192 nodes in LDS; one oracle evaluation serves both precisions.
     # The FP32 recursion's error grows with M and is largest on small lattices,
     # where each vector covers few sites: on 4^3 at M = 4096 and 8192 it
-    # reaches 1e-4 to 1e-3 in Delta S, beyond the FP32 bound, so FP32 is only
+    # reaches 3e-5 to 6e-4 in Delta S, beyond the FP32 bound, so FP32 is only
     # checked against gross failure (a wrong node count or table gives errors
     # of order one)
     m = oracle.Model(L=4, M=8192, beta=20.0)
