@@ -44,11 +44,16 @@
  *
  * Threading: a chain or batch handle is used by one caller thread at a time.
  *
- * Restrictions of the device path: L even (the lattice must be bipartite:
- * the recursion stores only the sublattice on which each vector is nonzero),
- * 2 <= L <= 256; b = 0 (a diagonal shift breaks that sublattice structure);
- * M even, 2 <= M <= 8192; K a power of two with M <= K <= 8192 (the radix-2
- * transform of the paper's node mapping runs in LDS).
+ * Restrictions of the device path (EINVAL otherwise):
+ *   L even, 2 <= L <= 256.  The model and the oracle are defined for any L
+ *     (Section 2.1), but the device recursion stores each vector only on the
+ *     sublattice where it is nonzero, which needs a bipartite (even-L)
+ *     periodic lattice; odd L is refused rather than run on a second, dense
+ *     layout.  This departs from the reading that allows odd L on every path.
+ *   b = 0 (a diagonal shift breaks that sublattice structure).
+ *   M even, 2 <= M <= 8192; K a power of two with M <= K <= 8192 (the radix-2
+ *     transform of the paper's node mapping runs in LDS).
+ *   GFMC_FP32_ACC64 only inside its validated range (see gfmc_precision).
  */
 #ifndef GFMC_H
 #define GFMC_H
@@ -70,6 +75,17 @@ typedef enum {
   GFMC_ECANCELED = -6  /* operation cancelled                                */
 } gfmc_status;
 
+/* Precision of the Chebyshev recursion (Section 2.2, equation "recursive").
+ * GFMC_FP64: FP64 throughout (moments within 1e-12, Delta S_eff within 1e-10
+ * of the FP64 oracle).  GFMC_FP32_ACC64: vectors and stencil in FP32, the
+ * moment sums (equation "mu2"), the reconstruction, the energy integral and
+ * the acceptance in FP64.  Its rounding error grows with M and falls with L,
+ * and the error of Delta S_eff grows with beta, so it is accepted only where
+ * its measured error stays within 1e-5 on the moments and 2e-5 on Delta
+ * S_eff: beta t <= 50 and M <= 512 (L = 2), 1024 (L = 4, 6), 2048
+ * (8 <= L < 32) or 8192 (L >= 32).  Elsewhere gfmc_workspace_bytes,
+ * gfmc_chain_create, gfmc_set_params and gfmc_engine_submit return EINVAL,
+ * unless params.fp32_unvalidated = 1 (for measuring that error). */
 typedef enum { GFMC_FP64 = 0, GFMC_FP32_ACC64 = 1 } gfmc_precision;
 typedef enum { GFMC_JACKSON = 0, GFMC_LORENTZ = 1 } gfmc_kernel;
 typedef enum { GFMC_PROPOSE_SPHERE = 0, GFMC_PROPOSE_CONE = 1 } gfmc_proposal;
@@ -114,6 +130,8 @@ typedef struct {
   uint64_t chain_id;        /* Philox key word 1                                      */
   gfmc_vectors vectors;     /* start vectors (GFMC_VECTORS_SITES default)             */
   gfmc_hoppings hoppings;   /* hopping amplitudes (GFMC_HOP_RECOMPUTE default)        */
+  int32_t fp32_unvalidated; /* 1: accept GFMC_FP32_ACC64 outside its validated range  */
+                            /* (error measurements only; see GFMC_FP32_ACC64 below)   */
 } gfmc_chain_params;
 
 /* Outcome of one proposal (Algorithm 1, inner loop body). */
@@ -134,7 +152,9 @@ typedef struct gfmc_batch gfmc_batch;   /* opaque */
 
 /* ---------------------------------------------------------------- chains --
  * Device workspace (bytes, 256-byte aligned base) that a chain with these
- * parameters needs: spin angles, spinor cache, the 7 Chebyshev vectors (one
+ * parameters needs (the device-resident state of one Markov chain of
+ * Algorithm 1, kept on the GPU across proposals as in Section 3, "Arrangement
+ * of CUDA Kernel Functions"): spin angles, spinor cache, the 7 Chebyshev vectors (one
  * sublattice each, 7*N complex values), per-step moment partial sums, the
  * moment table and reconstruction scratch.  EINVAL for parameters outside the
  * device path's restrictions. */
@@ -142,21 +162,34 @@ gfmc_status gfmc_workspace_bytes(const gfmc_chain_params* params, size_t* bytes)
 
 /* Create a chain on `dev_workspace` (device pointer of at least
  * gfmc_workspace_bytes bytes, owned by the caller, alive until destroy) and
- * `hip_stream` (hipStream_t, may be NULL for the default stream).  Spins start
- * ferromagnetic (all theta = phi = 0); the proposal counter starts at 0. */
+ * `hip_stream` (hipStream_t, may be NULL for the default stream): one Markov
+ * chain over the classical spins of the double-exchange model (Section 2.1;
+ * Algorithm 1).  Spins start ferromagnetic (all theta = phi = 0); the
+ * proposal counter starts at 0.  EINVAL for parameters outside the device
+ * path's restrictions, ENOMEM if `bytes` is too small; on error *out is not
+ * written and nothing is allocated.  destroy never frees the workspace. */
 gfmc_status gfmc_chain_create(const gfmc_chain_params* params, void* dev_workspace,
                               size_t bytes, void* hip_stream, gfmc_chain** out);
 gfmc_status gfmc_chain_destroy(gfmc_chain* chain);
 
-/* Change t, beta, mu (the rescaling a, if defaulted, follows t). */
+/* Change the hopping scale t, the inverse temperature beta and the chemical
+ * potential mu of the grand-canonical weight exp(-beta (H - mu N)) (Section
+ * 2.1); the rescaling Ht = (H - b)/a of Section 2.2, if defaulted, follows t.
+ * EINVAL (state unchanged) for non-positive t or beta, non-finite mu, or a
+ * new (t, beta) outside the validated FP32 range of an FP32 chain. */
 gfmc_status gfmc_set_params(gfmc_chain* chain, double t, double beta, double mu);
 
-/* Initialise spins on the device from the chain's Philox key: uniform on the
- * sphere, ferromagnetic, or ferromagnetic with exactly floor(frac*N) sites
- * (picked by a partial Fisher-Yates shuffle) redrawn on the sphere. */
+/* Initialise the classical spins (theta_i, phi_i) of Section 2.1 on the device
+ * from the chain's Philox key: uniform on the sphere, ferromagnetic, or
+ * ferromagnetic with exactly floor(frac*N) sites (picked by a partial
+ * Fisher-Yates shuffle) redrawn on the sphere (the starting configuration of
+ * Algorithm 1; the paper leaves it open).  EINVAL for an unknown mode or frac
+ * outside [0, 1]. */
 gfmc_status gfmc_init_spins(gfmc_chain* chain, gfmc_init mode, double random_fraction);
 
-/* Copy N angles from / to host arrays (theta in [0,pi], phi any finite value). */
+/* Copy the N spin angles (theta_i, phi_i) of equation "ht" from / to
+ * caller-owned host arrays of N doubles each, site order i = x + L(y + Lz)
+ * (theta in [0,pi], phi any finite value; EINVAL otherwise, state unchanged). */
 gfmc_status gfmc_set_spins(gfmc_chain* chain, const double* theta, const double* phi);
 gfmc_status gfmc_get_spins(gfmc_chain* chain, double* theta, double* phi);
 
@@ -164,9 +197,13 @@ gfmc_status gfmc_get_spins(gfmc_chain* chain, double* theta, double* phi);
 gfmc_status gfmc_set_counter(gfmc_chain* chain, int64_t index);
 gfmc_status gfmc_get_counter(gfmc_chain* chain, int64_t* index);
 
-/* Local moments around `site` for the current spins (no state change):
- * writes mu[M][7][7][2] (host).  Chains created with GFMC_VECTORS_SITES only
- * (ESTATE otherwise). */
+/* Local moments mu_n^{jk} = <j|T_n(Ht)|k>, n < M, around `site` for the current
+ * spins (no state change): the Chebyshev moments of Section 2.2 from M/2 steps
+ * of the recursion (equation "recursive") with doubling (equation "mu2"),
+ * start vectors j, k over `site` and its six neighbours.  Writes
+ * mu[M][7][7][2] (caller-owned host array, FP64, re/im).  EINVAL for a site
+ * outside [0, N) or mu NULL; ESTATE for chains not created with
+ * GFMC_VECTORS_SITES. */
 gfmc_status gfmc_moments(gfmc_chain* chain, int32_t site, double* mu);
 
 /* Moments of the pair {|o>, |v>} for moving the spin at `site` to
@@ -184,20 +221,38 @@ gfmc_status gfmc_pair_moments(gfmc_chain* chain, int32_t site, double theta_new,
 gfmc_status gfmc_mixed_moments(gfmc_chain* chain, int32_t site, double theta_new,
                                double phi_new, double* mu);
 
-/* Delta S_eff for moving the spin at `site` to (theta_new, phi_new), no state
- * change.  phase_top may be NULL. */
+/* Delta S_eff = S_eff(new) - S_eff(old) for moving the spin at `site` to
+ * (theta_new, phi_new), no state change: the kernel-damped local Green's
+ * functions (equations "green", "green_short", "green_fft"), the 2x2
+ * determinant d(z) of equation "d_z_green" and the Fermi-weighted phase
+ * integral of equation "d_seff2".  *dseff (host) receives the value;
+ * phase_top (may be NULL) the continuous phase of d at the highest node
+ * (ideally ~0).  EINVAL for a site outside [0, N), non-finite angles or
+ * dseff NULL. */
 gfmc_status gfmc_delta_seff(gfmc_chain* chain, int32_t site, double theta_new,
                             double phi_new, double* dseff, double* phase_top);
 
-/* One proposal at the chain's counter; force -1 takes the chain's own
- * decision, 0 rejects, 1 accepts.  rec may be NULL. */
+/* One proposal at the chain's counter: the body of Algorithm 1's inner loop
+ * (random site and direction, Delta from equation "ht", Delta S_eff, the
+ * Metropolis test e^{-Delta S} > u, spin update).  force -1 takes the
+ * chain's own decision, 0 rejects, 1 accepts (teacher forcing for parity
+ * runs).  rec (host, may be NULL) receives the record.  EINVAL for force
+ * outside -1..1. */
 gfmc_status gfmc_step(gfmc_chain* chain, int32_t force, gfmc_step_record* rec);
 
-/* nsweeps sweeps of N proposals each (Algorithm 1).  magnetization
- * [nsweeps] and accepted (total over the call) may be NULL. */
+/* nsweeps sweeps of N proposals each (Algorithm 1, outer loop), with the
+ * magnetization |sum_i S_i| / N after each sweep (Algorithm 1, after the
+ * inner loop).  magnetization [nsweeps] and accepted (total over the call)
+ * are caller-owned host arrays and may be NULL.  EINVAL for nsweeps < 0. */
 gfmc_status gfmc_sweep(gfmc_chain* chain, int32_t nsweeps, double* magnetization,
                        int64_t* accepted);
 
+/* The magnetization |sum_i S_i| / N of the chain's current spins, S_i the unit
+ * vector of (theta_i, phi_i) (Algorithm 1, the measurement after each sweep),
+ * computed on the device; *m (host) receives it.  EINVAL for m NULL. */
+gfmc_status gfmc_magnetization(gfmc_chain* chain, double* m);
+
+/* Wait for the chain's enqueued device work (its stream). */
 gfmc_status gfmc_sync(gfmc_chain* chain);
 
 /* ----------------------------------------------------------------- batches --
@@ -317,6 +372,19 @@ gfmc_status gfmc_engine_status(gfmc_engine* engine, int32_t* queued, int32_t* ru
 gfmc_status gfmc_engine_drain(gfmc_engine* engine, double timeout_s);
 /* Stop the worker (running requests are cancelled) and free the device memory. */
 gfmc_status gfmc_engine_destroy(gfmc_engine* engine);
+
+/* ------------------------------------------------------------ calibration --
+ * Streaming bandwidth of the device, the practical ceiling against which the
+ * step kernel's algorithmic bandwidth is read (no paper passage: measurement
+ * infrastructure).  mode 0 reads `a`, 1 writes `c`, 2 copies `a` to `c`,
+ * 3 writes a + b to `c` (two reads per write, the step kernel's mix); each
+ * buffer is a caller-owned device allocation of `bytes` (a multiple of 16;
+ * `c` is always required, 16 bytes suffice in mode 0), `reps` timed passes
+ * after one warm-up pass on `stream`.  *gbs = bytes moved once per pass
+ * (1, 1, 2 or 3 buffers) x reps / elapsed time, in GB/s.  Buffers well above
+ * the 256 MB last-level cache measure HBM; smaller ones the cache. */
+gfmc_status gfmc_stream_bandwidth(int32_t mode, const void* a, const void* b, void* c,
+                                  size_t bytes, int32_t reps, void* stream, double* gbs);
 
 /* ------------------------------------------------------------------ misc -- */
 const char* gfmc_status_string(gfmc_status status);

@@ -42,6 +42,7 @@ class ChainParams(ctypes.Structure):
         ("precision", ctypes.c_int32), ("proposal", ctypes.c_int32),
         ("cone_angle", ctypes.c_double), ("seed", ctypes.c_uint64), ("chain_id", ctypes.c_uint64),
         ("vectors", ctypes.c_int32), ("hoppings", ctypes.c_int32),
+        ("fp32_unvalidated", ctypes.c_int32),
     ]
 
 
@@ -85,6 +86,7 @@ _SIGS = {
     "gfmc_step": [_vp, _i32, _P(StepRecord)],
     "gfmc_sweep": [_vp, _i32, _P(_d), _P(_i64)],
     "gfmc_sync": [_vp],
+    "gfmc_magnetization": [_vp, _P(_d)],
     "gfmc_chain_step_bytes": [_vp, _P(_d), _P(_i32)],
     "gfmc_batch_workspace_bytes": [_P(_vp), _i32, _P(_sz)],
     "gfmc_batch_create": [_P(_vp), _i32, _vp, _sz, _vp, _P(_vp)],
@@ -105,6 +107,7 @@ _SIGS = {
     "gfmc_engine_status": [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_sz)],
     "gfmc_engine_drain": [_vp, _d],
     "gfmc_engine_destroy": [_vp],
+    "gfmc_stream_bandwidth": [_i32, _vp, _vp, _vp, _sz, _i32, _vp, _P(_d)],
 }
 EXPORTS = list(_SIGS) + ["gfmc_status_string", "gfmc_last_error", "gfmc_version"]
 
@@ -162,12 +165,14 @@ class Params:
     chain_id: int = 0
     vectors: int = VECTORS_SITES
     hoppings: int = HOP_RECOMPUTE
+    fp32_unvalidated: int = 0
 
     def c(self) -> ChainParams:
         return ChainParams(self.L, self.t, self.beta, self.mu, self.M, self.K, self.kernel,
                            self.lorentz_lambda, self.scale_a, self.scale_b, self.precision,
                            self.proposal, self.cone_angle, self.seed & (2**64 - 1),
-                           self.chain_id & (2**64 - 1), self.vectors, self.hoppings)
+                           self.chain_id & (2**64 - 1), self.vectors, self.hoppings,
+                           self.fp32_unvalidated)
 
     @property
     def N(self) -> int:
@@ -283,6 +288,11 @@ class Chain:
 
     def sync(self):
         _check(lib().gfmc_sync(self.h))
+
+    def magnetization(self) -> float:
+        v = ctypes.c_double()
+        _check(lib().gfmc_magnetization(self.h, ctypes.byref(v)))
+        return v.value
 
     def step_bytes(self):
         b, s = ctypes.c_double(), ctypes.c_int32()
@@ -421,3 +431,19 @@ class Engine:
 
     def drain(self, timeout_s: float = 600.0):
         _check(lib().gfmc_engine_drain(self.h, timeout_s))
+
+
+def stream_bandwidth(mode: int, nbytes: int, reps: int = 10, device="cuda:0") -> float:
+    """Streaming bandwidth (GB/s) of the device: mode 0 read, 1 write, 2 copy,
+    3 two reads + one write, over buffers of nbytes each."""
+    dev = torch.device(device)
+    with torch.cuda.device(dev):
+        bufs = [torch.zeros(nbytes, dtype=torch.uint8, device=dev) for _ in range(3)]
+        st = torch.cuda.current_stream(dev)
+        v = ctypes.c_double()
+        _check(lib().gfmc_stream_bandwidth(mode, ctypes.c_void_p(bufs[0].data_ptr()),
+                                           ctypes.c_void_p(bufs[1].data_ptr()),
+                                           ctypes.c_void_p(bufs[2].data_ptr()), nbytes, reps,
+                                           ctypes.c_void_p(st.cuda_stream), ctypes.byref(v)))
+        del bufs
+        return v.value

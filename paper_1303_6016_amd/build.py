@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgfmc.so")
-SOURCES = ["gfmc_kernels.hip", "gfmc_capi.hip", "gfmc_engine.hip"]
+SOURCES = ["gfmc_kernels.hip", "gfmc_capi.hip", "gfmc_engine.hip", "gfmc_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

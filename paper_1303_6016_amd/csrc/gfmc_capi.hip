@@ -25,6 +25,22 @@ gfmc_status gfmc_fail(gfmc_status s, const std::string& msg) {
 
 static gfmc_status fail(gfmc_status s, const std::string& msg) { return gfmc_fail(s, msg); }
 
+// Validated range of the FP32 recursion with FP64 sums: the (L, M, beta t)
+// cells where its measured error against the FP64 path (itself within
+// 1e-12 of the oracle) stays within the stated bounds, 1e-5 on the moments
+// and 2e-5 on Delta S_eff, with a margin.  The error grows with M (rounding
+// errors of the recursion accumulate over its M/2 steps), shrinks with L (a
+// vector spread over many sites averages them in the Gram sums), and the
+// error of Delta S_eff grows linearly with beta (the energy integral is
+// weighted by beta).  Largest M accepted per lattice size at beta t <= 50.
+int fp32_max_moments(int L) {
+  if (L < 4) return 512;
+  if (L < 8) return 1024;
+  if (L < 32) return 2048;
+  return 8192;
+}
+constexpr double kFp32MaxBetaT = 50.0;
+
 gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   if (!p) return fail(GFMC_EINVAL, "params is NULL");
   if (p->L < 2 || p->L > 256 || (p->L & 1))
@@ -54,6 +70,13 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
     return fail(GFMC_EINVAL, "unknown hopping mode");
   if (p->hoppings == GFMC_HOP_STORED && p->vectors != GFMC_VECTORS_SITES)
     return fail(GFMC_EINVAL, "stored hoppings need the 7 site start vectors");
+  if (p->fp32_unvalidated != 0 && p->fp32_unvalidated != 1)
+    return fail(GFMC_EINVAL, "fp32_unvalidated must be 0 or 1");
+  if (p->precision == GFMC_FP32_ACC64 && !p->fp32_unvalidated &&
+      (p->M > fp32_max_moments(p->L) || p->beta * p->t > kFp32MaxBetaT))
+    return fail(GFMC_EINVAL, "FP32 recursion outside its validated range (M <= " +
+                                 std::to_string(fp32_max_moments(p->L)) + " at L = " +
+                                 std::to_string(p->L) + ", beta t <= 50): use GFMC_FP64");
   d.L = p->L;
   d.N = p->L * p->L * p->L;
   d.half = d.N / 2;
@@ -618,6 +641,15 @@ gfmc_status gfmc_sweep(gfmc_chain* c, int32_t nsweeps, double* mag, int64_t* acc
   HIPCHK(hipMemcpyAsync(&a1, &c->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   if (accepted) *accepted = a1 - a0;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_magnetization(gfmc_chain* c, double* m) {
+  CHK(check_chain(c));
+  if (!m) return fail(GFMC_EINVAL, "m is NULL");
+  HIPCHK(launch_magnetization(c->plan.d_desc, 1, c->plan.d_mag, c->stream));
+  HIPCHK(hipMemcpyAsync(m, c->plan.d_mag, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return GFMC_OK;
 }
 

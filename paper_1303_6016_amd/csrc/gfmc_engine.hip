@@ -484,7 +484,7 @@ gfmc_status gfmc_engine_submit(gfmc_engine* E, const gfmc_chain_params* p, gfmc_
 }
 
 gfmc_status gfmc_engine_poll(gfmc_engine* E, gfmc_result* out, int32_t cap, int32_t* n) {
-  if (!E || !n || (cap > 0 && !out)) return gfmc_fail(GFMC_EINVAL, "bad arguments");
+  if (!E || !n || cap < 0 || (cap > 0 && !out)) return gfmc_fail(GFMC_EINVAL, "bad arguments");
   std::lock_guard<std::mutex> g(E->mu);
   const int k = std::min<int>(cap, (int)E->done.size());
   for (int i = 0; i < k; ++i) out[i] = E->done[i];
@@ -516,7 +516,7 @@ gfmc_status gfmc_engine_cancel(gfmc_engine* E, uint64_t id) {
 
 gfmc_status gfmc_engine_sweep_latencies(gfmc_engine* E, double* sec, uint64_t* ids, int32_t cap,
                                         int32_t* n) {
-  if (!E || !n || (cap > 0 && !sec)) return gfmc_fail(GFMC_EINVAL, "bad arguments");
+  if (!E || !n || cap < 0 || (cap > 0 && !sec)) return gfmc_fail(GFMC_EINVAL, "bad arguments");
   std::lock_guard<std::mutex> g(E->mu);
   const int k = std::min<int>(cap, (int)E->lat.size());
   for (int i = 0; i < k; ++i) {

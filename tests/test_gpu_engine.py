@@ -70,8 +70,12 @@ def test_engine_budget_and_cancel(g):
     long_id = eng.submit(g.Params(L=8, M=256, seed=1), nsweeps=1000)
     queued_id = eng.submit(g.Params(L=8, M=256, seed=2), nsweeps=1000)
     third = eng.submit(g.Params(L=8, M=256, seed=3), nsweeps=1000)   # waits for a slot
-    time.sleep(0.5)
-    assert eng.status()["queued"] >= 1
+    # poll the engine's state (bounded) until both slots are taken
+    deadline = time.monotonic() + 60.0
+    while eng.status()["running"] < 2 and time.monotonic() < deadline:
+        time.sleep(0.005)
+    st = eng.status()
+    assert st["running"] == 2 and st["queued"] == 1, st
     eng.cancel(third)
     eng.cancel(long_id)
     eng.cancel(queued_id)
@@ -116,3 +120,16 @@ def test_engine_mixed_kernel_shapes_equal_alone_runs(g):
         assert r.accepted == acc
         assert r.magnetization == mag[-1]
         assert abs(r.magnetization_mean - mag.mean()) < 1e-15
+
+
+def test_engine_rejects_negative_caps(g):
+    import ctypes
+    eng = g.Engine(0, hbm_budget_bytes=8 << 20, max_slots=1)
+    L = g.lib()
+    n = ctypes.c_int32(7)
+    out = (g.Result * 1)()
+    sec = (ctypes.c_double * 1)()
+    assert L.gfmc_engine_poll(eng.h, out, -1, ctypes.byref(n)) == g.GFMC_EINVAL
+    assert L.gfmc_engine_sweep_latencies(eng.h, sec, None, -1, ctypes.byref(n)) == g.GFMC_EINVAL
+    assert n.value == 7
+    eng.close()

@@ -24,6 +24,55 @@ def g():
     return g
 
 
+@pytest.mark.parametrize("T", [0.05, 0.2])
+def test_magnetization_per_sweep_matches_oracle(g, T):
+    # The paper's validation observable (|m| against T, Section 4: M = 256,
+    # mu = 0) anchored to the oracle: 4^3, ferromagnetic start, 4 warm-up and
+    # 6 measured sweeps at T = 0.05t (ordered) and 0.2t (melting), FP64, the
+    # same Philox key on both sides.  Every proposal is teacher-forced to the
+    # oracle's decision (a decision within rounding of the threshold is the
+    # only allowed difference, and is counted); after every sweep the
+    # device's |m| (its magnetization kernel) must equal the oracle's within
+    # 1e-12, and the accepted counts per sweep must be equal.
+    import math
+    import oracle
+    L, M, warm, meas = 4, 256, 4, 6
+    m = oracle.Model(L=L, M=M, beta=1.0 / T, mu=0.0, seed=2013, chain_id=7)
+    ch = g.Chain(g.Params(L=L, M=M, beta=1.0 / T, mu=0.0, precision=g.FP64, seed=2013,
+                          chain_id=7))
+    ch.init_spins(g.INIT_FM)
+    th, ph = oracle.init_spins(m, 1)
+    gth, gph = ch.get_spins()
+    assert np.array_equal(gth, th) and np.array_equal(gph, ph)
+    assert abs(ch.magnetization() - 1.0) < 1e-15
+    idx, forced, mags = 0, 0, []
+    for sweep in range(warm + meas):
+        acc_d = acc_o = own_d = own_o = 0
+        for _ in range(m.N):
+            ro = oracle.step(m, th, ph, idx)
+            rg = ch.step(force=ro.accepted)
+            assert rg.index == idx and rg.site == ro.site and rg.u == ro.u
+            assert abs(rg.dseff - ro.dseff) < 1e-10, (idx, rg.dseff, ro.dseff)
+            if rg.own != ro.own:
+                assert ro.u > 0 and abs(math.log(ro.u) + ro.dseff) < 1e-9, (idx, ro.dseff, ro.u)
+                forced += 1
+            acc_d += rg.accepted
+            acc_o += ro.accepted
+            own_d += rg.own
+            own_o += ro.own
+            idx += 1
+        md, mo = ch.magnetization(), oracle.magnetization(L, th, ph)
+        assert abs(md - mo) < 1e-12, (sweep, md, mo)
+        assert acc_d == acc_o and abs(own_d - own_o) <= forced
+        if sweep >= warm:
+            mags.append(mo)
+    gth, gph = ch.get_spins()
+    assert np.abs(gth - th).max() < 1e-12 and np.abs(gph - ph).max() < 1e-12
+    print(f"T={T}: <|m|> over {meas} sweeps {np.mean(mags):.4f}, forced {forced}", flush=True)
+    if T == 0.05:
+        assert np.mean(mags) > 0.7      # ordered below the melting temperature
+
+
 def test_magnetization_falls_with_temperature(g):
     temps = [0.02, 0.05, 0.1, 0.2, 0.4, 1.0]
     chains = []

@@ -38,6 +38,12 @@ MUTANTS = [
     ("Jackson coefficient", "g[n] = ((M - n + 1.0) * cos(q * n)", "g[n] = ((M - n) * cos(q * n)"),
     ("Lorentz coefficient", "g[n] = sinh(lambda * (1.0 - (double)n / M)) / sinh(lambda);",
      "g[n] = sinh(lambda * (1.0 - (double)n / M));"),
+    ("Lorentz coefficient: M + 1 in the ratio", "g[n] = sinh(lambda * (1.0 - (double)n / M)) / sinh(lambda);",
+     "g[n] = sinh(lambda * (1.0 - (double)n / (M + 1))) / sinh(lambda);"),
+    ("Lorentz coefficient: cosh", "g[n] = sinh(lambda * (1.0 - (double)n / M)) / sinh(lambda);",
+     "g[n] = cosh(lambda * (1.0 - (double)n / M)) / cosh(lambda);"),
+    ("Lorentz coefficient: shifted index", "g[n] = sinh(lambda * (1.0 - (double)n / M)) / sinh(lambda);",
+     "g[n] = sinh(lambda * (1.0 - (double)(n + 1) / M)) / sinh(lambda);"),
     ("green: mu_0 not halved", "if (n == 0) m *= 0.5;", "if (n == 0) m *= 1.0;"),
     ("green: node offset", "double thk = PI * (k + 0.5) / K;\n    cplx s = 0;",
      "double thk = PI * (k + 1.0) / K;\n    cplx s = 0;"),
