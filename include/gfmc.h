@@ -304,6 +304,23 @@ gfmc_status gfmc_batch_set_tuning(gfmc_batch* batch, int32_t pairs_per_thread);
  * EINVAL outside 1..4. */
 gfmc_status gfmc_batch_set_lanes(gfmc_batch* batch, int32_t lanes);
 
+/* Schedule of gfmc_batch_step over chains of different step counts M/2
+ * (independent Markov chains, Section 3 "Parallelization Frameworks";
+ * Algorithm 1 per chain).  0 (default), lock-step: every chain makes exactly
+ * nprop proposals and a chain with fewer steps idles until the longest
+ * chain's proposal ends.  1, step-granular: the chains with the most steps
+ * make nprop proposals in nprop x M_max/2 step rounds, and every other chain
+ * makes as many whole proposals as fit in those rounds, floor(nprop x
+ * M_max / M), each started right after the reconstruction of its last, so a
+ * chain of half the steps makes twice the proposals.  Chains of equal M (per
+ * step lane) draw, step and reconstruct together; every Chebyshev step of
+ * the others runs in one launch per round (per lane) that reads each
+ * chain's step index from the round.  Per-chain results equal the lock-step
+ * ones proposal for proposal.  Step-granular batches take no force or
+ * records (EINVAL); gfmc_batch_sweep always runs lock-step; the LDS-resident
+ * shape (one launch per proposal) is unaffected.  EINVAL outside {0, 1}. */
+gfmc_status gfmc_batch_set_schedule(gfmc_batch* batch, int32_t step_granular);
+
 /* Launch shape (0, 1, 2) and number of step lanes in effect. */
 gfmc_status gfmc_batch_get_tuning(gfmc_batch* batch, int32_t* pairs_per_thread, int32_t* lanes);
 

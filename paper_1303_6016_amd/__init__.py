@@ -97,6 +97,7 @@ _SIGS = {
     "gfmc_batch_step_timing": [_vp, _P(_d), _P(_i64)],
     "gfmc_batch_set_tuning": [_vp, _i32],
     "gfmc_batch_set_lanes": [_vp, _i32],
+    "gfmc_batch_set_schedule": [_vp, _i32],
     "gfmc_batch_get_tuning": [_vp, _P(_i32), _P(_i32)],
     "gfmc_batch_autotune": [_vp, _i32, _P(_i32)],
     "gfmc_engine_create": [ctypes.c_int, _sz, _i32, _P(_vp)],
@@ -361,6 +362,11 @@ class Batch:
     def set_lanes(self, lanes: int):
         """1 to 4 step lanes (>= 2: the chains' steps on that many forked streams)."""
         _check(lib().gfmc_batch_set_lanes(self.h, lanes))
+
+    def set_schedule(self, step_granular: bool):
+        """False: lock-step proposals; True: each chain restarts as soon as its
+        proposal ends (chains with fewer steps make more proposals)."""
+        _check(lib().gfmc_batch_set_schedule(self.h, 1 if step_granular else 0))
 
     def tuning(self):
         """(launch shape, lanes) in effect."""

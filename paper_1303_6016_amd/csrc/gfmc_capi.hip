@@ -171,6 +171,11 @@ gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
     for (int l = 0; l < P.lanes_on; ++l)
       HIPCHK(hipMemcpyAsync(P.d_lane_blkoff[l], P.lane_blkoff[l].data(),
                             P.lane_blkoff[l].size() * sizeof(int), hipMemcpyHostToDevice, P.stream));
+  if (P.d_coh_blkoff)
+    for (auto& C : P.coh)
+      HIPCHK(hipMemcpyAsync(C.d_blkoff, C.blkoff.data(), C.blkoff.size() * sizeof(int),
+                            hipMemcpyHostToDevice, P.stream));
+  P.act_end.clear();   // the device copy is rewritten by the next window
   HIPCHK(hipStreamSynchronize(P.stream));
   return GFMC_OK;
 }
@@ -222,6 +227,28 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
     P.lane_blkoff[l].assign(P.lane_n[l] + 1, 0);
     for (int j = 0; j < P.lane_n[l]; ++j)
       P.lane_blkoff[l][j + 1] = P.blkoff[P.lane_first[l] + j + 1] - P.blkoff[P.lane_first[l]];
+  }
+  // cohorts: runs of equal S within each lane (the chains are sorted by S)
+  P.coh.clear();
+  int used = 0;
+  for (int l = 0; l < k; ++l) {
+    const int f = P.lane_first[l], e = f + P.lane_n[l];
+    for (int i = f; i < e;) {
+      int j = i;
+      while (j < e && P.S[j] == P.S[i]) ++j;
+      Plan::Cohort C;
+      C.lane = l;
+      C.first = i;
+      C.n = j - i;
+      C.S = P.S[i];
+      for (int q = i; q < j; ++q) C.kmax = std::max(C.kmax, sorted[q]->d.K);
+      C.blkoff.assign(C.n + 1, 0);
+      for (int q = 0; q < C.n; ++q) C.blkoff[q + 1] = P.blkoff[i + q + 1] - P.blkoff[i];
+      if (P.d_coh_blkoff) C.d_blkoff = P.d_coh_blkoff + used;
+      used += C.n + 1;
+      P.coh.push_back(std::move(C));
+      i = j;
+    }
   }
 }
 
@@ -303,6 +330,87 @@ gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* 
   if (P.timing) P.step_launches += P.resident ? 1 : P.smax;
   HIPCHK(launch_moments(P.ov, P.d_desc, P.n, P.smax, P.stream));
   if (with_recon) HIPCHK(launch_recon(P.fp32, P.d_desc, P.n, P.kmax, d_force, d_rec, P.stream));
+  return GFMC_OK;
+}
+
+gfmc_status enqueue_window(Plan& P, int rounds, const int* cap, int* props, bool enqueue) {
+  if (!P.d_act_end || !P.d_coh_blkoff) return fail(GFMC_ESTATE, "plan has no window tables");
+  const int n = P.n, k = P.lanes_on;
+  // proposals and last active round of every chain
+  std::vector<int> act(n), np(n);
+  for (int c = 0; c < n; ++c) {
+    np[c] = rounds / P.S[c];
+    if (cap) np[c] = std::min(np[c], std::max(cap[c], 0));
+  }
+  // a cohort draws, steps and reconstructs together, so all of its chains run
+  // the same number of proposals: the smallest of their counts
+  std::vector<int> cp(P.coh.size());
+  for (size_t q = 0; q < P.coh.size(); ++q) {
+    const auto& C = P.coh[q];
+    cp[q] = np[C.first];
+    for (int i = C.first; i < C.first + C.n; ++i) cp[q] = std::min(cp[q], np[i]);
+    for (int i = C.first; i < C.first + C.n; ++i) np[i] = cp[q];
+  }
+  for (int c = 0; c < n; ++c) {
+    act[c] = np[c] * P.S[c];
+    if (props) props[c] = np[c];
+  }
+  if (act != P.act_end) {   // stream-ordered before the window's launches
+    P.act_end = act;
+    HIPCHK(hipMemcpyAsync(P.d_act_end, P.act_end.data(), n * sizeof(int), hipMemcpyHostToDevice,
+                          P.stream));
+  }
+  if (!enqueue) return GFMC_OK;
+  auto lane_st = [&](int l) { return k >= 2 ? P.lane_stream[l] : P.stream; };
+  if (k >= 2) {
+    HIPCHK(hipEventRecord(P.fork, P.stream));
+    for (int l = 0; l < k; ++l) HIPCHK(hipStreamWaitEvent(P.lane_stream[l], P.fork, 0));
+  }
+  // start of a proposal of cohort q: draw, and step 1 over the cohort alone
+  auto start = [&](size_t q) -> gfmc_status {
+    const auto& C = P.coh[q];
+    hipStream_t st = lane_st(C.lane);
+    HIPCHK(launch_propose(P.d_desc + C.first, C.n, st));
+    HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc + C.first, C.d_blkoff, C.n,
+                       C.blkoff[C.n], 1, st));
+    return GFMC_OK;
+  };
+  auto finish = [&](size_t q) -> gfmc_status {
+    const auto& C = P.coh[q];
+    hipStream_t st = lane_st(C.lane);
+    HIPCHK(launch_moments(P.ov, P.d_desc + C.first, C.n, C.S, st));
+    HIPCHK(launch_recon(P.fp32, P.d_desc + C.first, C.n, C.kmax, nullptr, nullptr, st));
+    return GFMC_OK;
+  };
+  // round r: cohorts whose next proposal starts here draw it and take step 1;
+  // one launch per lane takes every other active chain one step; cohorts whose
+  // proposal ends with this round reconstruct it (stream order then puts their
+  // next start after it)
+  for (int r = 1; r <= rounds; ++r) {
+    for (size_t q = 0; q < P.coh.size(); ++q) {
+      const int S = P.coh[q].S;
+      if ((r - 1) % S == 0 && r <= cp[q] * S) CHK(start(q));
+    }
+    for (int l = 0; l < k; ++l) {
+      const int f = k >= 2 ? P.lane_first[l] : 0, nl = k >= 2 ? P.lane_n[l] : n;
+      const int* bo = k >= 2 ? P.d_lane_blkoff[l] : P.d_blkoff;
+      const int blocks = k >= 2 ? P.lane_blkoff[l][nl] : P.blkoff[n];
+      bool any = false;
+      for (int i = f; i < f + nl && !any; ++i) any = r <= act[i] && (r - 1) % P.S[i] != 0;
+      if (any)
+        HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc + f, bo, nl, blocks, r,
+                           lane_st(l), P.d_act_end + f));
+    }
+    for (size_t q = 0; q < P.coh.size(); ++q) {
+      const int S = P.coh[q].S;
+      if (r % S == 0 && r <= cp[q] * S) CHK(finish(q));
+    }
+  }
+  if (k >= 2)
+    for (int l = 0; l < k; ++l) {
+      HIPCHK(hipEventRecord(P.join[l], P.lane_stream[l]));
+      HIPCHK(hipStreamWaitEvent(P.stream, P.join[l], 0));
+    }
   return GFMC_OK;
 }
 
@@ -679,7 +787,8 @@ gfmc_status gfmc_chain_step_bytes(gfmc_chain* c, double* bytes_per_step, int32_t
 // ---------------------------------------------------------------- batches
 static size_t batch_bytes(int n) {
   return align256((size_t)n * sizeof(Desc)) + align256((size_t)(n + 1) * sizeof(int)) +
-         align256((size_t)(n + kMaxLanes) * sizeof(int)) +
+         align256((size_t)(n + kMaxLanes) * sizeof(int)) + align256((size_t)n * sizeof(int)) +
+         align256((size_t)(2 * n + 8) * sizeof(int)) +
          align256((size_t)kRecCap * n * sizeof(int32_t)) +
          align256((size_t)kRecCap * n * sizeof(gfmc_step_record)) +
          align256((size_t)kMagCap * n * sizeof(double));
@@ -727,6 +836,8 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
   P.d_blkoff = (int*)w; w += align256((size_t)(n + 1) * sizeof(int));
   P.d_lane_blkoff[0] = (int*)w;   // the lane tables, n + kMaxLanes ints (split in plan_shape)
   w += align256((size_t)(n + kMaxLanes) * sizeof(int));
+  P.d_act_end = (int*)w; w += align256((size_t)n * sizeof(int));
+  P.d_coh_blkoff = (int*)w; w += align256((size_t)(2 * n + 8) * sizeof(int));
   P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * n * sizeof(int32_t));
   P.d_rec = (gfmc_step_record*)w; w += align256((size_t)kRecCap * n * sizeof(gfmc_step_record));
   P.d_mag = (double*)w;
@@ -770,10 +881,18 @@ gfmc_status gfmc_batch_use_graph(gfmc_batch* b, int32_t enable) {
   if (P.stream == nullptr) return fail(GFMC_EINVAL, "graph capture needs a non-default stream");
   if (!P.gexec) {
     HIPCHK(hipStreamSynchronize(P.stream));
-    HIPCHK(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal));
+    if (!(P.cont && !P.resident))
+      HIPCHK(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal));
     const bool tm = P.timing;
     P.timing = false;
-    gfmc_status st = enqueue_proposal(P, nullptr, nullptr, true);
+    const bool win = P.cont && !P.resident;
+    if (win) {   // the window's tables go to the device before the capture
+      CHK(enqueue_window(P, P.smax, nullptr, nullptr, false));
+      HIPCHK(hipStreamSynchronize(P.stream));
+      HIPCHK(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal));
+    }
+    gfmc_status st = win ? enqueue_window(P, P.smax, nullptr, nullptr, true)
+                         : enqueue_proposal(P, nullptr, nullptr, true);
     P.timing = tm;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(P.stream, &g);
@@ -803,6 +922,22 @@ gfmc_status gfmc_batch_step(gfmc_batch* b, int32_t nprop, const int32_t* force,
       }
   }
   std::vector<gfmc_step_record> r(recs ? (size_t)nprop * n : 0);
+  if (P.cont && !P.resident && !b->use_graph) {
+    if (force || recs)
+      return fail(GFMC_EINVAL, "the step-granular schedule takes no force or records");
+    if (nprop == 0) return GFMC_OK;
+    HIPCHK(hipStreamSynchronize(P.stream));
+    CHK(timing_begin(P, 1));
+    HIPCHK(hipEventRecord(P.ev[0], P.stream));
+    CHK(enqueue_window(P, nprop * P.smax, nullptr, nullptr, true));
+    HIPCHK(hipEventRecord(P.ev[1], P.stream));
+    P.ev_used = 2;
+    CHK(timing_end(P));
+    P.step_launches = (int64_t)nprop * P.smax;   // step rounds of the window
+    return GFMC_OK;
+  }
+  if (b->use_graph && P.cont && !P.resident && (force || recs))
+    return fail(GFMC_EINVAL, "the step-granular schedule takes no force or records");
   if (b->use_graph && !force && !recs) {
     HIPCHK(hipStreamSynchronize(P.stream));
     CHK(timing_begin(P, 1));
@@ -896,6 +1031,20 @@ gfmc_status gfmc_batch_set_lanes(gfmc_batch* b, int32_t lanes) {
   P.lanes = lanes;
   plan_shape(P, b->sorted);
   CHK(upload_plan(P, b->sorted));
+  const bool g = b->use_graph;
+  drop_graph(P);
+  b->use_graph = false;
+  if (g) return gfmc_batch_use_graph(b, 1);
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_set_schedule(gfmc_batch* b, int32_t step_granular) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  if (step_granular != 0 && step_granular != 1)
+    return fail(GFMC_EINVAL, "step_granular must be 0 or 1");
+  Plan& P = b->plan;
+  HIPCHK(hipStreamSynchronize(P.stream));
+  P.cont = step_granular;
   const bool g = b->use_graph;
   drop_graph(P);
   b->use_graph = false;

@@ -84,6 +84,7 @@ struct Request {
   gfmc_chain* chain = nullptr;
   size_t off = 0, bytes = 0;
   int64_t done_props = 0;
+  int64_t step_props = 0;   // proposals enqueued for it in the current iteration
   int sweeps = 0;
   double mag_last = 0, mag_sum = 0;
 };
@@ -168,6 +169,7 @@ struct gfmc_engine {
 
 static size_t plan_bytes(int n) {
   return align256((size_t)n * sizeof(Desc)) + align256((size_t)(n + 1) * sizeof(int)) +
+         align256((size_t)n * sizeof(int)) + align256((size_t)(2 * n + 8) * sizeof(int)) +
          align256((size_t)kRecCap * n * sizeof(int32_t)) +
          align256((size_t)kRecCap * n * sizeof(gfmc_step_record)) +
          align256((size_t)kMagCap * n * sizeof(double));
@@ -233,17 +235,15 @@ static void retire(gfmc_engine* E, Request* r, gfmc_status st) {
 // re-upload every non-empty plan (a new chain may reuse the host address of a
 // retired one, so equal pointer lists do not mean equal descriptors).
 static gfmc_status refresh_groups(gfmc_engine* E) {
-  std::vector<gfmc_chain*> lists[kGroups];
   for (int g = 0; g < kGroups; ++g) E->groups[g].reqs.clear();
-  for (auto* r : E->running) {
-    lists[group_of(r->d)].push_back(r->chain);
-    E->groups[group_of(r->d)].reqs.push_back(r);
-  }
+  for (auto* r : E->running) E->groups[group_of(r->d)].reqs.push_back(r);
   for (int g = 0; g < kGroups; ++g) {
-    auto& L = lists[g];
-    std::stable_sort(L.begin(), L.end(),
-                     [](gfmc_chain* a, gfmc_chain* b) { return a->d.S > b->d.S; });
     Group& G = E->groups[g];
+    // plan order: most Chebyshev steps first (requests and chains alike)
+    std::stable_sort(G.reqs.begin(), G.reqs.end(),
+                     [](const Request* a, const Request* b) { return a->d.S > b->d.S; });
+    std::vector<gfmc_chain*> L;
+    for (auto* r : G.reqs) L.push_back(r->chain);
     G.members = L;
     if (L.empty()) continue;
     plan_shape(G.plan, L);
@@ -254,10 +254,15 @@ static gfmc_status refresh_groups(gfmc_engine* E) {
   return GFMC_OK;
 }
 
-// One iteration: every group advances its chains by reps proposals, reps
-// about the ratio of the costliest group's proposal to its own (so chains
-// of every size progress at a similar device-time rate), at most kMaxReps
-// and never past a member's next sweep boundary (|m| is taken there).
+// One iteration: every group advances its chains by about reps proposals,
+// reps about the ratio of the costliest group's proposal to its own (so
+// chains of every size progress at a similar device-time rate), at most
+// kMaxReps, and no chain past its next sweep boundary (|m| is taken there).
+// LDS-resident groups run reps lock-step proposals.  Multi-block groups run
+// a step-granular window of reps x (their most steps) rounds: the chains with
+// the most steps make reps proposals and every other chain as many as fit,
+// each restarting as soon as its last proposal is reconstructed, capped at
+// its sweep boundary.
 static gfmc_status iterate(gfmc_engine* E) {
   if (E->members_changed) CHK(refresh_groups(E));
   double cmax = 0;
@@ -267,10 +272,28 @@ static gfmc_status iterate(gfmc_engine* E) {
     Group& G = E->groups[g];
     if (G.members.empty()) continue;
     int reps = (int)std::min((double)kMaxReps, std::max(1.0, cmax / std::max(G.cost, 1.0)));
-    for (auto* r : G.reqs)
-      reps = (int)std::min<int64_t>(reps, r->d.N - r->done_props % r->d.N);
-    G.reps = reps;
-    for (int k = 0; k < reps; ++k) CHK(enqueue_proposal(G.plan, nullptr, nullptr, true));
+    if (G.plan.cont && !G.plan.resident) {
+      // members are in plan order (most steps first), as the plan's tables
+      const int n = (int)G.members.size();
+      std::vector<int> cap(n), props(n);
+      int64_t rmax = 0;
+      for (int i = 0; i < n; ++i) {
+        const Request* r = G.reqs[i];
+        cap[i] = (int)std::min<int64_t>(kMaxReps * 64, r->d.N - r->done_props % r->d.N);
+        rmax = std::max<int64_t>(rmax, (int64_t)cap[i] * r->d.S);
+      }
+      // the window never outlasts every chain's sweep boundary
+      const int rounds = (int)std::min<int64_t>((int64_t)reps * G.plan.smax, rmax);
+      CHK(enqueue_window(G.plan, rounds, cap.data(), props.data()));
+      for (int i = 0; i < n; ++i) G.reqs[i]->step_props = props[i];
+      G.reps = reps;
+    } else {
+      for (auto* r : G.reqs)
+        reps = (int)std::min<int64_t>(reps, r->d.N - r->done_props % r->d.N);
+      G.reps = reps;
+      for (int k = 0; k < reps; ++k) CHK(enqueue_proposal(G.plan, nullptr, nullptr, true));
+      for (auto* r : G.reqs) r->step_props = reps;
+    }
   }
   return GFMC_OK;
 }
@@ -337,7 +360,7 @@ static void worker_main(gfmc_engine* E) {
     // queued requests are not kept behind a long run of enqueued work).
     bool boundary_now = false, pending = false;
     for (auto* r : E->running)
-      boundary_now |= ((r->done_props + E->groups[group_of(r->d)].reps) % r->d.N == 0);
+      boundary_now |= r->step_props > 0 && ((r->done_props + r->step_props) % r->d.N == 0);
     {
       std::lock_guard<std::mutex> g(E->mu);
       pending = !E->queue.empty();
@@ -359,8 +382,10 @@ static void worker_main(gfmc_engine* E) {
     const double t = E->now();
     std::vector<Request*> boundary;
     for (auto* r : E->running) {
-      r->done_props += E->groups[group_of(r->d)].reps;
-      if (r->done_props % r->d.N == 0) boundary.push_back(r);
+      const int64_t k = r->step_props;
+      r->done_props += k;
+      r->step_props = 0;
+      if (k > 0 && r->done_props % r->d.N == 0) boundary.push_back(r);
     }
     if (boundary.empty()) continue;
     std::vector<double> mags(boundary.size());
@@ -440,6 +465,9 @@ gfmc_status gfmc_engine_create(int device, size_t budget, int32_t max_slots, gfm
     P.ppt = (g & 8) ? 0 : 1;   // LDS-resident groups, else one site pair per thread
     P.d_desc = (Desc*)w; w += align256((size_t)max_slots * sizeof(Desc));
     P.d_blkoff = (int*)w; w += align256((size_t)(max_slots + 1) * sizeof(int));
+    P.d_act_end = (int*)w; w += align256((size_t)max_slots * sizeof(int));
+    P.d_coh_blkoff = (int*)w; w += align256((size_t)(2 * max_slots + 8) * sizeof(int));
+    P.cont = (g & 8) ? 0 : 1;   // multi-block groups: step-granular windows
     P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * max_slots * sizeof(int32_t));
     P.d_rec = (gfmc_step_record*)w;
     w += align256((size_t)kRecCap * max_slots * sizeof(gfmc_step_record));

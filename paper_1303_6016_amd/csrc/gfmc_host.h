@@ -10,8 +10,11 @@
 
 namespace gfmc {
 hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
+// One Chebyshev step launch over chains [0, nact) of table d.  act_end NULL:
+// every chain takes step s.  act_end non-NULL: s is the round of a window and
+// chain c takes step (s - 1) mod S_c + 1 while s <= act_end[c] (never step 1).
 hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const int* blkoff,
-                       int nact, int blocks, int s, hipStream_t st);
+                       int nact, int blocks, int s, hipStream_t st, const int* act_end = nullptr);
 hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st);
 hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
                         gfmc_step_record* recs, hipStream_t st);
@@ -95,6 +98,22 @@ struct Plan {
   // graph replay of one proposal
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // Step-granular schedule (cont = 1): within a window each chain runs its
+  // proposals back to back, a chain of S steps starting its next proposal
+  // right after the step rounds of its last, so chains with fewer steps make
+  // more proposals while longer ones keep stepping.  A cohort is a run of
+  // chains of one lane with equal S: they start, finish and reconstruct
+  // together.  act_end[c] is chain c's last active round of the window.
+  int cont = 0;
+  struct Cohort {
+    int lane = 0, first = 0, n = 0, S = 0, kmax = 0;
+    std::vector<int> blkoff;            // n + 1 block offsets within the cohort
+    int* d_blkoff = nullptr;
+  };
+  std::vector<Cohort> coh;
+  int* d_coh_blkoff = nullptr;          // device region of 2 n + 8 ints (cohort tables)
+  int* d_act_end = nullptr;             // device [n], plan order
+  std::vector<int> act_end;             // host copy of what the device holds
 };
 
 struct gfmc_chain {
@@ -130,6 +149,11 @@ gfmc_status enqueue_steps(Plan& P, int s_first, int s_last);
 void release_lanes(Plan& P);
 gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* d_rec,
                              bool with_recon);
+// Step-granular window of `rounds` step rounds (cont = 1): chain c runs
+// min(rounds / S_c, cap[c]) whole proposals (cap NULL: no cap) and
+// props[c] (plan order, may be NULL) receives that count.
+// enqueue = false only computes the counts and uploads act_end (before a capture).
+gfmc_status enqueue_window(Plan& P, int rounds, const int* cap, int* props, bool enqueue = true);
 gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived& d, void* ws,
                         size_t bytes, hipStream_t stream);
 gfmc_status chain_init_spins(gfmc_chain* c, int mode, double frac);

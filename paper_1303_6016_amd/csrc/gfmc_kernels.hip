@@ -104,11 +104,19 @@ __device__ inline spn<T> make_spinor(double th, double ph) {
 }
 
 // <chi_i|chi_j> = t_ij (the same amplitude as equation "ht", from cached
-// half-angle factors).
+// half-angle factors), formed in FP64 and rounded once to the recursion
+// precision T.  With FP32 spinors, forming the four products and their sum
+// in FP32 leaves an absolute error of a few 1e-8 on every amplitude, also on
+// small ones (nearly opposite spins), and that perturbation of the
+// Hamiltonian, not the rounding of the recursion, dominates the error of the
+// FP32 moments: forming it in FP64 from the same FP32 spinors cuts the
+// moment error about tenfold for the same bytes.
 template <typename T>
 __device__ inline void hop_spinor(const spn<T>& a, const spn<T>& b, T& re, T& im) {
-  re = a.ar * b.ar + a.ai * b.ai + a.br * b.br + a.bi * b.bi;
-  im = a.ar * b.ai - a.ai * b.ar + a.br * b.bi - a.bi * b.br;
+  const double ar = a.ar, ai = a.ai, br = a.br, bi = a.bi;
+  const double cr = b.ar, ci = b.ai, dr = b.br, di = b.bi;
+  re = (T)(ar * cr + ai * ci + br * dr + bi * di);
+  im = (T)(ar * ci - ai * cr + br * di - bi * dr);
 }
 
 // Block b of a grid of nb blocks runs on XCD b % 8; give each XCD a
@@ -364,10 +372,25 @@ __device__ inline double gram_combo(const double (*gsum)[256], const Combo& k) {
   return a + k.sg * b;
 }
 
+// Step index of a chain in a launch.  Lock-step launches (act_end == NULL)
+// give every chain the launch's step s.  Round launches (act_end != NULL)
+// pass the round r of a window in which each chain runs its proposals back
+// to back, S steps each: the chain is at step (r - 1) mod S + 1 of its
+// current proposal while r <= act_end[c] (its last active round), and idle
+// after it; step 1 of each proposal runs in a launch of its own (it also
+// writes the start vectors), so round launches skip it.  Returns 0 for a
+// chain that does not step in this launch.
+__device__ inline int chain_step(int s, const int* __restrict__ act_end, int c, int S) {
+  if (!act_end) return s;
+  if (s > act_end[c]) return 0;
+  const int sl = (s - 1) % S + 1;
+  return sl == 1 ? 0 : sl;
+}
+
 template <typename T, bool FIRST, int PPT, bool HOPS>
 __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ descs,
                                                        const int* __restrict__ blkoff, int nact,
-                                                       int s) {
+                                                       int s_arg, const int* __restrict__ act_end) {
   __shared__ double xs[4][16][17];
   __shared__ double gsum[4][256];
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
@@ -381,6 +404,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
     c = lo;
   }
   const Desc& D = descs[c];
+  const int s = chain_step(s_arg, act_end, c, D.S);
+  if (s == 0) return;   // uniform over the block: the chain does not step now
   const int lb = gb - blkoff[c];
   const int L = D.L, hx = L >> 1, half = D.half;
   const Ctl* ctl = D.ctl;
@@ -730,7 +755,8 @@ __device__ inline double sum_run(const double* __restrict__ src, int n) {
 template <typename T, bool FIRST, int PPT>
 __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict__ descs,
                                                           const int* __restrict__ blkoff,
-                                                          int nact, int s) {
+                                                          int nact, int s_arg,
+                                                          const int* __restrict__ act_end) {
   __shared__ double red[4][kNP2];
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
   int c = 0;
@@ -743,6 +769,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
     c = lo;
   }
   const Desc& D = descs[c];
+  const int s = chain_step(s_arg, act_end, c, D.S);
+  if (s == 0) return;   // uniform over the block: the chain does not step now
   const int lb = gb - blkoff[c];
   const int L = D.L, hx = L >> 1, half = D.half;
   const Ctl* ctl = D.ctl;
@@ -1411,34 +1439,38 @@ hipError_t launch_propose(const Desc* d, int n, hipStream_t st) {
 
 template <typename T, int PPT, bool HOPS>
 hipError_t launch_step_t(int ov, const Desc* d, const int* blkoff, int nact, int blocks, int s,
-                         hipStream_t st) {
+                         const int* act_end, hipStream_t st) {
   const dim3 g(blocks), b(kStepThreads);
+  // round launches (act_end) never run step 1: it has a launch of its own
+  const bool first = !act_end && s == 1;
   if (ov) {
-    if (s == 1) hipLaunchKernelGGL((k_step_ov<T, true, PPT>), g, b, 0, st, d, blkoff, nact, s);
-    else hipLaunchKernelGGL((k_step_ov<T, false, PPT>), g, b, 0, st, d, blkoff, nact, s);
-  } else {
-    if (s == 1)
-      hipLaunchKernelGGL((k_step<T, true, PPT, HOPS>), g, b, 0, st, d, blkoff, nact, s);
+    if (first)
+      hipLaunchKernelGGL((k_step_ov<T, true, PPT>), g, b, 0, st, d, blkoff, nact, s, act_end);
     else
-      hipLaunchKernelGGL((k_step<T, false, PPT, HOPS>), g, b, 0, st, d, blkoff, nact, s);
+      hipLaunchKernelGGL((k_step_ov<T, false, PPT>), g, b, 0, st, d, blkoff, nact, s, act_end);
+  } else {
+    if (first)
+      hipLaunchKernelGGL((k_step<T, true, PPT, HOPS>), g, b, 0, st, d, blkoff, nact, s, act_end);
+    else
+      hipLaunchKernelGGL((k_step<T, false, PPT, HOPS>), g, b, 0, st, d, blkoff, nact, s, act_end);
   }
   return hipGetLastError();
 }
 
 template <typename T, bool HOPS>
 hipError_t launch_step_h(int ov, int ppt, const Desc* d, const int* blkoff, int nact, int blocks,
-                         int s, hipStream_t st) {
-  return ppt == 2 ? launch_step_t<T, 2, HOPS>(ov, d, blkoff, nact, blocks, s, st)
-                  : launch_step_t<T, 1, HOPS>(ov, d, blkoff, nact, blocks, s, st);
+                         int s, const int* act_end, hipStream_t st) {
+  return ppt == 2 ? launch_step_t<T, 2, HOPS>(ov, d, blkoff, nact, blocks, s, act_end, st)
+                  : launch_step_t<T, 1, HOPS>(ov, d, blkoff, nact, blocks, s, act_end, st);
 }
 
 hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const int* blkoff,
-                       int nact, int blocks, int s, hipStream_t st) {
+                       int nact, int blocks, int s, hipStream_t st, const int* act_end) {
   if (fp32)
-    return hops ? launch_step_h<float, true>(ov, ppt, d, blkoff, nact, blocks, s, st)
-                : launch_step_h<float, false>(ov, ppt, d, blkoff, nact, blocks, s, st);
-  return hops ? launch_step_h<double, true>(ov, ppt, d, blkoff, nact, blocks, s, st)
-              : launch_step_h<double, false>(ov, ppt, d, blkoff, nact, blocks, s, st);
+    return hops ? launch_step_h<float, true>(ov, ppt, d, blkoff, nact, blocks, s, act_end, st)
+                : launch_step_h<float, false>(ov, ppt, d, blkoff, nact, blocks, s, act_end, st);
+  return hops ? launch_step_h<double, true>(ov, ppt, d, blkoff, nact, blocks, s, act_end, st)
+              : launch_step_h<double, false>(ov, ppt, d, blkoff, nact, blocks, s, act_end, st);
 }
 
 hipError_t launch_hops(int fp32, const Desc* d, int nmax, hipStream_t st) {

@@ -78,3 +78,35 @@ def test_null_handles_and_bad_arguments_are_rejected_on_the_host():
     assert e.value.status == EINVAL
     assert L.gfmc_chain_destroy(None) == g.GFMC_OK and L.gfmc_batch_destroy(None) == g.GFMC_OK
     assert L.gfmc_last_error()
+
+
+# The validated range of the FP32 recursion (include/gfmc.h, gfmc_precision):
+# just inside and just outside its edges in M and in beta t.
+FP32_EDGES = [(2, 512), (4, 1024), (6, 1024), (8, 2048), (16, 2048), (24, 2048), (32, 8192),
+              (64, 8192)]
+
+
+@pytest.mark.parametrize("L,M", FP32_EDGES)
+def test_fp32_guard_edges_in_moment_count(L, M):
+    import paper_1303_6016_amd as g
+    assert _bytes(L=L, M=M, precision=1, beta=50.0) > 0
+    if M < 8192:
+        with pytest.raises(g.GfmcError) as e:
+            _bytes(L=L, M=M + 2, K=2 * M, precision=1, beta=20.0)
+        assert e.value.status == g.GFMC_EINVAL and "validated" in str(e.value)
+        # FP64 has no such limit; FP32 outside the range is available for measuring its error
+        assert _bytes(L=L, M=M + 2, K=2 * M, precision=0) > 0
+        assert _bytes(L=L, M=M + 2, K=2 * M, precision=1, fp32_unvalidated=1) > 0
+
+
+def test_fp32_guard_edge_in_beta():
+    import paper_1303_6016_amd as g
+    assert _bytes(L=32, M=2048, precision=1, beta=1.0 / 0.02) > 0
+    assert _bytes(L=32, M=2048, precision=1, beta=25.0, t=2.0) > 0
+    for kw in (dict(beta=50.001), dict(beta=26.0, t=2.0)):
+        with pytest.raises(g.GfmcError) as e:
+            _bytes(L=32, M=2048, precision=1, **kw)
+        assert e.value.status == g.GFMC_EINVAL
+    assert _bytes(L=32, M=2048, precision=0, beta=1000.0) > 0
+    with pytest.raises(g.GfmcError):
+        _bytes(L=32, M=2048, precision=1, fp32_unvalidated=2)
