@@ -390,6 +390,26 @@ gfmc_status gfmc_engine_drain(gfmc_engine* engine, double timeout_s);
 /* Stop the worker (running requests are cancelled) and free the device memory. */
 gfmc_status gfmc_engine_destroy(gfmc_engine* engine);
 
+/* ----------------------------------------------------- allocation-free --
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): Delta S_eff
+ * exactly as gfmc_delta_seff computes it (same kernels, same launch shape,
+ * same value), for the spins in the caller's device arrays d_theta[N] and
+ * d_phi[N] (FP64, read only) and the move of `site` to (theta_new, phi_new),
+ * with no chain handle and no workspace.  Every intermediate buffer lives in
+ * a static device array of the library, 64 MiB per device, held from the
+ * first use of the library on that device until the process ends; no call
+ * allocates or frees device memory.  Parameters whose buffers exceed 64 MiB
+ * (e.g. 32^3 with M above 2048, 64^3) return EINVAL.  All work is enqueued on
+ * `hip_stream` (NULL: the default stream); *d_dseff and, if non-NULL,
+ * *d_phase_top are device doubles written by the last kernel.  The array is
+ * shared by every call on a device: calls that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller. */
+gfmc_status gfmc_delta_seff_static(const gfmc_chain_params* params, const double* d_theta,
+                                   const double* d_phi, int32_t site, double theta_new,
+                                   double phi_new, double* d_dseff, double* d_phase_top,
+                                   void* hip_stream);
+
 /* ------------------------------------------------------------ calibration --
  * Streaming bandwidth of the device, the practical ceiling against which the
  * step kernel's algorithmic bandwidth is read (no paper passage: measurement

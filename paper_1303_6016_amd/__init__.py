@@ -109,6 +109,7 @@ _SIGS = {
     "gfmc_engine_drain": [_vp, _d],
     "gfmc_engine_destroy": [_vp],
     "gfmc_stream_bandwidth": [_i32, _vp, _vp, _vp, _sz, _i32, _vp, _P(_d)],
+    "gfmc_delta_seff_static": [_P(ChainParams), _vp, _vp, _i32, _d, _d, _vp, _vp, _vp],
 }
 EXPORTS = list(_SIGS) + ["gfmc_status_string", "gfmc_last_error", "gfmc_version"]
 

@@ -703,6 +703,123 @@ gfmc_status gfmc_delta_seff(gfmc_chain* c, int32_t site, double tn, double pn, d
 
 }  // extern "C"
 
+// ------------------------------------------- allocation-free evaluation --
+// gfmc_delta_seff_static evaluates Delta S_eff like gfmc_delta_seff, but every
+// buffer the kernels use beyond the caller's inputs and output (descriptor,
+// control block, spinor cache, vectors, moment partials and table,
+// reconstruction scratch and tables) lives in one file-scope device array,
+// `scratch`, of kStaticScratchBytes.  Each device holds its own copy from
+// the moment the library's code object is loaded until the process ends;
+// its device address is looked up once per device and kept.  Every call on
+// a device shares that device's array: calls that overlap on one device
+// (different streams, or threads) race.  Nothing is allocated per call.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static char* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+static gfmc_status scratch_base(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(GFMC_EDEVICE, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    // with `dev` current: each device holds the array at its own address
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(GFMC_EDEVICE, "scratch array has no device address");
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GFMC_OK;
+}
+
+// Descriptor, block offsets and control block of the evaluation, written on
+// the device from kernel arguments (no host-to-device copy, so the sequence
+// can be captured): the control block is cleared, then given the move.
+__global__ void k_static_setup(Desc* __restrict__ desc, Desc D, int* __restrict__ blkoff,
+                               int nblk_total, int site, double tn, double pn) {
+  Ctl* ctl = D.ctl;
+  int* w = (int*)ctl;
+  for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int)); i += blockDim.x) w[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    desc[0] = D;
+    blkoff[0] = 0;
+    blkoff[1] = nblk_total;
+    ctl->mode = 1;
+    ctl->site = site;
+    ctl->th_new = tn;
+    ctl->ph_new = pn;
+  }
+}
+
+__global__ void k_static_out(const Ctl* __restrict__ ctl, double* __restrict__ dseff,
+                             double* __restrict__ phase_top) {
+  dseff[0] = ctl->dseff;
+  if (phase_top) phase_top[0] = ctl->phase_top;
+}
+
+extern "C" gfmc_status gfmc_delta_seff_static(const gfmc_chain_params* p, const double* d_theta,
+                                              const double* d_phi, int32_t site, double tn,
+                                              double pn, double* d_dseff, double* d_phase_top,
+                                              void* hip_stream) {
+  Derived d;
+  CHK(derive(p, d));
+  if (!d_theta || !d_phi || !d_dseff) return fail(GFMC_EINVAL, "theta/phi/dseff is NULL");
+  if (site < 0 || site >= d.N) return fail(GFMC_EINVAL, "site out of range");
+  if (!std::isfinite(tn) || !std::isfinite(pn)) return fail(GFMC_EINVAL, "angles not finite");
+  const Layout l = layout_of(d);
+  if (l.total > kStaticScratchBytes)
+    return fail(GFMC_EINVAL, "these parameters need " + std::to_string(l.total) +
+                                 " bytes of scratch; the static array holds " +
+                                 std::to_string(kStaticScratchBytes));
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  char* base = nullptr;
+  CHK(scratch_base(dev, &base));
+  hipStream_t st = (hipStream_t)hip_stream;
+  // a host-side chain handle over the scratch array (no host or device
+  // allocation: its plan's tables stay empty); it never leaves this call
+  gfmc_chain c;
+  c.p = *p;
+  c.d = d;
+  c.l = l;
+  c.ws = base;
+  c.bytes = kStaticScratchBytes;
+  c.stream = st;
+  c.device = dev;
+  fill_desc(&c);
+  c.desc.theta = const_cast<double*>(d_theta);   // read only: evaluation never accepts
+  c.desc.phi = const_cast<double*>(d_phi);
+  // the single-chain launch shape of gfmc_chain_create: the LDS-resident
+  // kernel where the chain fits, else one multi-block launch per step with
+  // one site pair per thread
+  const bool resident = resident_ok(d);
+  Desc D = c.desc;
+  D.nblk = resident ? 1 : blocks_of(d, 1);
+  Desc* d_desc = (Desc*)(base + l.desc);
+  int* d_blkoff = (int*)(base + l.blkoff);
+  hipLaunchKernelGGL(k_static_setup, dim3(1), dim3(64), 0, st, d_desc, D, d_blkoff, D.nblk, site,
+                     tn, pn);
+  HIPCHK(hipGetLastError());
+  HIPCHK(launch_spinors(d.fp32, d_desc, 1, d.N, st));
+  if (d.hops) HIPCHK(launch_hops(d.fp32, d_desc, d.N, st));
+  HIPCHK(launch_tables(d_desc, d.K, st));
+  // one proposal in evaluation mode, the launch sequence of enqueue_proposal
+  HIPCHK(launch_propose(d_desc, 1, st));
+  if (resident) {
+    HIPCHK(launch_resident(d.fp32, d_desc, 1, resident_lds(d), st));
+  } else {
+    for (int s = 1; s <= d.S; ++s)
+      HIPCHK(launch_step(d.fp32, d.ov, d.hops, 1, d_desc, d_blkoff, 1, D.nblk, s, st));
+  }
+  HIPCHK(launch_moments(d.ov, d_desc, 1, d.S, st));
+  HIPCHK(launch_recon(d.fp32, d_desc, 1, d.K, nullptr, nullptr, st));
+  hipLaunchKernelGGL(k_static_out, dim3(1), dim3(1), 0, st, D.ctl, d_dseff, d_phase_top);
+  HIPCHK(hipGetLastError());
+  return GFMC_OK;
+}
+
 // nprop proposals of every chain in the plan.  force: host [nprop][n] or NULL;
 // recs: host [nprop][n] or NULL.  Host arrays are in sorted plan order.
 static gfmc_status run_proposals(Plan& P, int nprop, const int32_t* force,
