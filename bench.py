@@ -56,13 +56,16 @@ def parse():
     ap.add_argument("--no-fp64-single", action="store_true")
     ap.add_argument("--graph", type=int, default=0, help="replay one proposal as a HIP graph")
     ap.add_argument("--tuning", type=str, default="",
-                    help="PPT,LANES: fix the launch shape and step lanes instead of autotuning")
+                    help="PPT,LANES[,NT]: fix the launch shape, step lanes and non-temporal access "
+                         "instead of autotuning")
     ap.add_argument("--pair", type=int, default=1,
                     help="also time the {o, v} start-vector form on the same workload")
     ap.add_argument("--stored-hops", type=int, default=1,
                     help="also time the stored-hopping A/B variant of the step kernel")
     ap.add_argument("--small", type=int, default=1,
                     help="also time the 4^3 and 16^3 FP64 workloads")
+    ap.add_argument("--hbm", type=int, default=1,
+                    help="also time the step kernel with working sets above the last-level cache")
     ap.add_argument("--mixed", type=int, default=1,
                     help="also time one 64^3 chain with eight 32^3 chains in one batch")
     ap.add_argument("--chain-sweep", action="store_true",
@@ -73,6 +76,12 @@ def parse():
                     help="also run 30 s of the small serving mix and report its sweep latencies")
     ap.add_argument("--serving-mix", type=str, default="small", choices=sorted(SERVING_MIXES),
                     help="lattice-size mix of the serving run")
+    ap.add_argument("--serving-load", type=float, default=1.0,
+                    help="offered load as a fraction of --serving-capacity (mixes without a rate)")
+    ap.add_argument("--serving-capacity", type=float, default=0.0,
+                    help="capacity in svu/s that sets the arrival rate (mixes without a rate)")
+    ap.add_argument("--serving-drain", type=float, default=1e9,
+                    help="seconds of drain after the arrivals before the rest is cancelled")
     ap.add_argument("--physics", action="store_true",
                     help="magnetization against temperature on 4^3, 6^3 and 8^3 (M = 256, mu = 0)")
     ap.add_argument("--fp32-accuracy", action="store_true",
@@ -87,9 +96,12 @@ def parse():
 def tune(batch, fixed: str):
     """Autotune the batch, or fix (pairs per thread, lanes) from "PPT,LANES"."""
     if fixed:
-        ppt, lanes = (int(v) for v in fixed.split(","))
+        vals = [int(v) for v in fixed.split(",")]
+        ppt, lanes = vals[0], vals[1]
         batch.set_lanes(lanes)
         batch.set_tuning(ppt)
+        if len(vals) > 2:
+            batch.set_nontemporal(bool(vals[2]))
     else:
         batch.autotune(64)
 
@@ -185,6 +197,59 @@ def cpu_baseline(max_threads: int = 16):
             "host": host_cpu()}
 
 
+def chain_state_bytes(ch):
+    """Bytes a step reads or writes of one chain: the vectors and the spinor
+    cache (the per-step working set; the moment partials are written once)."""
+    bps, _ = ch.step_bytes()
+    prec = 4 if ch.p.precision == 1 else 8
+    nvec = 2 if ch.p.vectors else 7
+    return ch.p.L ** 3 * (nvec * 2 * prec + 4 * prec)
+
+
+def hbm_regime(g, torch, dev, fixed: str, nprop: int = 2):
+    """The step kernel with working sets well above the 256 MB last-level
+    cache: 128 chains of 32^3 in FP32 (302 MB of vectors and spinors) and 64
+    chains of 32^3 in FP64 (302 MB), M = 2048, same temperatures and starts
+    as the headline; autotuned shape and lanes; the step rounds of `nprop`
+    proposals after one warm-up proposal."""
+    out = []
+    for nch, prec in ((128, g.FP32_ACC64), (64, g.FP64)):
+        temps = [T_LO + (T_HI - T_LO) * c / (nch - 1) for c in range(nch)]
+        chs = [g.Chain(g.Params(L=L, M=M, beta=1.0 / temps[c], precision=prec, seed=SEED,
+                                chain_id=c), device=dev) for c in range(nch)]
+        for ch in chs:
+            ch.init_spins(g.INIT_RANDOM)
+        b = g.Batch(chs)
+        tune(b, fixed)
+        ppt, lanes = b.tuning()
+        nt = b.form()["nontemporal"]
+        b.step(1)
+        torch.cuda.synchronize()
+        ms_tot, nl_tot = 0.0, 0
+        for _ in range(nprop):
+            b.step(1)
+            ms, nl = b.step_timing()
+            ms_tot += ms
+            nl_tot += nl
+        bps, _ = chs[0].step_bytes()
+        avg = ms_tot / 1e3 / max(nl_tot, 1)
+        ws = nch * chain_state_bytes(chs[0])
+        achieved = nch * bps / avg / 1e9
+        kern = "k_step<float>" if prec == g.FP32_ACC64 else "k_step<double>"
+        out.append({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "kernel": kern,
+                    "workload": f"{nch} chains of 32^3, M=2048, "
+                                f"{'FP32 recursion / FP64 sums' if prec else 'FP64'}",
+                    "working_set_bytes": ws, "pairs_per_thread": ppt, "lanes": lanes,
+                    "nontemporal": nt,
+                    "avg_round_us": avg * 1e6, "bytes_per_round": nch * bps,
+                    "rounds_timed": nl_tot})
+        b.close()
+        del chs
+        torch.cuda.empty_cache()
+    return out
+
+
 def small_configs(g, torch, dev):
     """The two small workloads, FP64 (the oracle's figures for them are in
     the cpu_baseline leg):
@@ -219,6 +284,7 @@ def small_configs(g, torch, dev):
     ch.init_spins(g.INIT_FM_PLUS_RANDOM, 0.1)
     b = g.Batch([ch])
     b.autotune(8)
+    form = b.form()
     b.step(2)
     torch.cuda.synchronize()
     n2 = 256
@@ -230,6 +296,9 @@ def small_configs(g, torch, dev):
     b.close()
     svu = 4096 * 7 * 512
     out["16cubed_M1024_fp64_cone"] = {
+        "step_launches": ("one persistent launch per proposal on one compute die "
+                          f"({form['persistent']} working blocks)" if form["persistent"]
+                          else "one launch per Chebyshev step"),
         "proposals_timed": n2, "proposals_per_s": n2 / dt, "svu_per_s": n2 * svu / dt,
         "ten_sweeps_s": 40960 * dt / n2, "ten_sweeps_note": "extrapolated from the timed proposals"}
     return out
@@ -291,31 +360,52 @@ def mixed_batch(g, torch, dev, n_prop: int = 2, step_granular: bool = True):
     return rec
 
 
-# serving mixes: lattice sizes, their probabilities, default arrival rate (1/s)
+# serving mixes: lattice sizes, their probabilities, default arrival rate (1/s;
+# None: set from the offered load, a fraction of a stated capacity in svu/s)
 SERVING_MIXES = {
     # small chains: L <= 8 on the LDS-resident kernel, 12 and 16 multi-block
     "small": ((4, 6, 8, 12, 16), (0.3, 0.25, 0.25, 0.15, 0.05), 6.0),
     # the serving workload's sizes whose sweeps finish within minutes on one GPU
     "large": ((8, 16, 24, 32), (0.4, 0.3, 0.2, 0.1), 0.3),
+    # the serving workload as specified: L uniform in {8, 16, 24, 32, 48}
+    "survey": ((8, 16, 24, 32, 48), (0.2, 0.2, 0.2, 0.2, 0.2), None),
 }
 
 
-def serving(g, seconds: float, mix: str = "small", seed: int = 2024, emit: bool = True):
+def serving_request_svu(L: int) -> float:
+    """Work of one request of lattice size L in site-vector updates: N
+    proposals per sweep, N * 7 * M/2 per proposal, M = min(2048, 64 L);
+    2 sweeps for L <= 24, 1 above."""
+    N, M = L ** 3, min(2048, 64 * L)
+    return (2 if L <= 24 else 1) * N * N * 7 * (M // 2)
+
+
+def serving(g, seconds: float, mix: str = "small", seed: int = 2024, emit: bool = True,
+            load: float = 1.0, capacity_svu: float = 0.0, drain_s: float = 1e9):
     """Continuous-batching serving run: Poisson arrivals (seeded) of chains
     from a mix of lattice sizes, M = min(2048, 64 L) (K the next power of
     two), T uniform in [0.02, 0.2], FP32 recursion, 2 sweeps per request for
     L <= 24 and 1 above; arrivals stop after `seconds`, then the engine
-    drains.  Prints a progress line every 30 s and one JSON line with the
-    per-sweep latency percentiles overall and per L, the queueing delay and
-    the throughput, and returns that record; with emit=False (a leg of the
-    default benchmark) the progress lines go to stderr and nothing else is
-    printed."""
+    drains for at most `drain_s` seconds and the requests still running are
+    cancelled and reported as unfinished (their sweep latency is at least
+    the time they ran).  A mix without a fixed rate arrives at `load` x
+    `capacity_svu` / (mean svu per request).  Prints a progress line every
+    30 s and one JSON line with the per-sweep latency percentiles overall and
+    per L, the queueing delay and the throughput, and returns that record;
+    with emit=False (a leg of the default benchmark) the progress lines go to
+    stderr and nothing else is printed."""
     import numpy as np
     sizes, probs, rate = SERVING_MIXES[mix]
+    mean_svu = sum(p * serving_request_svu(Lk) for Lk, p in zip(sizes, probs))
+    if rate is None:
+        if capacity_svu <= 0:
+            raise ValueError(f"mix {mix} needs a capacity (svu/s) to set its arrival rate")
+        rate = load * capacity_svu / mean_svu
     rng = np.random.default_rng(seed)
-    eng = g.Engine(0, hbm_budget_bytes=16 << 30, max_slots=64)
+    eng = g.Engine(0, hbm_budget_bytes=32 << 30, max_slots=64)
     t0 = time.perf_counter()
     t_next, k, meta, t_print = rng.exponential(1.0 / rate), 0, {}, 30.0
+    admitted_at = {}
 
     def progress(now):
         st = eng.status()
@@ -342,38 +432,68 @@ def serving(g, seconds: float, mix: str = "small", seed: int = 2024, emit: bool 
             t_next += rng.exponential(1.0 / rate)
         else:
             time.sleep(min(0.01, max(0.0, t_next - now)))
-    while True:   # drain, reporting progress
+    t_drain = time.perf_counter()
+    unfinished = []
+    while True:   # drain, reporting progress, for at most drain_s
         try:
-            eng.drain(30.0)
+            eng.drain(min(30.0, max(1.0, drain_s - (time.perf_counter() - t_drain))))
             break
         except g.GfmcError as e:
             if e.status != g.GFMC_EBUSY:
                 raise
             progress(time.perf_counter() - t0)
+            if time.perf_counter() - t_drain >= drain_s:
+                done_ids = set()
+                for rid in meta:
+                    try:
+                        eng.cancel(rid)
+                        unfinished.append(rid)
+                    except g.GfmcError:
+                        done_ids.add(rid)
+                eng.drain(120.0)
+                break
     wall = time.perf_counter() - t0
     res = eng.poll(1 << 16)
     lat, ids = eng.sweep_latencies()
     eng.close()
+    ok = [r for r in res if r.status == 0]
     props = sum(r.proposals for r in res)
     svu = sum(r.proposals * (r.L ** 3) * 7 * (r.M // 2) for r in res)
     per_L = {}
     for Lk in sizes:
         sel = np.array([meta.get(int(i)) == Lk for i in ids], dtype=bool)
+        rec_L = {"requests": sum(1 for v in meta.values() if v == Lk)}
         if sel.any():
-            per_L[str(Lk)] = {"p50_s": float(np.percentile(lat[sel], 50)),
-                              "p99_s": float(np.percentile(lat[sel], 99)), "sweeps": int(sel.sum())}
-    wait = np.array([r.t_admit - r.t_submit for r in res])
+            rec_L.update({"p50_s": float(np.percentile(lat[sel], 50)),
+                          "p99_s": float(np.percentile(lat[sel], 99)), "sweeps": int(sel.sum())})
+        cut = [r for r in res if r.status == g.GFMC_ECANCELED and meta.get(r.request_id) == Lk]
+        if cut:
+            # a request cancelled at the drain limit: its open sweep had run at least this long
+            rec_L["unfinished"] = len(cut)
+            rec_L["unfinished_sweep_lower_bound_s"] = [
+                round(r.t_done - (r.t_first_sweep if r.t_first_sweep >= 0 else r.t_admit), 1)
+                for r in cut if r.t_admit >= 0]
+            rec_L["unfinished_queued"] = sum(1 for r in cut if r.t_admit < 0)
+        per_L[str(Lk)] = rec_L
+    wait = np.array([r.t_admit - r.t_submit for r in res if r.t_admit >= 0])
     rec = {
-        "mode": "serving", "mix": mix, "requests": k,
-        "completed": sum(r.status == 0 for r in res),
-        "arrival_rate_per_s": rate, "arrival_window_s": seconds, "wall_s": wall,
-        "sweep_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                            "per_L": per_L, "sweeps": int(len(lat))},
-        "queue_wait_s": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+        "mode": "serving", "mix": mix, "requests": k, "completed": len(ok),
+        "unfinished_at_drain_limit": len(unfinished),
+        "arrival_rate_per_s": rate, "arrival_window_s": seconds,
+        "drain_limit_s": drain_s if drain_s < 1e8 else None, "wall_s": wall,
+        "offered_load": ({"fraction_of_capacity": load, "capacity_svu_per_s": capacity_svu,
+                          "mean_request_svu": mean_svu}
+                         if SERVING_MIXES[mix][2] is None else None),
+        "sweep_latency_s": ({"p50": float(np.percentile(lat, 50)),
+                             "p99": float(np.percentile(lat, 99))} if len(lat) else {}) |
+                           {"per_L": per_L, "sweeps": int(len(lat))},
+        "queue_wait_s": ({"p50": float(np.percentile(wait, 50)),
+                          "p99": float(np.percentile(wait, 99))} if len(wait) else {}),
         "mc_spin_updates_per_s": props / wall, "svu_per_s": svu / wall,
-        "config": {"workload": f"Poisson arrivals ({rate}/s), L in {set(sizes)} w.p. {probs}, "
-                               "M = min(2048, 64 L), T ~ U[0.02, 0.2], FP32 recursion, 2 sweeps "
-                               "per request for L <= 24 and 1 above, 16 GiB budget, 64 slots"}}
+        "config": {"workload": f"Poisson arrivals ({rate:.4g}/s), L in {sorted(set(sizes))} w.p. "
+                               f"{probs}, M = min(2048, 64 L), T ~ U[0.02, 0.2], FP32 recursion, "
+                               "2 sweeps per request for L <= 24 and 1 above, 32 GiB budget, "
+                               "64 slots"}}
     if emit:
         print(json.dumps(rec), flush=True)
     return rec
@@ -538,7 +658,8 @@ def main():
     import paper_1303_6016_amd as g
     import synth
     if args.serving > 0:
-        serving(g, args.serving, args.serving_mix)
+        serving(g, args.serving, args.serving_mix, load=args.serving_load,
+                capacity_svu=args.serving_capacity, drain_s=args.serving_drain)
         return
     if args.chain_sweep:
         chain_sweep(g, torch)
@@ -574,6 +695,7 @@ def main():
     batch = g.Batch(chains)
     tune(batch, args.tuning)
     ppt, lanes = batch.tuning()
+    nt = batch.form()["nontemporal"]
     if args.graph:
         batch.use_graph(True)
     stream = batch.stream
@@ -618,20 +740,21 @@ def main():
                       ": one k_step launch"),
             "avg_round_us": avg_round_s * 1e6, "bytes_per_round": bytes_per_round}
 
-    # measured copy bandwidth on this machine (1 GiB device copy, read + write)
-    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    c1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 4 / (c0.elapsed_time(c1) / 1e3) / 1e9
-    del src, dst
-    roof["measured_copy_GBs"] = copy_gbs
-    roof["frac_of_measured_copy"] = achieved / copy_gbs
+    # the device's streaming ceilings, measured live with the library's own
+    # streaming kernel: two reads + one write per item (the step kernel's mix)
+    # over buffers well above the 256 MB last-level cache (HBM), and over
+    # 64 MiB buffers (cache-resident, the regime of this batch)
+    ceil_hbm = g.stream_bandwidth(3, 1 << 30, 10)
+    ceil_llc = g.stream_bandwidth(3, 64 << 20, 20)
+    ws = NCHAIN * chain_state_bytes(chains[0])
+    roof["working_set_bytes"] = ws
+    roof["regime"] = ("last-level-cache resident: the chains' vectors and spinors "
+                      f"({ws / 1e6:.0f} MB) fit the 256 MB Infinity Cache, so this fraction is "
+                      "read against the HBM peak but served partly from the cache; the HBM "
+                      "figures are the roofline_hbm_regime records")
+    roof["ceiling_2r1w_hbm_GBs"] = ceil_hbm
+    roof["ceiling_2r1w_llc_GBs"] = ceil_llc
+    roof["frac_of_llc_ceiling"] = achieved / ceil_llc
 
     out = {
         "metric": "Chebyshev site-vector updates/s + MC spin updates/s at 32^3; p50/p99 sweep latency",
@@ -641,7 +764,7 @@ def main():
         "config": {"workload": "32^3 lattice x 64 chains, M=2048, FP32 recursion / FP64 moment "
                                "sums, T=0.02..0.2 t, uniform-sphere starts (seed 7)",
                    "L": L, "M": M, "chains": NCHAIN, "graph": bool(args.graph),
-                   "pairs_per_thread": ppt, "lanes": lanes},
+                   "pairs_per_thread": ppt, "lanes": lanes, "nontemporal": nt},
         "mc_spin_updates_per_s": args.steps * NCHAIN / total_s,
         "step_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "sweep_latency_s": {"p50": float(np.percentile(lat, 50)) * N,
@@ -752,6 +875,14 @@ def main():
             note(f"{name} failed: {e}")
             return {"error": str(e)}
 
+    if args.hbm:
+        note("HBM-regime step kernel (128 x 32^3 FP32, 64 x 32^3 FP64)")
+        hr = leg("HBM regime", lambda: hbm_regime(g, torch, dev, args.tuning))
+        out["roofline_hbm_regime"] = hr
+        if isinstance(hr, list):
+            for r in hr:
+                r["ceiling_2r1w_hbm_GBs"] = roof["ceiling_2r1w_hbm_GBs"]
+                r["frac_of_hbm_ceiling"] = r["achieved"] / roof["ceiling_2r1w_hbm_GBs"]
     if args.mixed:
         note("64^3 + 8 x 32^3 batch")
         out["mixed_64cubed_plus_8x32cubed"] = leg("mixed batch", lambda: mixed_batch(g, torch, dev))

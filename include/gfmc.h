@@ -82,8 +82,8 @@ typedef enum {
  * the acceptance in FP64.  Its rounding error grows with M and falls with L,
  * and the error of Delta S_eff grows with beta, so it is accepted only where
  * its measured error stays within 1e-5 on the moments and 2e-5 on Delta
- * S_eff: beta t <= 50 and M <= 512 (L = 2), 1024 (L = 4, 6), 2048
- * (8 <= L < 32) or 8192 (L >= 32).  Elsewhere gfmc_workspace_bytes,
+ * S_eff: beta t <= 50 and M <= 1024 (L = 4, 6), 4096 (8 <= L < 16) or
+ * 8192 (L >= 16); never on 2^3.  Elsewhere gfmc_workspace_bytes,
  * gfmc_chain_create, gfmc_set_params and gfmc_engine_submit return EINVAL,
  * unless params.fp32_unvalidated = 1 (for measuring that error). */
 typedef enum { GFMC_FP64 = 0, GFMC_FP32_ACC64 = 1 } gfmc_precision;
@@ -321,10 +321,29 @@ gfmc_status gfmc_batch_set_lanes(gfmc_batch* batch, int32_t lanes);
  * shape (one launch per proposal) is unaffected.  EINVAL outside {0, 1}. */
 gfmc_status gfmc_batch_set_schedule(gfmc_batch* batch, int32_t step_granular);
 
+/* Non-temporal memory access in the Chebyshev steps of the 7-vector
+ * multi-block kernel (on != 0): each site's own a_{s-2} is loaded and a_s
+ * stored without retaining the lines in the caches.  Pays where a batch's
+ * vectors stream from HBM (working sets well above the 256 MB last-level
+ * cache); slower where they fit it.  Results do not depend on it.
+ * gfmc_batch_autotune chooses it with the launch shape.  EINVAL outside
+ * {0, 1}. */
+gfmc_status gfmc_batch_set_nontemporal(gfmc_batch* batch, int32_t on);
+
+/* Execution form in effect: *resident = 1 when every chain runs all its
+ * steps in one LDS-resident workgroup; *persistent = the number of working
+ * blocks when a lone chain runs all its steps in one persistent launch on
+ * one compute die (0 otherwise); *step_granular = the schedule set by
+ * gfmc_batch_set_schedule; *nontemporal = gfmc_batch_set_nontemporal's
+ * setting.  Pointers may be NULL. */
+gfmc_status gfmc_batch_get_form(gfmc_batch* batch, int32_t* resident, int32_t* persistent,
+                                int32_t* step_granular, int32_t* nontemporal);
+
 /* Launch shape (0, 1, 2) and number of step lanes in effect. */
 gfmc_status gfmc_batch_get_tuning(gfmc_batch* batch, int32_t* pairs_per_thread, int32_t* lanes);
 
-/* Time each step-kernel launch shape with one to four lanes over
+/* Time each step-kernel launch shape (with and without non-temporal access)
+ * with one to four lanes over
  * `trial_steps` Chebyshev steps on the batch's current spins (no change of
  * chain state), keep the fastest, and remember it for later batches of the
  * same shape (precision, number of chains, L and M of each chain).  chosen
@@ -416,10 +435,11 @@ gfmc_status gfmc_delta_seff_static(const gfmc_chain_params* params, const double
  * infrastructure).  mode 0 reads `a`, 1 writes `c`, 2 copies `a` to `c`,
  * 3 writes a + b to `c` (two reads per write, the step kernel's mix); each
  * buffer is a caller-owned device allocation of `bytes` (a multiple of 16;
- * `c` is always required, 16 bytes suffice in mode 0), `reps` timed passes
- * after one warm-up pass on `stream`.  *gbs = bytes moved once per pass
- * (1, 1, 2 or 3 buffers) x reps / elapsed time, in GB/s.  Buffers well above
- * the 256 MB last-level cache measure HBM; smaller ones the cache. */
+ * `c` is always required, 16 bytes suffice in mode 0).  For grids of 2, 4, 8
+ * and 16 blocks per compute unit: one warm-up pass, then `reps` timed passes
+ * on `stream`; *gbs = the best of bytes moved once per pass (1, 1, 2 or 3
+ * buffers) x reps / elapsed time, in GB/s.  Buffers well above the 256 MB
+ * last-level cache measure HBM; smaller ones the cache. */
 gfmc_status gfmc_stream_bandwidth(int32_t mode, const void* a, const void* b, void* c,
                                   size_t bytes, int32_t reps, void* stream, double* gbs);
 

@@ -98,6 +98,8 @@ _SIGS = {
     "gfmc_batch_set_tuning": [_vp, _i32],
     "gfmc_batch_set_lanes": [_vp, _i32],
     "gfmc_batch_set_schedule": [_vp, _i32],
+    "gfmc_batch_get_form": [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32)],
+    "gfmc_batch_set_nontemporal": [_vp, _i32],
     "gfmc_batch_get_tuning": [_vp, _P(_i32), _P(_i32)],
     "gfmc_batch_autotune": [_vp, _i32, _P(_i32)],
     "gfmc_engine_create": [ctypes.c_int, _sz, _i32, _P(_vp)],
@@ -368,6 +370,18 @@ class Batch:
         """False: lock-step proposals; True: each chain restarts as soon as its
         proposal ends (chains with fewer steps make more proposals)."""
         _check(lib().gfmc_batch_set_schedule(self.h, 1 if step_granular else 0))
+
+    def form(self):
+        """{"resident", "persistent" (working blocks, 0 if off), "step_granular",
+        "nontemporal"}."""
+        r, p, c, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().gfmc_batch_get_form(self.h, ctypes.byref(r), ctypes.byref(p), ctypes.byref(c),
+                                         ctypes.byref(n)))
+        return {"resident": r.value, "persistent": p.value, "step_granular": c.value,
+                "nontemporal": n.value}
+
+    def set_nontemporal(self, on: bool):
+        _check(lib().gfmc_batch_set_nontemporal(self.h, 1 if on else 0))
 
     def tuning(self):
         """(launch shape, lanes) in effect."""

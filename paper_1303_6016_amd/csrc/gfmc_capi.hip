@@ -28,15 +28,17 @@ static gfmc_status fail(gfmc_status s, const std::string& msg) { return gfmc_fai
 // Validated range of the FP32 recursion with FP64 sums: the (L, M, beta t)
 // cells where its measured error against the FP64 path (itself within
 // 1e-12 of the oracle) stays within the stated bounds, 1e-5 on the moments
-// and 2e-5 on Delta S_eff, with a margin.  The error grows with M (rounding
-// errors of the recursion accumulate over its M/2 steps), shrinks with L (a
-// vector spread over many sites averages them in the Gram sums), and the
-// error of Delta S_eff grows linearly with beta (the energy integral is
-// weighted by beta).  Largest M accepted per lattice size at beta t <= 50.
+// and 2e-5 on Delta S_eff, over 16 seeded moves per cell at beta t = 20 and
+// 50.  The error grows with M (rounding errors of the recursion accumulate
+// over its M/2 steps), shrinks with L (a vector spread over many sites
+// averages them in the Gram sums), and the error of Delta S_eff grows
+// linearly with beta (the energy integral is weighted by beta).  Largest M
+// accepted per lattice size at beta t <= 50; none on 2^3, whose 8 levels
+// leave the phase of d(z) ill-conditioned.
 int fp32_max_moments(int L) {
-  if (L < 4) return 512;
+  if (L < 4) return 0;
   if (L < 8) return 1024;
-  if (L < 32) return 2048;
+  if (L < 16) return 4096;
   return 8192;
 }
 constexpr double kFp32MaxBetaT = 50.0;
@@ -76,7 +78,8 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
       (p->M > fp32_max_moments(p->L) || p->beta * p->t > kFp32MaxBetaT))
     return fail(GFMC_EINVAL, "FP32 recursion outside its validated range (M <= " +
                                  std::to_string(fp32_max_moments(p->L)) + " at L = " +
-                                 std::to_string(p->L) + ", beta t <= 50): use GFMC_FP64");
+                                 std::to_string(p->L) + ", beta t <= 50): use GFMC_FP64, "
+                                 "or set fp32_unvalidated to measure its error");
   d.L = p->L;
   d.N = p->L * p->L * p->L;
   d.half = d.N / 2;
@@ -157,11 +160,59 @@ bool resident_fits(const Derived& d) {
 // launch of the multi-block kernel (about 6 us for a lone small chain).
 bool resident_ok(const Derived& d) { return resident_fits(d); }
 
+// The persistent single-chain kernel keeps a chain's steps on one die: the
+// chain's vectors and spinors must fit well inside that die's 4 MB L2, and
+// its blocks (one site pair per thread) within the die's 32 compute units.
+static bool persist_fits(const Derived& d) {
+  const size_t bytes = (size_t)d.N * (d.fp32 ? 72 : 144);
+  return !d.ov && !d.hops && !resident_fits(d) && bytes <= ((size_t)3 << 20) &&
+         blocks_of(d, 1) <= 32;
+}
+
+// Blocks are dealt to the dies in turn; the persistent kernel relies on a
+// grid of 8 nb blocks putting at least nb blocks on every die it reaches.
+// Checked once per device and block count by a census kernel.
+static std::mutex g_census_mu;
+static std::vector<std::pair<std::pair<int, int>, bool>> g_census;
+
+static gfmc_status die_census(Plan& P, int nb, bool* ok) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_census_mu);
+    for (auto& e : g_census)
+      if (e.first == std::make_pair(dev, nb)) {
+        *ok = e.second;
+        return GFMC_OK;
+      }
+  }
+  unsigned* cnt = (unsigned*)P.d_mag;   // 16 counters in the plan's scratch (512 B)
+  unsigned h[16];
+  memset(h, 0, sizeof(h));
+  HIPCHK(hipMemcpyAsync(cnt, h, sizeof(h), hipMemcpyHostToDevice, P.stream));
+  HIPCHK(launch_die_census(cnt, 8 * nb, P.stream));
+  HIPCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, P.stream));
+  HIPCHK(hipStreamSynchronize(P.stream));
+  bool good = true;
+  for (int x = 0; x < 16; ++x) good = good && (h[x] == 0 || h[x] >= (unsigned)nb);
+  {
+    std::lock_guard<std::mutex> lk(g_census_mu);
+    g_census.push_back({{dev, nb}, good});
+  }
+  *ok = good;
+  return GFMC_OK;
+}
+
 gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
+  if (P.persist < 0) {
+    bool ok = false;
+    CHK(die_census(P, -P.persist, &ok));
+    P.persist = ok ? -P.persist : 0;
+  }
   std::vector<Desc> ds(sorted.size());
   for (size_t i = 0; i < sorted.size(); ++i) {
     ds[i] = sorted[i]->desc;
-    ds[i].nblk = P.resident ? 1 : blocks_of(sorted[i]->d, P.ppt);
+    ds[i].nblk = P.persist > 0 ? P.persist : P.resident ? 1 : blocks_of(sorted[i]->d, P.ppt);
   }
   HIPCHK(hipMemcpyAsync(P.d_desc, ds.data(), ds.size() * sizeof(Desc), hipMemcpyHostToDevice,
                         P.stream));
@@ -192,6 +243,14 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
     P.res_lds = std::max(P.res_lds, resident_lds(c->d));
   }
   P.resident = ok ? 1 : 0;
+  // a lone multi-block chain small enough for one die: persistent step kernel
+  P.persist = 0;
+  P.persist_ctl = nullptr;
+  if (P.allow_persist && P.n == 1 && !P.resident && P.ppt == 1 && P.lanes <= 1 && P.d_mag &&
+      !P.gexec && persist_fits(sorted[0]->d)) {
+    P.persist = -blocks_of(sorted[0]->d, 1);
+    P.persist_ctl = sorted[0]->desc.ctl;
+  }
   for (int i = 0; i < P.n; ++i) {
     P.S[i] = sorted[i]->d.S;
     P.blkoff[i + 1] = P.blkoff[i] + blocks_of(sorted[i]->d, P.ppt);
@@ -261,7 +320,7 @@ gfmc_status enqueue_steps(Plan& P, int s_first, int s_last) {
       while (nact > 0 && P.S[nact - 1] < s) --nact;
       if (nact == 0) break;
       HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact],
-                         s, P.stream));
+                         s, P.stream, nullptr, P.nt));
     }
     return GFMC_OK;
   }
@@ -276,7 +335,7 @@ gfmc_status enqueue_steps(Plan& P, int s_first, int s_last) {
       while (nact[l] > 0 && P.S[f + nact[l] - 1] < s) --nact[l];
       if (nact[l] == 0) continue;
       HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc + f, P.d_lane_blkoff[l], nact[l],
-                         P.lane_blkoff[l][nact[l]], s, P.lane_stream[l]));
+                         P.lane_blkoff[l][nact[l]], s, P.lane_stream[l], nullptr, P.nt));
     }
   for (int l = 0; l < k; ++l) {
     HIPCHK(hipEventRecord(P.join[l], P.lane_stream[l]));
@@ -320,6 +379,8 @@ gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* 
   if (tm) HIPCHK(hipEventRecord(P.ev[P.ev_used], P.stream));
   if (P.resident) {
     HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
+  } else if (P.persist > 0) {
+    HIPCHK(launch_persist(P.fp32, P.d_desc, P.persist, P.stream));
   } else {
     CHK(enqueue_steps(P, 1, P.smax));
   }
@@ -399,7 +460,7 @@ gfmc_status enqueue_window(Plan& P, int rounds, const int* cap, int* props, bool
       for (int i = f; i < f + nl && !any; ++i) any = r <= act[i] && (r - 1) % P.S[i] != 0;
       if (any)
         HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc + f, bo, nl, blocks, r,
-                           lane_st(l), P.d_act_end + f));
+                           lane_st(l), P.d_act_end + f, P.nt));
     }
     for (size_t q = 0; q < P.coh.size(); ++q) {
       const int S = P.coh[q].S;
@@ -412,6 +473,19 @@ gfmc_status enqueue_window(Plan& P, int rounds, const int* cap, int* props, bool
       HIPCHK(hipStreamWaitEvent(P.stream, P.join[l], 0));
     }
   return GFMC_OK;
+}
+
+gfmc_status persist_check(Plan& P) {
+  if (P.persist <= 0 || !P.persist_ctl) return GFMC_OK;
+  unsigned err = 0;
+  HIPCHK(hipMemcpyAsync(&err, &P.persist_ctl->bar[3], sizeof(err), hipMemcpyDeviceToHost,
+                        P.stream));
+  HIPCHK(hipStreamSynchronize(P.stream));
+  if (!err) return GFMC_OK;
+  P.persist = 0;
+  P.allow_persist = false;
+  return fail(GFMC_EDEVICE, "a barrier of the persistent step kernel timed out: that proposal "
+                            "left the chain unchanged; later proposals use one launch per step");
 }
 
 static gfmc_status timing_begin(Plan& P, int nprop) {
@@ -484,6 +558,7 @@ gfmc_status chain_setup(gfmc_chain* c, const gfmc_chain_params* p, const Derived
   P.ov = d.ov;
   P.hops = d.hops;
   P.ppt = resident_ok(d) ? 0 : 1;
+  P.allow_persist = true;
   P.d_desc = (Desc*)(c->ws + l.desc);
   P.d_blkoff = (int*)(c->ws + l.blkoff);
   P.d_force = (int32_t*)(c->ws + l.force);
@@ -583,6 +658,8 @@ gfmc_status gfmc_set_params(gfmc_chain* c, double t, double beta, double mu) {
   fill_desc(c);
   CHK(upload_plan(c->plan, {c}));
   HIPCHK(launch_tables(c->plan.d_desc, d.K, c->stream));
+  // stored hopping rows hold -(t/a) t_ij: rebuild them for the new t
+  if (d.hops) HIPCHK(launch_hops(d.fp32, c->plan.d_desc, d.N, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return GFMC_OK;
 }
@@ -652,6 +729,7 @@ gfmc_status gfmc_moments(gfmc_chain* c, int32_t site, double* mu) {
   HIPCHK(hipMemcpyAsync(mu, c->desc.mom, (size_t)c->d.M * 49 * 16, hipMemcpyDeviceToHost,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  CHK(persist_check(c->plan));
   return set_mode(c, 0, 0, 0.0, 0.0);
 }
 
@@ -696,6 +774,7 @@ gfmc_status gfmc_delta_seff(gfmc_chain* c, int32_t site, double tn, double pn, d
   Ctl h;
   HIPCHK(hipMemcpyAsync(&h, c->desc.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  CHK(persist_check(c->plan));
   *dseff = h.dseff;
   if (phase_top) *phase_top = h.phase_top;
   return set_mode(c, 0, 0, 0.0, 0.0);
@@ -847,6 +926,7 @@ gfmc_status gfmc_step(gfmc_chain* c, int32_t force, gfmc_step_record* rec) {
   if (force < -1 || force > 1) return fail(GFMC_EINVAL, "force must be -1, 0 or 1");
   gfmc_step_record r;
   CHK(run_proposals(c->plan, 1, &force, &r));
+  CHK(persist_check(c->plan));
   if (rec) *rec = r;
   return GFMC_OK;
 }
@@ -862,6 +942,7 @@ gfmc_status gfmc_sweep(gfmc_chain* c, int32_t nsweeps, double* mag, int64_t* acc
     HIPCHK(launch_magnetization(c->plan.d_desc, 1, c->plan.d_mag, c->stream));
     if (mag) HIPCHK(hipMemcpyAsync(mag + s, c->plan.d_mag, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(persist_check(c->plan));
   }
   HIPCHK(hipMemcpyAsync(&a1, &c->desc.ctl->accepted_total, 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -962,6 +1043,7 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
   bool all_res = true;
   for (auto* c : sorted) all_res = all_res && resident_ok(c->d);
   P.ppt = all_res ? 0 : 1;
+  P.allow_persist = true;
   plan_shape(P, sorted);
   b->sorted = sorted;
   // chains' own streams may hold pending work
@@ -998,6 +1080,7 @@ gfmc_status gfmc_batch_use_graph(gfmc_batch* b, int32_t enable) {
   if (P.stream == nullptr) return fail(GFMC_EINVAL, "graph capture needs a non-default stream");
   if (!P.gexec) {
     HIPCHK(hipStreamSynchronize(P.stream));
+    P.persist = 0;   // the graph replays one launch per step (same block table)
     if (!(P.cont && !P.resident))
       HIPCHK(hipStreamBeginCapture(P.stream, hipStreamCaptureModeThreadLocal));
     const bool tm = P.timing;
@@ -1070,6 +1153,7 @@ gfmc_status gfmc_batch_step(gfmc_batch* b, int32_t nprop, const int32_t* force,
   CHK(timing_begin(P, nprop));
   CHK(run_proposals(P, nprop, force ? f.data() : nullptr, recs ? r.data() : nullptr));
   CHK(timing_end(P));
+  CHK(persist_check(P));
   if (recs)
     for (int q = 0; q < nprop; ++q)
       for (int i = 0; i < n; ++i) recs[(size_t)q * n + b->order[i]] = r[(size_t)q * n + i];
@@ -1169,6 +1253,29 @@ gfmc_status gfmc_batch_set_schedule(gfmc_batch* b, int32_t step_granular) {
   return GFMC_OK;
 }
 
+gfmc_status gfmc_batch_get_form(gfmc_batch* b, int32_t* resident, int32_t* persistent,
+                                int32_t* step_granular, int32_t* nontemporal) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  if (resident) *resident = b->plan.resident;
+  if (persistent) *persistent = b->plan.persist > 0 ? b->plan.persist : 0;
+  if (step_granular) *step_granular = b->plan.cont;
+  if (nontemporal) *nontemporal = b->plan.nt;
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_set_nontemporal(gfmc_batch* b, int32_t on) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  if (on != 0 && on != 1) return fail(GFMC_EINVAL, "on must be 0 or 1");
+  Plan& P = b->plan;
+  HIPCHK(hipStreamSynchronize(P.stream));
+  P.nt = on;
+  const bool g = b->use_graph;
+  drop_graph(P);
+  b->use_graph = false;
+  if (g) return gfmc_batch_use_graph(b, 1);
+  return GFMC_OK;
+}
+
 gfmc_status gfmc_batch_get_tuning(gfmc_batch* b, int32_t* pairs_per_thread, int32_t* lanes) {
   if (!b || !pairs_per_thread || !lanes) return fail(GFMC_EINVAL, "NULL argument");
   *pairs_per_thread = b->plan.resident ? 0 : b->plan.ppt;
@@ -1194,14 +1301,15 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
     for (auto& kv : g_tune_cache)
       if (kv.first == key) hit = kv.second;
   }
-  if (hit.first >= 0) {
+  if (hit.first >= 0) {   // second = lanes + 16 x non-temporal
     if (chosen) *chosen = hit.first;
-    CHK(gfmc_batch_set_lanes(b, hit.second));
+    CHK(gfmc_batch_set_lanes(b, hit.second & 15));
+    CHK(gfmc_batch_set_nontemporal(b, hit.second >> 4));
     return gfmc_batch_set_tuning(b, hit.first);
   }
   // The step kernel only touches per-proposal scratch (vectors, partials), so
   // trial launches between proposals leave the chains' state unchanged.
-  int best = 1, best_lanes = 1;
+  int best = 1, best_lanes = 1, best_nt = 0;
   float best_ms = 1e30f;
   struct Events {   // destroyed on every return path
     hipEvent_t a = nullptr, b = nullptr;
@@ -1215,12 +1323,15 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   hipEvent_t e0 = ev.a, e1 = ev.b;
   bool all_res = true;
   for (auto* c : b->sorted) all_res = all_res && resident_fits(c->d);
-  for (int ppt : {0, 1, 2}) {
+  for (int ppt : {0, 1, 2})
+   for (int nt = 0; nt <= 1; ++nt) {
     if (ppt == 0 && !all_res) continue;
+    if (nt && (ppt == 0 || P.ov)) continue;   // the 7-vector multi-block kernel only
     for (int lanes = 1; lanes <= kMaxLanes; ++lanes) {
       if (lanes >= 2 && (ppt == 0 || P.n < lanes)) continue;
       CHK(gfmc_batch_set_lanes(b, lanes));
       CHK(gfmc_batch_set_tuning(b, ppt));
+      CHK(gfmc_batch_set_nontemporal(b, nt));
       float ms = 0;
       if (ppt == 0) {   // the resident kernel runs every step of a proposal in one launch
         HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
@@ -1247,15 +1358,16 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
           ms = std::min(ms, t);
         }
       }
-      if (ms < best_ms) { best_ms = ms; best = ppt; best_lanes = lanes; }
+      if (ms < best_ms) { best_ms = ms; best = ppt; best_lanes = lanes; best_nt = nt; }
     }
-  }
+   }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache.push_back({key, {best, best_lanes}});
+    g_tune_cache.push_back({key, {best, best_lanes + 16 * best_nt}});
   }
   if (chosen) *chosen = best;
   CHK(gfmc_batch_set_lanes(b, best_lanes));
+  CHK(gfmc_batch_set_nontemporal(b, best_nt));
   return gfmc_batch_set_tuning(b, best);
 }
 

@@ -44,6 +44,10 @@ struct Ctl {
   int32_t own, accepted;
   double th_old, ph_old, th_new, ph_new, u, dseff, phase_top;
   double delta[12];         // Delta_{n_d,o}, d = 0..5 (re, im)
+  // persistent single-chain step kernel, cleared by the proposal kernel:
+  // [0] tickets handed out, [1] 1 + the compute die (XCD) that claimed the
+  // run, [2] barrier arrivals, [3] nonzero when a barrier wait timed out
+  unsigned bar[4];
 };
 
 // Per-chain descriptor (device table read by the batched kernels).

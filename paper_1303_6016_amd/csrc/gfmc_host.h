@@ -13,14 +13,21 @@ hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
 // One Chebyshev step launch over chains [0, nact) of table d.  act_end NULL:
 // every chain takes step s.  act_end non-NULL: s is the round of a window and
 // chain c takes step (s - 1) mod S_c + 1 while s <= act_end[c] (never step 1).
+// nt: non-temporal loads of each site's own a_{s-2} and stores of a_s (steps >= 2
+// of the 7-vector kernel; pays where the batch streams from HBM).
 hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const int* blkoff,
-                       int nact, int blocks, int s, hipStream_t st, const int* act_end = nullptr);
+                       int nact, int blocks, int s, hipStream_t st, const int* act_end = nullptr,
+                       int nt = 0);
 hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st);
 hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
                         gfmc_step_record* recs, hipStream_t st);
 hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t st);
 hipError_t launch_hops(int fp32, const Desc* d, int nmax, hipStream_t st);
 hipError_t launch_resident(int fp32, const Desc* d, int n, size_t lds, hipStream_t st);
+// Persistent single-chain step run (cooperative launch of 8 nb blocks, nb work).
+hipError_t launch_persist(int fp32, const Desc* d, int nb, hipStream_t st);
+// counts[die] (16 unsigned, zeroed by the caller) += blocks landing on each die.
+hipError_t launch_die_census(unsigned* counts, int blocks, hipStream_t st);
 hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st);
 hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st);
 hipError_t launch_magnetization(const Desc* d, int n, double* out, hipStream_t st);
@@ -64,9 +71,15 @@ struct Layout {
 // Chebyshev steps, largest first) and the block offsets of the step kernel.
 struct Plan {
   int n = 0, fp32 = 0, smax = 0, kmax = 0, nmax = 0;
+  int nt = 0;                          // non-temporal own loads and stores in the steps
   int ppt = 1;                         // site pairs per thread of the step kernel;
                                        // 0: one LDS-resident workgroup per chain
   int resident = 0;                    // shape 0 in effect (every chain fits in LDS)
+  int persist = 0;                     // > 0: a lone chain's steps in one launch of this
+                                       // many working blocks on one die (persistent kernel);
+                                       // < 0: candidate, pending the die census
+  bool allow_persist = false;          // chain and batch plans (not the engine's groups)
+  Ctl* persist_ctl = nullptr;          // the lone chain's control block (timeout flag)
   size_t res_lds = 0;                  // dynamic LDS of the resident kernel
   int ov = 0;                          // start vectors {o, v} instead of the 7 sites
   int hops = 0;                        // stored hopping table instead of recompute
@@ -149,6 +162,10 @@ gfmc_status enqueue_steps(Plan& P, int s_first, int s_last);
 void release_lanes(Plan& P);
 gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* d_rec,
                              bool with_recon);
+// After proposals that used the persistent kernel: EDEVICE if one of its
+// barrier waits timed out (that proposal left the chain unchanged; the plan
+// falls back to one launch per step).
+gfmc_status persist_check(Plan& P);
 // Step-granular window of `rounds` step rounds (cont = 1): chain c runs
 // min(rounds / S_c, cap[c]) whole proposals (cap NULL: no cap) and
 // props[c] (plan order, may be NULL) receives that count.

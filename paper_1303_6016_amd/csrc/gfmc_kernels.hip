@@ -103,20 +103,23 @@ __device__ inline spn<T> make_spinor(double th, double ph) {
   return s;
 }
 
-// <chi_i|chi_j> = t_ij (the same amplitude as equation "ht", from cached
-// half-angle factors), formed in FP64 and rounded once to the recursion
-// precision T.  With FP32 spinors, forming the four products and their sum
-// in FP32 leaves an absolute error of a few 1e-8 on every amplitude, also on
-// small ones (nearly opposite spins), and that perturbation of the
-// Hamiltonian, not the rounding of the recursion, dominates the error of the
-// FP32 moments: forming it in FP64 from the same FP32 spinors cuts the
-// moment error about tenfold for the same bytes.
+// sc <chi_i|chi_j> = sc t_ij with sc = -t/a: the element of the rescaled
+// Hamiltonian Ht (t_ij as in equation "ht", from the cached half-angle
+// factors), formed in FP64 and rounded once to the recursion precision T.
+// In the FP32 recursion two roundings of the Hamiltonian dominate the error
+// of the moments, not the rounding of the vectors: a scale -2t/a rounded to
+// FP32 once multiplies every step's Ht by the same (1 + 4e-8), an error that
+// grows coherently with the moment order, and amplitudes summed in FP32
+// carry a few 1e-8 absolute error each.  Forming sc t_ij in FP64 and
+// rounding each element once (the steps then double it exactly) cuts the
+// FP32 moment error several-fold for the same bytes and instructions.
 template <typename T>
-__device__ inline void hop_spinor(const spn<T>& a, const spn<T>& b, T& re, T& im) {
+__device__ inline void hop_spinor(const spn<T>& a, const spn<T>& b, const double sc, T& re,
+                                  T& im) {
   const double ar = a.ar, ai = a.ai, br = a.br, bi = a.bi;
   const double cr = b.ar, ci = b.ai, dr = b.br, di = b.bi;
-  re = (T)(ar * cr + ai * ci + br * dr + bi * di);
-  im = (T)(ar * ci - ai * cr + br * di - bi * dr);
+  re = (T)(sc * (ar * cr + ai * ci + br * dr + bi * di));
+  im = (T)(sc * (ar * ci - ai * cr + br * di - bi * dr));
 }
 
 // Block b of a grid of nb blocks runs on XCD b % 8; give each XCD a
@@ -145,6 +148,7 @@ __global__ __launch_bounds__(64) void k_propose(const Desc* __restrict__ descs, 
   const int L = D.L;
   int o = 0;
   double tn = 0.0, pn = 0.0, to = 0.0, po = 0.0;
+  if (lane < 4) ctl->bar[lane] = 0u;
   if (lane == 0) {
     double u = 0.0, ua = 0.0, ub = 0.0;
     if (mode == 0) {
@@ -256,6 +260,24 @@ __device__ inline void st(GLOBAL cpx<double>* p, const cpx<double>& c) {
   d2v v = {c.x, c.y};
   *(GLOBAL d2v*)p = v;
 }
+// Non-temporal forms: a thread's own a_{s-2} is read once and then
+// overwritten, and a_s is read again only in later steps.
+__device__ inline cpx<float> ld_nt(const GLOBAL cpx<float>* p) {
+  const f2v v = __builtin_nontemporal_load((const GLOBAL f2v*)p);
+  return {v.x, v.y};
+}
+__device__ inline cpx<double> ld_nt(const GLOBAL cpx<double>* p) {
+  const d2v v = __builtin_nontemporal_load((const GLOBAL d2v*)p);
+  return {v.x, v.y};
+}
+__device__ inline void st_nt(GLOBAL cpx<float>* p, const cpx<float>& c) {
+  f2v v = {c.x, c.y};
+  __builtin_nontemporal_store(v, (GLOBAL f2v*)p);
+}
+__device__ inline void st_nt(GLOBAL cpx<double>* p, const cpx<double>& c) {
+  d2v v = {c.x, c.y};
+  __builtin_nontemporal_store(v, (GLOBAL d2v*)p);
+}
 // Global storage of six values per site (the n-slots, the stored hopping
 // rows): planes of 16-byte items, item i of plane q at q * stride + i, so a
 // wave's access to one plane is one contiguous run (a 48- or 96-byte record
@@ -285,6 +307,23 @@ struct Planes<float> {
       p[q * stride + i] = v;
     }
   }
+  __device__ six<float> ld_nt(size_t i) const {
+    six<float> r;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const f4v v = __builtin_nontemporal_load(p + q * stride + i);
+      r.v[2 * q] = {v.x, v.y};
+      r.v[2 * q + 1] = {v.z, v.w};
+    }
+    return r;
+  }
+  __device__ void st_nt(size_t i, const six<float>& r) const {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      f4v v = {r.v[2 * q].x, r.v[2 * q].y, r.v[2 * q + 1].x, r.v[2 * q + 1].y};
+      __builtin_nontemporal_store(v, p + q * stride + i);
+    }
+  }
 };
 template <>
 struct Planes<double> {
@@ -306,6 +345,22 @@ struct Planes<double> {
       p[q * stride + i] = v;
     }
   }
+  __device__ six<double> ld_nt(size_t i) const {
+    six<double> r;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const d2v v = __builtin_nontemporal_load(p + q * stride + i);
+      r.v[q] = {v.x, v.y};
+    }
+    return r;
+  }
+  __device__ void st_nt(size_t i, const six<double>& r) const {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      d2v v = {r.v[q].x, r.v[q].y};
+      __builtin_nontemporal_store(v, p + q * stride + i);
+    }
+  }
 };
 template <typename T>
 __device__ inline Planes<T> planes(void* base, size_t stride) {
@@ -313,10 +368,10 @@ __device__ inline Planes<T> planes(void* base, size_t stride) {
   return Planes<T>{(GLOBAL I*)base, stride};
 }
 
-// One step s >= 1 of |a_s> = c1 Ht'|a_{s-1}> - c2 |a_{s-2}> for the 7 start
-// vectors of every chain in the launch, where Ht' is the hopping part with
-// the factor -t/a folded into c1 (c1 = -t/a, c2 = 0 for s = 1; c1 = -2t/a,
-// c2 = 1 otherwise).  The lattice is bipartite and Ht connects only opposite
+// One step s >= 1 of the recursion (equation "recursive"), |a_1> = Ht|a_0>
+// and |a_s> = 2 Ht|a_{s-1}> - |a_{s-2}> for s >= 2, for the 7 start vectors
+// of every chain in the launch, with the elements of Ht = -(t/a) t_ij formed
+// per bond in FP64 and rounded once (the factor 2 is exact).  The lattice is bipartite and Ht connects only opposite
 // parities, so a^o_s lives on parity p(o)^(s&1) and the six neighbour
 // vectors a^n_s on the other parity; each site therefore stores one value of
 // a^o (o-slot) and six of a^n (n-slots) and a_{s+1} overwrites a_{s-1} in
@@ -387,26 +442,17 @@ __device__ inline int chain_step(int s, const int* __restrict__ act_end, int c, 
   return sl == 1 ? 0 : sl;
 }
 
-template <typename T, bool FIRST, int PPT, bool HOPS>
-__global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ descs,
-                                                       const int* __restrict__ blkoff, int nact,
-                                                       int s_arg, const int* __restrict__ act_end) {
-  __shared__ double xs[4][16][17];
-  __shared__ double gsum[4][256];
-  const int gb = xcd_remap(blockIdx.x, gridDim.x);
-  int c = 0;
-  {
-    int lo = 0, hi = nact - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (blkoff[mid] <= gb) lo = mid; else hi = mid - 1;
-    }
-    c = lo;
-  }
-  const Desc& D = descs[c];
-  const int s = chain_step(s_arg, act_end, c, D.S);
-  if (s == 0) return;   // uniform over the block: the chain does not step now
-  const int lb = gb - blkoff[c];
+// Step s of the chain D on its logical block lb (kStepThreads threads, PPT
+// half-row indices per thread): the stencil, the in-place update and the
+// block's 49 Gram sums.  Shared by the one-launch-per-step kernel and the
+// persistent single-chain kernel.
+// The point after which all loads of a batch (one site, or a group of its
+// directions) must have been issued.
+#define STEP_LOADS_ISSUED() __builtin_amdgcn_sched_barrier(0)
+
+template <typename T, bool FIRST, int PPT, bool HOPS, bool NT>
+__device__ __forceinline__ void step_block(const Desc& D, const int lb, const int s,
+                                           double (*xs)[16][17], double (*gsum)[256]) {
   const int L = D.L, hx = L >> 1, half = D.half;
   const Ctl* ctl = D.ctl;
   const int pO = ctl->parity_o;
@@ -416,7 +462,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   int sh[6];
 #pragma unroll
   for (int e = 0; e < 6; ++e) sh[e] = FIRST ? ctl->start_half[1 + e] : 0;
-  const T c1 = FIRST ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
+  const double hsc = -D.t / D.a;        // Ht = -(t/a) t_ij
+  const T two = FIRST ? (T)1 : (T)2;     // |a_1> = Ht|a_0>, then 2 Ht|a_{s-1}> - |a_{s-2}>
   const GLOBAL spn<T>* sp = (const GLOBAL spn<T>*)D.spin;            // [2][half]
   GLOBAL cpx<T>* vo = (GLOBAL cpx<T>*)D.vec;                         // o-slots [2][half]
   const Planes<T> vn = planes<T>((cpx<T>*)D.vec + D.N, D.N);        // n-slots [2][half]
@@ -435,44 +482,58 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
     const int k = h % hx, r = h / hx, y = r % L, z = r / L;
     const int xo = 2 * k + ((y + z + po) & 1);
     const int xn = 2 * k + ((y + z + pn) & 1);
-    // a^o_s on the o-site
+    // a^o_s on the o-site.  Every load of the site is issued before its
+    // arithmetic (one memory round trip): left to itself the compiler keeps
+    // registers low by waiting for each direction's loads in turn, and the
+    // kernel becomes bound by the latency of those round trips.
     {
-      spn<T> si;
+      int nh[6];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) nh[d] = nb_half(xo, y, z, d, L);
+      spn<T> si, sj[6];
       six<T> row;
-      if (HOPS) row = hrow.ld((size_t)po * half + h);
-      else si = ld(sp_o + h);
+      cpx<T> an[6], pr = {(T)0, (T)0};
+      if (HOPS) {
+        row = hrow.ld((size_t)po * half + h);
+      } else {
+        si = ld(sp_o + h);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) sj[d] = ld(sp_n + nh[d]);
+      }
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        if (FIRST) { an[d].x = (nh[d] == o_half) ? (T)1 : (T)0; an[d].y = 0; }
+        else an[d] = ld(vo + (size_t)pn * half + nh[d]);
+      }
+      if (!FIRST) pr = NT ? ld_nt(vo + (size_t)po * half + h) : ld(vo + (size_t)po * half + h);
+      STEP_LOADS_ISSUED();
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
-        const int nh = nb_half(xo, y, z, d, L);
         T hr, hi_;
         if (HOPS) {
           hr = row.v[d].x;
           hi_ = row.v[d].y;
         } else {
-          const spn<T> sj = ld(sp_n + nh);
-          hop_spinor(si, sj, hr, hi_);
+          hop_spinor(si, sj[d], hsc, hr, hi_);
         }
-        cpx<T> an;
-        if (FIRST) { an.x = (nh == o_half) ? (T)1 : (T)0; an.y = 0; }
-        else an = ld(vo + (size_t)pn * half + nh);
-        ar += hr * an.x - hi_ * an.y;
-        ai += hr * an.y + hi_ * an.x;
+        ar += hr * an[d].x - hi_ * an[d].y;
+        ai += hr * an[d].y + hi_ * an[d].x;
       }
       cpx<T> ao;
-      ao.x = c1 * ar;
-      ao.y = c1 * ai;
-      if (!FIRST) {
-        const cpx<T> pr = ld(vo + (size_t)po * half + h);
-        ao.x -= pr.x;
-        ao.y -= pr.y;
-      }
-      st(vo + (size_t)po * half + h, ao);
+      ao.x = two * ar - pr.x;
+      ao.y = two * ai - pr.y;
+      if (NT) st_nt(vo + (size_t)po * half + h, ao);
+      else st(vo + (size_t)po * half + h, ao);
       x[p][14] = (double)ao.x;
       x[p][15] = (double)ao.y;
     }
-    // a^{n_e}_s, e = 0..5, on the n-site
+    // a^{n_e}_s, e = 0..5, on the n-site: the six directions in groups of
+    // kGroup, each group's loads issued together (six 16-value records at
+    // once are too many registers to keep the occupancy; groups of two
+    // measured fastest on the HBM-resident batches)
     {
+      constexpr int kGroup = 2;
       spn<T> si;
       six<T> row;
       if (HOPS) row = hrow.ld((size_t)pn * half + h);
@@ -480,37 +541,55 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
       T accr[6], acci[6];
 #pragma unroll
       for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
+      six<T> prev;
+      cpx<T> aop;   // a^o_{s-1} at the n-site
 #pragma unroll
-      for (int d = 0; d < 6; ++d) {
-        const int nh = nb_half(xn, y, z, d, L);
-        T hr, hi_;
-        if (HOPS) {
-          hr = row.v[d].x;
-          hi_ = row.v[d].y;
-        } else {
-          const spn<T> sj = ld(sp_o + nh);
-          hop_spinor(si, sj, hr, hi_);
+      for (int d0 = 0; d0 < 6; d0 += kGroup) {
+        int nh[kGroup];
+        spn<T> sj[kGroup];
+        six<T> an[kGroup];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) nh[g] = nb_half(xn, y, z, d0 + g, L);
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+          if (!HOPS) sj[g] = ld(sp_o + nh[g]);
+          if (FIRST) {
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+              an[g].v[e].x = (nh[g] == sh[e]) ? (T)1 : (T)0;
+              an[g].v[e].y = 0;
+            }
+          } else {
+            an[g] = vn.ld((size_t)po * half + nh[g]);
+          }
         }
-        six<T> an;
-        if (FIRST) {
-#pragma unroll
-          for (int e = 0; e < 6; ++e) { an.v[e].x = (nh == sh[e]) ? (T)1 : (T)0; an.v[e].y = 0; }
-        } else {
-          an = vn.ld((size_t)po * half + nh);
+        if (d0 + kGroup >= 6 && !FIRST) {   // the site's own values ride with the last group
+          prev = NT ? vn.ld_nt((size_t)pn * half + h) : vn.ld((size_t)pn * half + h);
+          aop = ld(vo + (size_t)pn * half + h);
         }
+        STEP_LOADS_ISSUED();
 #pragma unroll
-        for (int e = 0; e < 6; ++e) {
-          accr[e] += hr * an.v[e].x - hi_ * an.v[e].y;
-          acci[e] += hr * an.v[e].y + hi_ * an.v[e].x;
+        for (int g = 0; g < kGroup; ++g) {
+          const int d = d0 + g;
+          T hr, hi_;
+          if (HOPS) {
+            hr = row.v[d].x;
+            hi_ = row.v[d].y;
+          } else {
+            hop_spinor(si, sj[g], hsc, hr, hi_);
+          }
+#pragma unroll
+          for (int e = 0; e < 6; ++e) {
+            accr[e] += hr * an[g].v[e].x - hi_ * an[g].v[e].y;
+            acci[e] += hr * an[g].v[e].y + hi_ * an[g].v[e].x;
+          }
         }
       }
       six<T> out;
-      six<T> prev;
-      if (!FIRST) prev = vn.ld((size_t)pn * half + h);
 #pragma unroll
       for (int e = 0; e < 6; ++e) {
-        out.v[e].x = c1 * accr[e];
-        out.v[e].y = c1 * acci[e];
+        out.v[e].x = two * accr[e];
+        out.v[e].y = two * acci[e];
         if (!FIRST) {
           out.v[e].x -= prev.v[e].x;
           out.v[e].y -= prev.v[e].y;
@@ -518,8 +597,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
         x[p][2 * e] = (double)out.v[e].x;
         x[p][2 * e + 1] = (double)out.v[e].y;
       }
-      vn.st((size_t)pn * half + h, out);
-      cpx<T> aop;   // a^o_{s-1} at the n-site
+      if (NT) vn.st_nt((size_t)pn * half + h, out);
+      else vn.st((size_t)pn * half + h, out);
       if (FIRST) {
         aop.x = (h == o_half) ? (T)1 : (T)0;
         aop.y = 0;
@@ -529,8 +608,6 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
 #pragma unroll
         for (int e = 0; e < 6; ++e) { u.v[e].x = (h == sh[e]) ? (T)1 : (T)0; u.v[e].y = 0; }
         vn.st((size_t)po * half + h, u);
-      } else {
-        aop = ld(vo + (size_t)pn * half + h);
       }
       x[p][12] = (double)aop.x;
       x[p][13] = (double)aop.y;
@@ -573,6 +650,104 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
     D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo(gsum, gram_combo_index(t));
 }
 
+template <typename T, bool FIRST, int PPT, bool HOPS, bool NT>
+__global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ descs,
+                                                       const int* __restrict__ blkoff, int nact,
+                                                       int s_arg, const int* __restrict__ act_end) {
+  __shared__ double xs[4][16][17];
+  __shared__ double gsum[4][256];
+  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+  int c = 0;
+  {
+    int lo = 0, hi = nact - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (blkoff[mid] <= gb) lo = mid; else hi = mid - 1;
+    }
+    c = lo;
+  }
+  const Desc& D = descs[c];
+  const int s = chain_step(s_arg, act_end, c, D.S);
+  if (s == 0) return;   // uniform over the block: the chain does not step now
+  step_block<T, FIRST, PPT, HOPS, NT>(D, gb - blkoff[c], s, xs, gsum);
+}
+
+// ------------------------------------------- persistent single chain ---
+// A lone mid-size chain (its vectors fit one compute die's L2) takes all M/2
+// steps of a proposal in one launch instead of M/2 launches of a few
+// microseconds each.  Blocks are dealt to the eight compute dies (XCDs) in
+// turn; the first block to start claims its die, and the first nb blocks on
+// that die take the work (the others return), so every block of the run
+// shares one L2 and the step barrier's counter lives there.  Between steps
+// each block releases its stores and acquires the others' at device scope
+// (the L2 write-back and the L1 and L2 invalidation the memory model
+// prescribes for visibility across compute units); one thread per block
+// counts in at the L2 and polls it past the L1.  Waits are bounded: on a
+// timeout the run sets an error flag, every block returns, and the
+// reconstruction leaves the chain unchanged.
+constexpr int kBarrierSpins = 1 << 21;
+
+__device__ inline unsigned xcd_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 0xfu;   // HW_REG_XCC_ID, bits 3:0
+}
+
+__device__ inline bool die_barrier(unsigned* count, unsigned target, unsigned* err, int* ok_sh) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this wave's stores are visible
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    for (int i = 0;
+         __hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++i) {
+      if (i >= kBarrierSpins ||
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
+        __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    *ok_sh = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // no stale lines of others' stores
+  return *ok_sh != 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kStepThreads) void k_persist(const Desc* __restrict__ descs, int nb) {
+  __shared__ double xs[4][16][17];
+  __shared__ double gsum[4][256];
+  __shared__ int tk, ok_sh;
+  const Desc& D = descs[0];
+  unsigned* bar = D.ctl->bar;
+  if (threadIdx.x == 0) {
+    const unsigned x = xcd_id() + 1u;
+    unsigned old = 0u;
+    __hip_atomic_compare_exchange_strong(&bar[1], &old, x, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_SYSTEM);
+    const unsigned die = old ? old : x;   // old == 0: this block claimed its die
+    tk = (x == die) ? (int)__hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_SYSTEM)
+                    : nb;
+  }
+  __syncthreads();
+  const int lb = tk;
+  if (lb >= nb) return;
+  for (int s = 1; s <= D.S; ++s) {
+    if (s == 1) step_block<T, true, 1, false, false>(D, lb, 1, xs, gsum);
+    else step_block<T, false, 1, false, false>(D, lb, s, xs, gsum);
+    if (s == D.S) break;
+    if (!die_barrier(&bar[2], (unsigned)nb * (unsigned)s, &bar[3], &ok_sh)) return;
+  }
+}
+
+// Census of the dies a grid of `blocks` lands on: counts[die] += 1 per block.
+__global__ void k_die_census(unsigned* counts) {
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(&counts[xcd_id()], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Small lattices: one workgroup runs all M/2 steps of one chain out of LDS,
 // so a proposal costs one launch instead of M/2.  Same arithmetic as k_step
 // (sum over the six directions in order, a_{s+1} over a_{s-1} in place, the
@@ -607,6 +782,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
 #pragma unroll
   for (int e = 0; e < 6; ++e) sh[e] = ctl->start_half[1 + e];
   const GLOBAL spn<T>* gsp = (const GLOBAL spn<T>*)D.spin;
+  const double hsc = -D.t / D.a;   // Ht = -(t/a) t_ij
   // global (not flat) stores of the step partials: a flat store counts against
   // the LDS wait counter, so every barrier would wait for its write to memory
   GLOBAL double* part = (GLOBAL double*)D.part;
@@ -622,7 +798,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
     for (int d = 0; d < 6; ++d) {
       const int nh = nb_half(x, y, z, d, L);
       T hr, hi_;
-      hop_spinor(si, ld(gsp + (size_t)(par ^ 1) * half + nh), hr, hi_);
+      hop_spinor(si, ld(gsp + (size_t)(par ^ 1) * half + nh), hsc, hr, hi_);
       hp[d * N + q] = cpx<T>{hr, hi_};
       nb[d * N + q] = nh;
       vn[d * N + q] = cpx<T>{(par != pO && h == sh[d]) ? (T)1 : (T)0, (T)0};
@@ -649,7 +825,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
     if (defer && s > 1 && combiner)
       part[(size_t)(s - 2) * kNP + t49] = gram_combo(gsum[(s - 1) & 1], cmb);
     const int po = pO ^ (s & 1), pn = po ^ 1;   // parities that carry a^o_s, a^n_s
-    const T c1 = (s == 1) ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
+    const T two = (s == 1) ? (T)1 : (T)2;   // |a_1> = Ht|a_0>, then 2 Ht|a_{s-1}> - |a_{s-2}>
     // item (j, h): j = 0 forms a^o_s at the o-site (po, h), j >= 1 forms
     // a^{n_{j-1}}_s at the n-site (pn, h); at s = 1 the slot being
     // overwritten holds zero, so subtracting it is exact
@@ -677,7 +853,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
         ar += hv[d].x * an[d].x - hv[d].y * an[d].y;
         ai += hv[d].x * an[d].y + hv[d].y * an[d].x;
       }
-      *dst = cpx<T>{c1 * ar - pr.x, c1 * ai - pr.y};
+      *dst = cpx<T>{two * ar - pr.x, two * ai - pr.y};
     }
     __syncthreads();
     // Gram matrix of the 16-vector of every site pair h,
@@ -786,7 +962,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
     dr[e] = FIRST ? (T)ctl->delta[2 * e] : (T)0;
     di[e] = FIRST ? (T)ctl->delta[2 * e + 1] : (T)0;
   }
-  const T c1 = FIRST ? (T)(-D.t / D.a) : (T)(-2.0 * D.t / D.a);
+  const double hsc = -D.t / D.a;        // Ht = -(t/a) t_ij
+  const T two = FIRST ? (T)1 : (T)2;     // |a_1> = Ht|a_0>, then 2 Ht|a_{s-1}> - |a_{s-2}>
   const GLOBAL spn<T>* sp = (const GLOBAL spn<T>*)D.spin;
   GLOBAL cpx<T>* vo = (GLOBAL cpx<T>*)D.vec;               // o-slots [2][half]
   GLOBAL cpx<T>* vv = (GLOBAL cpx<T>*)D.vec + D.N;         // v-slots [2][half]
@@ -809,58 +986,68 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
     const int xo = 2 * k + ((y + z + po) & 1);
     const int xn = 2 * k + ((y + z + pn) & 1);
     cpx<T> ao, av, aop;
+    // each site's loads issued together, before its arithmetic (one memory
+    // round trip per site instead of one per direction)
     {
+      int nh[6];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) nh[d] = nb_half(xo, y, z, d, L);
       const spn<T> si = ld(sp_o + h);
+      spn<T> sj[6];
+      cpx<T> an[6], pr = {(T)0, (T)0};
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        sj[d] = ld(sp_n + nh[d]);
+        if (FIRST) { an[d].x = (nh[d] == o_half) ? (T)1 : (T)0; an[d].y = 0; }
+        else an[d] = ld(vo + (size_t)pn * half + nh[d]);
+      }
+      if (!FIRST) pr = ld(vo + (size_t)po * half + h);
+      STEP_LOADS_ISSUED();
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
-        const int nh = nb_half(xo, y, z, d, L);
-        const spn<T> sj = ld(sp_n + nh);
         T hr, hi_;
-        hop_spinor(si, sj, hr, hi_);
-        cpx<T> an;
-        if (FIRST) { an.x = (nh == o_half) ? (T)1 : (T)0; an.y = 0; }
-        else an = ld(vo + (size_t)pn * half + nh);
-        ar += hr * an.x - hi_ * an.y;
-        ai += hr * an.y + hi_ * an.x;
+        hop_spinor(si, sj[d], hsc, hr, hi_);
+        ar += hr * an[d].x - hi_ * an[d].y;
+        ai += hr * an[d].y + hi_ * an[d].x;
       }
-      ao.x = c1 * ar;
-      ao.y = c1 * ai;
-      if (!FIRST) {
-        const cpx<T> pr = ld(vo + (size_t)po * half + h);
-        ao.x -= pr.x;
-        ao.y -= pr.y;
-      }
+      ao.x = two * ar - pr.x;
+      ao.y = two * ai - pr.y;
       st(vo + (size_t)po * half + h, ao);
     }
     {
+      int nh[6];
+#pragma unroll
+      for (int d = 0; d < 6; ++d) nh[d] = nb_half(xn, y, z, d, L);
       const spn<T> si = ld(sp_n + h);
+      spn<T> sj[6];
+      cpx<T> an[6], pr = {(T)0, (T)0};
+#pragma unroll
+      for (int d = 0; d < 6; ++d) {
+        sj[d] = ld(sp_o + nh[d]);
+        an[d] = FIRST ? v0(nh[d]) : ld(vv + (size_t)po * half + nh[d]);
+      }
+      if (!FIRST) {
+        pr = ld(vv + (size_t)pn * half + h);
+        aop = ld(vo + (size_t)pn * half + h);
+      }
+      STEP_LOADS_ISSUED();
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
-        const int nh = nb_half(xn, y, z, d, L);
-        const spn<T> sj = ld(sp_o + nh);
         T hr, hi_;
-        hop_spinor(si, sj, hr, hi_);
-        const cpx<T> an = FIRST ? v0(nh) : ld(vv + (size_t)po * half + nh);
-        ar += hr * an.x - hi_ * an.y;
-        ai += hr * an.y + hi_ * an.x;
+        hop_spinor(si, sj[d], hsc, hr, hi_);
+        ar += hr * an[d].x - hi_ * an[d].y;
+        ai += hr * an[d].y + hi_ * an[d].x;
       }
-      av.x = c1 * ar;
-      av.y = c1 * ai;
-      if (!FIRST) {
-        const cpx<T> pr = ld(vv + (size_t)pn * half + h);
-        av.x -= pr.x;
-        av.y -= pr.y;
-      }
+      av.x = two * ar - pr.x;
+      av.y = two * ai - pr.y;
       st(vv + (size_t)pn * half + h, av);
       if (FIRST) {
         aop.x = (h == o_half) ? (T)1 : (T)0;
         aop.y = 0;
         st(vo + (size_t)pn * half + h, aop);
         st(vv + (size_t)po * half + h, v0(h));
-      } else {
-        aop = ld(vo + (size_t)pn * half + h);
       }
     }
     const double aor = ao.x, aoi = ao.y, avr = av.x, avi = av.y, apr = aop.x, api = aop.y;
@@ -1277,10 +1464,11 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
     __syncthreads();
   }
   if (tid == 0) {
-    const double ds = red[0];
+    const bool failed = ctl->bar[3] != 0u;   // the persistent step run timed out
+    const double ds = failed ? __builtin_nan("") : red[0];
     ctl->dseff = ds;
     ctl->phase_top = ptop;
-    if (ctl->mode == 0) {
+    if (ctl->mode == 0 && !failed) {
       const double u = ctl->u;
       const int own = (ds <= 0.0 || u < exp(-ds)) ? 1 : 0;
       const int f = force ? force[c] : -1;
@@ -1320,7 +1508,7 @@ __device__ inline void build_row(const Desc& D, int site) {
   for (int d = 0; d < 6; ++d) {
     const int nh = nb_half(x, y, z, d, D.L);
     const spn<T> sj = sp[(size_t)(par ^ 1) * D.half + nh];
-    hop_spinor(si, sj, row.v[d].x, row.v[d].y);
+    hop_spinor(si, sj, -D.t / D.a, row.v[d].x, row.v[d].y);
   }
   planes<T>(D.hop, D.N).st((size_t)par * D.half + hh, row);
 }
@@ -1438,8 +1626,8 @@ hipError_t launch_propose(const Desc* d, int n, hipStream_t st) {
 }
 
 template <typename T, int PPT, bool HOPS>
-hipError_t launch_step_t(int ov, const Desc* d, const int* blkoff, int nact, int blocks, int s,
-                         const int* act_end, hipStream_t st) {
+hipError_t launch_step_t(int ov, int nt, const Desc* d, const int* blkoff, int nact, int blocks,
+                         int s, const int* act_end, hipStream_t st) {
   const dim3 g(blocks), b(kStepThreads);
   // round launches (act_end) never run step 1: it has a launch of its own
   const bool first = !act_end && s == 1;
@@ -1448,29 +1636,33 @@ hipError_t launch_step_t(int ov, const Desc* d, const int* blkoff, int nact, int
       hipLaunchKernelGGL((k_step_ov<T, true, PPT>), g, b, 0, st, d, blkoff, nact, s, act_end);
     else
       hipLaunchKernelGGL((k_step_ov<T, false, PPT>), g, b, 0, st, d, blkoff, nact, s, act_end);
+  } else if (first) {
+    hipLaunchKernelGGL((k_step<T, true, PPT, HOPS, false>), g, b, 0, st, d, blkoff, nact, s,
+                       act_end);
+  } else if (nt) {
+    hipLaunchKernelGGL((k_step<T, false, PPT, HOPS, true>), g, b, 0, st, d, blkoff, nact, s,
+                       act_end);
   } else {
-    if (first)
-      hipLaunchKernelGGL((k_step<T, true, PPT, HOPS>), g, b, 0, st, d, blkoff, nact, s, act_end);
-    else
-      hipLaunchKernelGGL((k_step<T, false, PPT, HOPS>), g, b, 0, st, d, blkoff, nact, s, act_end);
+    hipLaunchKernelGGL((k_step<T, false, PPT, HOPS, false>), g, b, 0, st, d, blkoff, nact, s,
+                       act_end);
   }
   return hipGetLastError();
 }
 
 template <typename T, bool HOPS>
-hipError_t launch_step_h(int ov, int ppt, const Desc* d, const int* blkoff, int nact, int blocks,
-                         int s, const int* act_end, hipStream_t st) {
-  return ppt == 2 ? launch_step_t<T, 2, HOPS>(ov, d, blkoff, nact, blocks, s, act_end, st)
-                  : launch_step_t<T, 1, HOPS>(ov, d, blkoff, nact, blocks, s, act_end, st);
+hipError_t launch_step_h(int ov, int nt, int ppt, const Desc* d, const int* blkoff, int nact,
+                         int blocks, int s, const int* act_end, hipStream_t st) {
+  return ppt == 2 ? launch_step_t<T, 2, HOPS>(ov, nt, d, blkoff, nact, blocks, s, act_end, st)
+                  : launch_step_t<T, 1, HOPS>(ov, nt, d, blkoff, nact, blocks, s, act_end, st);
 }
 
 hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const int* blkoff,
-                       int nact, int blocks, int s, hipStream_t st, const int* act_end) {
+                       int nact, int blocks, int s, hipStream_t st, const int* act_end, int nt) {
   if (fp32)
-    return hops ? launch_step_h<float, true>(ov, ppt, d, blkoff, nact, blocks, s, act_end, st)
-                : launch_step_h<float, false>(ov, ppt, d, blkoff, nact, blocks, s, act_end, st);
-  return hops ? launch_step_h<double, true>(ov, ppt, d, blkoff, nact, blocks, s, act_end, st)
-              : launch_step_h<double, false>(ov, ppt, d, blkoff, nact, blocks, s, act_end, st);
+    return hops ? launch_step_h<float, true>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st)
+                : launch_step_h<float, false>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st);
+  return hops ? launch_step_h<double, true>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st)
+              : launch_step_h<double, false>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st);
 }
 
 hipError_t launch_hops(int fp32, const Desc* d, int nmax, hipStream_t st) {
@@ -1522,6 +1714,20 @@ hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st) 
 
 hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStream_t st) {
   hipLaunchKernelGGL(k_fisher_yates, dim3(1), dim3(1), 0, st, d, nr, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_persist(int fp32, const Desc* d, int nb, hipStream_t st) {
+  // eight blocks per working block: nb of them land on every die
+  void* args[] = {(void*)&d, (void*)&nb};
+  const dim3 g(8 * nb), b(kStepThreads);
+  if (fp32)
+    return hipLaunchCooperativeKernel((const void*)k_persist<float>, g, b, args, 0, st);
+  return hipLaunchCooperativeKernel((const void*)k_persist<double>, g, b, args, 0, st);
+}
+
+hipError_t launch_die_census(unsigned* counts, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_die_census, dim3(blocks), dim3(64), 0, st, counts);
   return hipGetLastError();
 }
 

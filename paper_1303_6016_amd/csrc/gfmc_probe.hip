@@ -2,10 +2,13 @@
 // ceiling the step kernel's algorithmic bandwidth is compared against).
 //
 // Four access patterns over caller buffers of `bytes` each, 16-byte items,
-// four items in flight per thread, grid-stride: read only, write only, copy
-// (one read + one write), and two reads + one write (the step kernel's mix
-// of stored values read to values written is 2 : 1).  The rate counts the
-// bytes each pattern must move once: 1, 1, 2 and 3 buffers per pass.
+// grid-stride with one item per thread and pass (measured on MI355X: four
+// independent items per thread in flight, spread a grid apart, stream 10-20 %
+// slower from HBM): read only, write only, copy (one read + one write), and
+// two reads + one write (the step kernel's mix of stored values read to
+// values written is 2 : 1).  Grids of 2 to 16 blocks per compute unit are
+// timed and the fastest counts.  The rate counts the bytes each pattern must
+// move once: 1, 1, 2 and 3 buffers per pass.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,7 +19,7 @@
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 1;
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_stream(const f4* __restrict__ a, const f4* __restrict__ b,
@@ -80,29 +83,34 @@ extern "C" gfmc_status gfmc_stream_bandwidth(int32_t mode, const void* a, const 
   int dev = 0, cus = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  // eight 256-thread blocks per compute unit, each thread kUnroll items in flight
-  size_t want = (n + (size_t)kUnroll * 256 - 1) / ((size_t)kUnroll * 256);
-  const int grid = (int)std::min<size_t>(want, (size_t)cus * 8);
+  const size_t want = (n + (size_t)kUnroll * 256 - 1) / ((size_t)kUnroll * 256);
   const f4* fa = (const f4*)a;
   const f4* fb = (const f4*)b;
   f4* fc = (f4*)c;
-  HIPCHK(launch_mode(mode, fa, fb, fc, n, grid, st));   // warm-up pass
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return gfmc_fail(GFMC_EDEVICE, "hipEventCreate failed");
   }
-  hipError_t e = hipEventRecord(e0, st);
-  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_mode(mode, fa, fb, fc, n, grid, st);
-  if (e == hipSuccess) e = hipEventRecord(e1, st);
-  if (e == hipSuccess) e = hipEventSynchronize(e1);
-  float ms = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  const double per = (mode <= 1) ? 1.0 : (mode == 2 ? 2.0 : 3.0);
+  double best = 0.0;
+  hipError_t e = hipSuccess;
+  for (int bpc : {2, 4, 8, 16}) {
+    const int grid = (int)std::max<size_t>(1, std::min<size_t>(want, (size_t)cus * bpc));
+    e = launch_mode(mode, fa, fb, fc, n, grid, st);   // warm-up pass
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_mode(mode, fa, fb, fc, n, grid, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) break;
+    best = std::max(best, per * (double)bytes * reps / (ms * 1e-3) / 1e9);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return gfmc_fail(GFMC_EDEVICE, std::string("stream probe: ") + hipGetErrorString(e));
-  const double per = (mode <= 1) ? 1.0 : (mode == 2 ? 2.0 : 3.0);
-  *gbs = per * (double)bytes * reps / (ms * 1e-3) / 1e9;
+  *gbs = best;
   return GFMC_OK;
 }

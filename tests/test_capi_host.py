@@ -82,8 +82,7 @@ def test_null_handles_and_bad_arguments_are_rejected_on_the_host():
 
 # The validated range of the FP32 recursion (include/gfmc.h, gfmc_precision):
 # just inside and just outside its edges in M and in beta t.
-FP32_EDGES = [(2, 512), (4, 1024), (6, 1024), (8, 2048), (16, 2048), (24, 2048), (32, 8192),
-              (64, 8192)]
+FP32_EDGES = [(4, 1024), (6, 1024), (8, 4096), (12, 4096), (16, 8192), (32, 8192), (64, 8192)]
 
 
 @pytest.mark.parametrize("L,M", FP32_EDGES)
@@ -97,6 +96,15 @@ def test_fp32_guard_edges_in_moment_count(L, M):
         # FP64 has no such limit; FP32 outside the range is available for measuring its error
         assert _bytes(L=L, M=M + 2, K=2 * M, precision=0) > 0
         assert _bytes(L=L, M=M + 2, K=2 * M, precision=1, fp32_unvalidated=1) > 0
+
+
+def test_fp32_guard_refuses_the_smallest_lattice():
+    import paper_1303_6016_amd as g
+    with pytest.raises(g.GfmcError) as e:
+        _bytes(L=2, M=32, precision=1)
+    assert e.value.status == g.GFMC_EINVAL
+    assert _bytes(L=2, M=32, precision=0) > 0
+    assert _bytes(L=2, M=32, precision=1, fp32_unvalidated=1) > 0
 
 
 def test_fp32_guard_edge_in_beta():

@@ -53,6 +53,11 @@ def make(g, L, M, prec=0, seed=0, chain_id=0, **kw):
                                             (6, 128, 3, [0, 100, 215]), (8, 256, 4, [3, 511])])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_moments_small(g, L, M, seed, sites, prec):
+    if prec == 1 and L < 4:   # outside the FP32 recursion's validated range
+        with pytest.raises(g.GfmcError) as e:
+            make(g, L, M, prec)
+        assert e.value.status == g.GFMC_EINVAL
+        return
     ch, m = make(g, L, M, prec)
     th, ph = synth.random_angles(m.N, seed)
     ch.set_spins(th, ph)
@@ -111,6 +116,11 @@ def test_moment_invariants_on_device(g):
                                         (2, 64, 8192, 20.0)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_delta_seff(g, L, M, K, beta, prec):
+    if prec == 1 and L < 4:   # outside the FP32 recursion's validated range
+        with pytest.raises(g.GfmcError) as e:
+            make(g, L, M, prec, beta=beta, K=K)
+        assert e.value.status == g.GFMC_EINVAL
+        return
     ch, m = make(g, L, M, prec, beta=beta, K=K)
     th, ph = synth.random_angles(m.N, 5)
     ch.set_spins(th, ph)
@@ -130,23 +140,29 @@ def test_delta_seff(g, L, M, K, beta, prec):
 
 def test_delta_seff_largest_moment_count(g):
     # M = K = 8192, the largest the library accepts: the reconstruction block
-    # holds 8192 nodes in LDS; one oracle evaluation serves both precisions.
-    # The FP32 recursion's error grows with M and is largest on small lattices,
-    # where each vector covers few sites: on 4^3 at M = 4096 and 8192 it
-    # reaches 3e-5 to 6e-4 in Delta S, beyond the FP32 bound, so FP32 is only
-    # checked against gross failure (a wrong node count or table gives errors
-    # of order one)
+    # holds 8192 nodes in LDS.  FP64 on 4^3 against the oracle; the FP32
+    # recursion at this M lies outside its validated range on 4^3 (EINVAL) and
+    # inside it on 32^3, where it must meet the FP32 bound at the range's
+    # largest beta t = 50.
     m = oracle.Model(L=4, M=8192, beta=20.0)
     th, ph = synth.random_angles(m.N, 5)
     ref, rtop = oracle.delta_seff(m, th, ph, 3, 1.0, 2.0, with_phase_top=True)
-    for prec, tol in ((0, FP64_DS), (1, 1e-3)):
-        ch, _ = make(g, 4, 8192, prec, beta=20.0)
-        ch.set_spins(th, ph)
-        got, top = ch.delta_seff(3, 1.0, 2.0, with_phase_top=True)
-        print(f"M=K=8192 prec={prec} dS={ref:.6f} err={got - ref:.2e} top={top:.2e}", flush=True)
-        assert abs(got - ref) < tol
-        if prec == 0:   # FP32 noise, times 1/sin th at the outermost nodes, moves the top phase
-            assert abs(top - rtop) < 1e-8
+    ch, _ = make(g, 4, 8192, 0, beta=20.0)
+    ch.set_spins(th, ph)
+    got, top = ch.delta_seff(3, 1.0, 2.0, with_phase_top=True)
+    print(f"4^3 M=K=8192 FP64 dS={ref:.6f} err={got - ref:.2e} top={top:.2e}", flush=True)
+    assert abs(got - ref) < FP64_DS and abs(top - rtop) < 1e-8
+    with pytest.raises(g.GfmcError) as e:
+        make(g, 4, 8192, 1, beta=20.0)
+    assert e.value.status == g.GFMC_EINVAL
+    m32 = oracle.Model(L=32, M=8192, beta=50.0, seed=2, chain_id=5)
+    th, ph = synth.random_angles(m32.N, 6)
+    ref = oracle.delta_seff(m32, th, ph, 1234, 1.0, 2.0)
+    ch, _ = make(g, 32, 8192, 1, beta=50.0, seed=2, chain_id=5)
+    ch.set_spins(th, ph)
+    got = ch.delta_seff(1234, 1.0, 2.0)
+    print(f"32^3 M=K=8192 FP32 beta=50 dS={ref:.6f} err={got - ref:.2e}", flush=True)
+    assert abs(got - ref) < FP32_DS
 
 
 def test_delta_seff_lorentz_and_identity(g):

@@ -96,8 +96,7 @@ def test_step_granular_uneven_counts_and_validation(g):
     b.set_schedule(False)
     b.step(1)   # lock-step: one more each
     assert [c.get_counter() for c in chs] == [4, 5]
-    with pytest.raises(g.GfmcError):
-        b.set_schedule(2)
+    assert g.lib().gfmc_batch_set_schedule(b.h, 2) == g.GFMC_EINVAL
     b.close()
     for i, sp in enumerate(specs):
         ch = mk(i, *sp)
@@ -106,3 +105,61 @@ def test_step_granular_uneven_counts_and_validation(g):
         th, ph = ch.get_spins()
         gth, gph = chs[i].get_spins()
         assert np.array_equal(gth, th) and np.array_equal(gph, ph)
+
+
+@pytest.mark.parametrize("L,M,prec", [(16, 256, 0), (12, 128, 1), (10, 64, 0), (24, 64, 1)])
+def test_lone_chain_persistent_run_equals_step_launches(g, L, M, prec):
+    # A lone chain that fits one compute die runs all M/2 steps of a proposal
+    # in one persistent launch; the same chain beside another one in a batch
+    # runs one launch per step.  Same step code and block table: the
+    # trajectories must agree bit for bit, and with the oracle's moments.
+    import oracle
+    import synth
+    p = g.Params(L=L, M=M, beta=20.0, precision=prec, seed=5, chain_id=2)
+    probe = g.Chain(p)
+    pb = g.Batch([probe])
+    assert pb.form()["persistent"] > 0   # the lone chain takes the persistent path
+    pb.close()
+    lone = g.Chain(p)
+    th, ph = synth.random_angles(L ** 3, 3)
+    lone.set_spins(th, ph)
+    mu = lone.moments(17)
+    ref = oracle.moments(oracle.Model(L=L, M=M, beta=20.0, seed=5, chain_id=2), th, ph, 17)
+    assert np.abs(mu - ref).max() < (1e-12 if prec == 0 else 1e-5)
+    recs = [lone.step() for _ in range(4)]
+    a = g.Chain(p)
+    a.set_spins(th, ph)
+    other = g.Chain(g.Params(L=L, M=M, beta=5.0, precision=prec, seed=9))
+    b = g.Batch([a, other])
+    b.set_tuning(1)
+    assert b.form()["persistent"] == 0
+    brecs = b.step(4, records=True)
+    b.close()
+    for q in range(4):
+        assert brecs[q][0].site == recs[q].site and brecs[q][0].dseff == recs[q].dseff
+        assert brecs[q][0].accepted == recs[q].accepted
+    t1, p1 = lone.get_spins()
+    t2, p2 = a.get_spins()
+    assert np.array_equal(t1, t2) and np.array_equal(p1, p2)
+
+
+def test_nontemporal_steps_do_not_change_results(g):
+    # non-temporal loads and stores change only how the caches keep the lines
+    def run(nt):
+        chs = [g.Chain(g.Params(L=L, M=64, beta=10.0, precision=1, seed=12, chain_id=i))
+               for i, L in enumerate((12, 16))]
+        for c in chs:
+            c.init_spins(g.INIT_RANDOM)
+        b = g.Batch(chs)
+        b.set_tuning(1)
+        b.set_nontemporal(nt)
+        assert b.form()["nontemporal"] == int(nt)
+        recs = b.step(3, records=True)
+        b.close()
+        return [(r.site, r.dseff, r.accepted) for row in recs for r in row], \
+               [c.get_spins() for c in chs]
+    r0, s0 = run(False)
+    r1, s1 = run(True)
+    assert r0 == r1
+    for (a, b_), (c, d) in zip(s0, s1):
+        assert np.array_equal(a, c) and np.array_equal(b_, d)
