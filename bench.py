@@ -60,6 +60,9 @@ def parse():
                          "instead of autotuning")
     ap.add_argument("--pair", type=int, default=1,
                     help="also time the {o, v} start-vector form on the same workload")
+    ap.add_argument("--pair-tuning", type=str, default="",
+                    help="PPT,LANES for the pair-form leg (shape 3: two steps per launch); "
+                         "default: autotune")
     ap.add_argument("--stored-hops", type=int, default=1,
                     help="also time the stored-hopping A/B variant of the step kernel")
     ap.add_argument("--small", type=int, default=1,
@@ -785,7 +788,7 @@ def main():
             ch.init_spins(g.INIT_RANDOM)
             pch.append(ch)
         pb = g.Batch(pch)
-        tune(pb, args.tuning)
+        tune(pb, args.pair_tuning)
         pppt, plan = pb.tuning()
         pb.step(1)
         torch.cuda.synchronize()
@@ -801,18 +804,33 @@ def main():
         e1.record(pb.stream)
         torch.cuda.synchronize()
         dt = e0.elapsed_time(e1) / 1e3
-        pbytes, _ = pch[0].step_bytes()
+        pbytes, psteps = pch[0].step_bytes()
+        # algorithmic bytes of one proposal's step launches: one step per launch
+        # reads the two stored values and the spinor of every site and writes one
+        # value (40 B/site FP32); the two-step shape (3) runs step 1 so, then per
+        # launch reads both slots and the spinor once and writes both slots
+        # (48 B/site for two steps: 1.2 x one step's bytes)
+        if pppt == 3:
+            prop_bytes = NCHAIN * pbytes * (1 + 1.2 * (psteps // 2))
+            kern = "k_step_ov2<float>"
+            rnd = "step 1, then two Chebyshev steps of all chains per k_step_ov2 launch"
+        else:
+            prop_bytes = NCHAIN * pbytes * psteps
+            kern = "k_step_ov<float>"
+            rnd = "one Chebyshev step of all chains"
+        achieved = prop_bytes * nps / (ms_tot / 1e3) / 1e9
         pavg = ms_tot / 1e3 / max(nl_tot, 1)
         out["pair_form"] = {
             "mc_spin_updates_per_s": nps * NCHAIN / dt,
             "svu_per_s": nps * NCHAIN * N * 2 * (M // 2) / dt,
             "ms_per_step": 1e3 * dt / nps, "pairs_per_thread": pppt, "lanes": plan,
-            "roofline": {"bound": "hbm", "achieved": NCHAIN * pbytes / pavg / 1e9,
+            "roofline": {"bound": "hbm", "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": NCHAIN * pbytes / pavg / 1e9 / HBM_PEAK_GBS,
-                         "traffic": traffic_bytes("k_step_ov<float>", pppt),
-                         "kernel": "k_step_ov<float>", "lanes": plan,
-                         "avg_round_us": pavg * 1e6, "bytes_per_round": NCHAIN * pbytes}}
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": traffic_bytes(kern, pppt),
+                         "kernel": kern, "lanes": plan, "round": rnd,
+                         "avg_round_us": pavg * 1e6,
+                         "bytes_per_round": prop_bytes * nps / max(nl_tot, 1)}}
         pb.close()
         del pch
 

@@ -289,9 +289,18 @@ gfmc_status gfmc_batch_use_graph(gfmc_batch* batch, int32_t enable);
  * workgroup per chain that runs all M/2 steps in a single launch (every
  * chain must fit: 128 B/site FP32, 232 B/site FP64 within 140 KB, i.e. up
  * to 10^3 FP32 / 8^3 FP64, 7 site start vectors, recomputed hoppings).
- * Results do not depend on the shape beyond the order of the moment partial
- * sums.  Single chains, and new batches whose chains all fit, use shape 0;
- * otherwise shape 1. */
+ * Shape 3 (pair form only, GFMC_VECTORS_OV or GFMC_VECTORS_MIXED, with
+ * recomputed hoppings): step 1 as shape 1, then two Chebyshev steps per
+ * launch, each block advancing a tile of full x-rows staged in LDS with two
+ * halo rows in y and z (Section 2.2's three series need only the pair of
+ * vectors, so a tile of both slots and the spinors fits); needs L >= 8
+ * divisible by the tile rows (8, 4 or 2, FP32 up to L = 64 and FP64 up to
+ * L = 32 with the 144 KB tile), lock-step proposals (EINVAL in the
+ * step-granular schedule) and uses one step lane.  Vector values agree bit
+ * for bit with shape 1.  Results do not depend on the shape beyond the order
+ * of the moment partial sums.  Single chains, and new batches whose chains
+ * all fit, use shape 0; otherwise shape 1.  EINVAL when a chain does not fit
+ * the shape asked for. */
 gfmc_status gfmc_batch_set_tuning(gfmc_batch* batch, int32_t pairs_per_thread);
 
 /* Step lanes: 1 (every Chebyshev step one launch on the batch stream) to 4
@@ -339,14 +348,16 @@ gfmc_status gfmc_batch_set_nontemporal(gfmc_batch* batch, int32_t on);
 gfmc_status gfmc_batch_get_form(gfmc_batch* batch, int32_t* resident, int32_t* persistent,
                                 int32_t* step_granular, int32_t* nontemporal);
 
-/* Launch shape (0, 1, 2) and number of step lanes in effect. */
+/* Launch shape (0 to 3) and number of step lanes in effect. */
 gfmc_status gfmc_batch_get_tuning(gfmc_batch* batch, int32_t* pairs_per_thread, int32_t* lanes);
 
-/* Time each step-kernel launch shape (with and without non-temporal access)
+/* Time each step-kernel launch shape the batch's chains fit (shape 3 only
+ * in the lock-step schedule; non-temporal access for the 7-vector kernel)
  * with one to four lanes over
  * `trial_steps` Chebyshev steps on the batch's current spins (no change of
  * chain state), keep the fastest, and remember it for later batches of the
- * same shape (precision, number of chains, L and M of each chain).  chosen
+ * same shape (precision, start vectors, hoppings, schedule, number of
+ * chains, L and M of each chain).  chosen
  * (the shape) may be NULL; gfmc_batch_get_tuning reports the lanes. */
 gfmc_status gfmc_batch_autotune(gfmc_batch* batch, int32_t trial_steps, int32_t* chosen);
 

@@ -143,9 +143,20 @@ void fill_desc(gfmc_chain* c) {
   D.ctl = (Ctl*)(c->ws + c->l.ctl);
 }
 
+// Blocks of a one-step launch with ppt site pairs per thread (the two-step
+// pair shape runs its first step, and sizes its partial sums, as shape 1).
 static int blocks_of(const Derived& d, int ppt) {
-  const int per = kStepThreads * (ppt < 1 ? 1 : ppt);
+  const int per = kStepThreads * (ppt < 1 ? 1 : ppt > 2 ? 1 : ppt);
   return (d.half + per - 1) / per;
+}
+
+// A chain the two-step pair kernel can take: pair form, hoppings recomputed,
+// a tile shape for its L, and no more tiles than one-step blocks (the tiles
+// fill the first partial-sum slots of a step, zeros the rest).
+static bool tile2_fits(const Derived& d) {
+  int ty = 0, tz = 0;
+  if (!d.ov || d.hops || d.L < 8 || !tile_dims(d.L, d.fp32, &ty, &tz)) return false;
+  return (d.L / ty) * (d.L / tz) <= blocks_of(d, 1);
 }
 
 // The LDS-resident kernel holds, per site, the 7 bipartite vector slots, the
@@ -213,6 +224,12 @@ gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   for (size_t i = 0; i < sorted.size(); ++i) {
     ds[i] = sorted[i]->desc;
     ds[i].nblk = P.persist > 0 ? P.persist : P.resident ? 1 : blocks_of(sorted[i]->d, P.ppt);
+    if (P.ppt == kShapeTile2) {
+      int ty = 0, tz = 0;
+      tile_dims(sorted[i]->d.L, sorted[i]->d.fp32, &ty, &tz);
+      ds[i].tile_y = ty;
+      ds[i].tile_z = tz;
+    }
   }
   HIPCHK(hipMemcpyAsync(P.d_desc, ds.data(), ds.size() * sizeof(Desc), hipMemcpyHostToDevice,
                         P.stream));
@@ -222,6 +239,9 @@ gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
     for (int l = 0; l < P.lanes_on; ++l)
       HIPCHK(hipMemcpyAsync(P.d_lane_blkoff[l], P.lane_blkoff[l].data(),
                             P.lane_blkoff[l].size() * sizeof(int), hipMemcpyHostToDevice, P.stream));
+  if (P.ppt == kShapeTile2)
+    HIPCHK(hipMemcpyAsync(P.d_tileoff, P.tileoff.data(), P.tileoff.size() * sizeof(int),
+                          hipMemcpyHostToDevice, P.stream));
   if (P.d_coh_blkoff)
     for (auto& C : P.coh)
       HIPCHK(hipMemcpyAsync(C.d_blkoff, C.blkoff.data(), C.blkoff.size() * sizeof(int),
@@ -258,10 +278,24 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
     P.kmax = std::max(P.kmax, sorted[i]->d.K);
     P.nmax = std::max(P.nmax, sorted[i]->d.N);
   }
+  // two-step pair shape: tiles per chain and the largest tile's LDS
+  P.tileoff.assign(P.n + 1, 0);
+  P.tile_lds = 0;
+  if (P.ppt == kShapeTile2)
+    for (int i = 0; i < P.n; ++i) {
+      const Derived& d = sorted[i]->d;
+      int ty = 0, tz = 0;
+      tile_dims(d.L, d.fp32, &ty, &tz);
+      P.tileoff[i + 1] = P.tileoff[i] + (d.L / ty) * (d.L / tz);
+      P.tile_lds = std::max(P.tile_lds, (size_t)(ty + 4) * (tz + 4) * d.L * (d.fp32 ? 32 : 64));
+    }
   // lanes: k contiguous ranges, each closed once the work (steps x blocks)
-  // reaches its share, every lane at least one chain
+  // reaches its share, every lane at least one chain (one range for the
+  // two-step pair shape: its tiles fill the chip by themselves)
   int k = std::min(P.lanes, P.n);
-  if (k < 2 || P.resident || !P.d_lane_blkoff[0] || !P.lane_stream[k - 1]) k = 1;
+  if (k < 2 || P.resident || P.ppt == kShapeTile2 || !P.d_lane_blkoff[0] ||
+      !P.lane_stream[k - 1])
+    k = 1;
   P.lanes_on = k;
   std::vector<double> work(P.n);
   double tot = 0;
@@ -311,9 +345,33 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   }
 }
 
+// Step launches (rounds) of one proposal: one for the resident kernel, step 1
+// and one per two steps for the two-step pair shape, else one per step.
+static int64_t step_rounds(const Plan& P) {
+  return P.resident ? 1 : P.ppt == kShapeTile2 ? 1 + P.smax / 2 : P.smax;
+}
+
 // The Chebyshev steps s_first..s_last of every chain still stepping: one
 // launch per step on the plan stream, or per lane on the two lane streams.
 gfmc_status enqueue_steps(Plan& P, int s_first, int s_last) {
+  if (P.ppt == kShapeTile2) {
+    // step 1 as shape 1, then steps (s, s + 1) per launch over the chains
+    // with at least s steps (a chain whose last step is s takes it alone)
+    int nact = P.n;
+    int s = s_first;
+    if (s == 1) {
+      HIPCHK(launch_step(P.fp32, P.ov, P.hops, 1, P.d_desc, P.d_blkoff, P.n, P.blkoff[P.n], 1,
+                         P.stream));
+      ++s;
+    }
+    for (; s <= s_last; s += 2) {
+      while (nact > 0 && P.S[nact - 1] < s) --nact;
+      if (nact == 0) break;
+      HIPCHK(launch_step_ov2(P.fp32, P.d_desc, P.d_tileoff, nact, P.tileoff[nact], s, P.tile_lds,
+                             P.stream));
+    }
+    return GFMC_OK;
+  }
   if (P.lanes_on < 2) {
     int nact = P.n;
     for (int s = s_first; s <= s_last; ++s) {
@@ -388,7 +446,7 @@ gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* 
     HIPCHK(hipEventRecord(P.ev[P.ev_used + 1], P.stream));
     P.ev_used += 2;
   }
-  if (P.timing) P.step_launches += P.resident ? 1 : P.smax;
+  if (P.timing) P.step_launches += step_rounds(P);
   HIPCHK(launch_moments(P.ov, P.d_desc, P.n, P.smax, P.stream));
   if (with_recon) HIPCHK(launch_recon(P.fp32, P.d_desc, P.n, P.kmax, d_force, d_rec, P.stream));
   return GFMC_OK;
@@ -512,7 +570,7 @@ static gfmc_status timing_end(Plan& P) {
   }
   const int timed = P.ev_used / 2;
   // scale the step launch count to the timed proposals
-  if (timed > 0 && P.step_launches > 0) P.step_launches = (int64_t)timed * (P.resident ? 1 : P.smax);
+  if (timed > 0 && P.step_launches > 0) P.step_launches = (int64_t)timed * step_rounds(P);
   P.step_ms = tot;
   P.timing = false;
   return GFMC_OK;
@@ -986,7 +1044,7 @@ gfmc_status gfmc_chain_step_bytes(gfmc_chain* c, double* bytes_per_step, int32_t
 static size_t batch_bytes(int n) {
   return align256((size_t)n * sizeof(Desc)) + align256((size_t)(n + 1) * sizeof(int)) +
          align256((size_t)(n + kMaxLanes) * sizeof(int)) + align256((size_t)n * sizeof(int)) +
-         align256((size_t)(2 * n + 8) * sizeof(int)) +
+         align256((size_t)(2 * n + 8) * sizeof(int)) + align256((size_t)(n + 1) * sizeof(int)) +
          align256((size_t)kRecCap * n * sizeof(int32_t)) +
          align256((size_t)kRecCap * n * sizeof(gfmc_step_record)) +
          align256((size_t)kMagCap * n * sizeof(double));
@@ -1036,6 +1094,7 @@ gfmc_status gfmc_batch_create(gfmc_chain* const* chains, int32_t n, void* ws, si
   w += align256((size_t)(n + kMaxLanes) * sizeof(int));
   P.d_act_end = (int*)w; w += align256((size_t)n * sizeof(int));
   P.d_coh_blkoff = (int*)w; w += align256((size_t)(2 * n + 8) * sizeof(int));
+  P.d_tileoff = (int*)w; w += align256((size_t)(n + 1) * sizeof(int));
   P.d_force = (int32_t*)w; w += align256((size_t)kRecCap * n * sizeof(int32_t));
   P.d_rec = (gfmc_step_record*)w; w += align256((size_t)kRecCap * n * sizeof(gfmc_step_record));
   P.d_mag = (double*)w;
@@ -1147,7 +1206,7 @@ gfmc_status gfmc_batch_step(gfmc_batch* b, int32_t nprop, const int32_t* force,
     P.ev_used = 2;
     CHK(timing_end(P));
     // whole proposals were timed: report the per-proposal time spread over the steps
-    P.step_launches = (int64_t)nprop * P.smax;
+    P.step_launches = (int64_t)nprop * step_rounds(P);
     return GFMC_OK;
   }
   CHK(timing_begin(P, nprop));
@@ -1205,13 +1264,22 @@ static void drop_graph(Plan& P) {
 
 gfmc_status gfmc_batch_set_tuning(gfmc_batch* b, int32_t pairs_per_thread) {
   if (!b) return fail(GFMC_EINVAL, "batch is NULL");
-  if (pairs_per_thread < 0 || pairs_per_thread > 2)
-    return fail(GFMC_EINVAL, "pairs_per_thread must be 0, 1 or 2");
+  if (pairs_per_thread < 0 || pairs_per_thread > kShapeTile2)
+    return fail(GFMC_EINVAL, "pairs_per_thread must be 0, 1, 2 or 3");
   Plan& P = b->plan;
   if (pairs_per_thread == 0)
     for (auto* c : b->sorted)
       if (!resident_fits(c->d))
         return fail(GFMC_EINVAL, "shape 0 needs every chain to fit in LDS");
+  if (pairs_per_thread == kShapeTile2) {
+    for (auto* c : b->sorted)
+      if (!tile2_fits(c->d))
+        return fail(GFMC_EINVAL, "shape 3 needs pair-form chains with recomputed hoppings "
+                                 "and L >= 8 divisible by its tile rows");
+    if (P.cont) return fail(GFMC_EINVAL, "shape 3 runs lock-step proposals only");
+    if (!P.d_tileoff) return fail(GFMC_ESTATE, "plan has no tile table");
+    HIPCHK(prepare_step_ov2());
+  }
   HIPCHK(hipStreamSynchronize(P.stream));
   P.ppt = pairs_per_thread;
   plan_shape(P, b->sorted);
@@ -1244,6 +1312,8 @@ gfmc_status gfmc_batch_set_schedule(gfmc_batch* b, int32_t step_granular) {
   if (step_granular != 0 && step_granular != 1)
     return fail(GFMC_EINVAL, "step_granular must be 0 or 1");
   Plan& P = b->plan;
+  if (step_granular && P.ppt == kShapeTile2)
+    return fail(GFMC_EINVAL, "shape 3 runs lock-step proposals only: set another shape first");
   HIPCHK(hipStreamSynchronize(P.stream));
   P.cont = step_granular;
   const bool g = b->use_graph;
@@ -1293,7 +1363,7 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   if (!b) return fail(GFMC_EINVAL, "batch is NULL");
   if (trial_steps < 1) return fail(GFMC_EINVAL, "trial_steps must be >= 1");
   Plan& P = b->plan;
-  std::vector<int> key = {P.fp32, P.ov, P.hops, P.n};
+  std::vector<int> key = {P.fp32, P.ov, P.hops, P.cont, P.n};
   for (auto* c : b->sorted) { key.push_back(c->d.L); key.push_back(c->d.M); }
   std::pair<int, int> hit(-1, -1);
   {
@@ -1321,14 +1391,18 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   HIPCHK(hipEventCreate(&ev.a));
   HIPCHK(hipEventCreate(&ev.b));
   hipEvent_t e0 = ev.a, e1 = ev.b;
-  bool all_res = true;
-  for (auto* c : b->sorted) all_res = all_res && resident_fits(c->d);
-  for (int ppt : {0, 1, 2})
+  bool all_res = true, all_tile2 = !P.cont;
+  for (auto* c : b->sorted) {
+    all_res = all_res && resident_fits(c->d);
+    all_tile2 = all_tile2 && tile2_fits(c->d);
+  }
+  for (int ppt : {0, 1, 2, kShapeTile2})
    for (int nt = 0; nt <= 1; ++nt) {
     if (ppt == 0 && !all_res) continue;
+    if (ppt == kShapeTile2 && !all_tile2) continue;
     if (nt && (ppt == 0 || P.ov)) continue;   // the 7-vector multi-block kernel only
     for (int lanes = 1; lanes <= kMaxLanes; ++lanes) {
-      if (lanes >= 2 && (ppt == 0 || P.n < lanes)) continue;
+      if (lanes >= 2 && (ppt == 0 || ppt == kShapeTile2 || P.n < lanes)) continue;
       CHK(gfmc_batch_set_lanes(b, lanes));
       CHK(gfmc_batch_set_tuning(b, ppt));
       CHK(gfmc_batch_set_nontemporal(b, nt));

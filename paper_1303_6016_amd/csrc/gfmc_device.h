@@ -19,6 +19,10 @@ constexpr int kMaxK = 8192;         // energy nodes held in LDS by the transform
 // dynamic LDS of the single-workgroup (LDS-resident) Chebyshev kernel; the
 // kernel's static LDS (staging and Gram sums) is 16.9 KB of the 160 KB
 constexpr int kResidentLds = 140 * 1024;
+// two-step pair-form kernel: threads per block (one tile) and the most
+// dynamic LDS a tile may take
+constexpr int kTileThreads = 1024;
+constexpr int kTileLds = 144 * 1024;
 
 // Complex value and per-site spinor in the recursion precision T.
 template <typename T>
@@ -54,6 +58,7 @@ struct Ctl {
 struct Desc {
   int32_t L, N, half, M, S, K, nblk, kernel, proposal, log2K;
   int32_t vectors, hops;      // GFMC_VECTORS_*, GFMC_HOP_*
+  int32_t tile_y, tile_z;    // two-step pair kernel: rows per tile in y and z
   double t, beta, mu, a, cone, lambda;
   uint64_t seed, chain_id;
   double* theta;            // [N]
@@ -71,6 +76,25 @@ struct Desc {
                             // g[M], pre[K][2], tw[K/2][2], sinth[K], wt[K]
   Ctl* ctl;
 };
+
+// Tiles of the two-step pair-form kernel: ty x tz full x-rows of one chain,
+// staged in LDS with two halo rows on each side in y and z (o-slot, v-slot
+// and spinor of every site: 32 B in FP32, 64 B in FP64).  The largest of
+// 8x8, 8x4, 4x4, 4x2, 2x2 that divides L and fits kTileLds; false if none.
+__host__ __device__ inline bool tile_dims(int L, int fp32, int* ty, int* tz) {
+  const int bytes = fp32 ? 32 : 64;
+  const int cand[5][2] = {{8, 8}, {8, 4}, {4, 4}, {4, 2}, {2, 2}};
+  for (int i = 0; i < 5; ++i) {
+    const int y = cand[i][0], z = cand[i][1];
+    if (L % y != 0 || L % z != 0) continue;
+    if ((long long)(y + 4) * (z + 4) * L * bytes <= kTileLds) {
+      *ty = y;
+      *tz = z;
+      return true;
+    }
+  }
+  return false;
+}
 
 // Site decomposition of the bipartite layout: site (x,y,z) has parity
 // (x+y+z)&1 and half-row index (x>>1) + (L/2)(y + L z); the two sites of a

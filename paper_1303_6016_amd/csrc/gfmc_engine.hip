@@ -3,8 +3,11 @@
 //
 // A host worker thread owns the device streams.  Running chains are grouped
 // by precision x start-vector form x hopping mode x kernel shape (LDS-resident
-// or multi-block); each group has a launch plan and a stream of its own, so
-// groups run side by side.  Each iteration the worker (1) admits queued
+// or multi-block); each group has a launch plan, and the groups with members
+// are dealt over two streams, created when first needed, so that two run side
+// by side.  With its own stream the engine uses at most three, which leaves
+// the caller's stream a hardware queue of its own among the four a process
+// gets by default.  Each iteration the worker (1) admits queued
 // requests in arrival order while a slot and a large enough block of the HBM
 // budget are free, (2) retires cancelled requests, (3) re-uploads the plans
 // when the set of running chains changed, (4) advances every group by a
@@ -96,9 +99,11 @@ struct Request {
 // re-uploaded only when its members change.  Keeping the shapes apart lets
 // small chains run one launch per proposal while large ones run M/2.
 constexpr int kGroups = 16;
+constexpr int kStreams = 2;              // group streams (plus the engine's own)
 constexpr int kMaxReps = 64;             // proposals per group and iteration
 struct Group {
   Plan plan;
+  int slot = -1;                      // group stream in use (-1: none yet)
   std::vector<gfmc_chain*> members;   // plan order (most Chebyshev steps first)
   std::vector<Request*> reqs;         // the members' requests
   double cost = 0;                    // estimated device time of one proposal (us)
@@ -145,7 +150,7 @@ struct gfmc_engine {
   char* base = nullptr;
   char* plan_mem = nullptr;
   hipStream_t stream = nullptr;         // admissions, |m|, read-backs
-  hipStream_t gstream[kGroups] = {};    // one per group: groups run side by side
+  hipStream_t gstream[kStreams] = {};   // dealt over the groups with members
   Arena arena;
   Group groups[kGroups];
   bool members_changed = true;
@@ -199,7 +204,7 @@ static gfmc_result make_result(const Request* r, gfmc_status st, int64_t accepte
 // engine's own stream).
 static hipError_t sync_all(gfmc_engine* E) {
   hipError_t e = hipSuccess;
-  for (int g = 0; g < kGroups; ++g)
+  for (int g = 0; g < kStreams; ++g)
     if (E->gstream[g]) {
       const hipError_t eg = hipStreamSynchronize(E->gstream[g]);
       if (e == hipSuccess) e = eg;
@@ -237,6 +242,24 @@ static void retire(gfmc_engine* E, Request* r, gfmc_status st) {
 static gfmc_status refresh_groups(gfmc_engine* E) {
   for (int g = 0; g < kGroups; ++g) E->groups[g].reqs.clear();
   for (auto* r : E->running) E->groups[group_of(r->d)].reqs.push_back(r);
+  // deal the groups with members over the streams in group order; a group
+  // that changes stream may still have work queued on its old one that reads
+  // its plan tables, so all streams drain first
+  int k = 0;
+  bool moved = false;
+  int slot[kGroups];
+  for (int g = 0; g < kGroups; ++g) {
+    slot[g] = E->groups[g].reqs.empty() ? -1 : (k++ % kStreams);
+    moved |= slot[g] >= 0 && E->groups[g].slot >= 0 && slot[g] != E->groups[g].slot;
+  }
+  if (moved && sync_all(E) != hipSuccess) return gfmc_fail(GFMC_EDEVICE, "stream sync failed");
+  for (int g = 0; g < kGroups; ++g) {
+    if (slot[g] < 0) continue;
+    if (!E->gstream[slot[g]])
+      HIPCHK(hipStreamCreateWithFlags(&E->gstream[slot[g]], hipStreamNonBlocking));
+    E->groups[g].slot = slot[g];
+    E->groups[g].plan.stream = E->gstream[slot[g]];
+  }
   for (int g = 0; g < kGroups; ++g) {
     Group& G = E->groups[g];
     // plan order: most Chebyshev steps first (requests and chains alike)
@@ -442,11 +465,7 @@ gfmc_status gfmc_engine_create(int device, size_t budget, int32_t max_slots, gfm
   }
   bool ok = hipMalloc(&E->plan_mem, kGroups * plan_bytes(max_slots)) == hipSuccess &&
             hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking) == hipSuccess;
-  for (int g = 0; ok && g < kGroups; ++g)
-    ok = hipStreamCreateWithFlags(&E->gstream[g], hipStreamNonBlocking) == hipSuccess;
   if (!ok) {
-    for (int g = 0; g < kGroups; ++g)
-      if (E->gstream[g]) (void)hipStreamDestroy(E->gstream[g]);
     if (E->stream) (void)hipStreamDestroy(E->stream);
     (void)hipFree(E->base);
     if (E->plan_mem) (void)hipFree(E->plan_mem);
@@ -458,7 +477,7 @@ gfmc_status gfmc_engine_create(int device, size_t budget, int32_t max_slots, gfm
   for (int g = 0; g < kGroups; ++g) {
     Plan& P = E->groups[g].plan;
     char* w = E->plan_mem + g * pb;
-    P.stream = E->gstream[g];
+    P.stream = nullptr;   // a group stream is dealt when the group gains members
     P.fp32 = g & 1;
     P.ov = (g >> 1) & 1;
     P.hops = (g >> 2) & 1;
@@ -592,7 +611,8 @@ gfmc_status gfmc_engine_destroy(gfmc_engine* E) {
   if (E->worker.joinable()) E->worker.join();
   (void)hipSetDevice(E->device);
   (void)sync_all(E);
-  for (int g = 0; g < kGroups; ++g) (void)hipStreamDestroy(E->gstream[g]);
+  for (int g = 0; g < kStreams; ++g)
+    if (E->gstream[g]) (void)hipStreamDestroy(E->gstream[g]);
   (void)hipStreamDestroy(E->stream);
   (void)hipFree(E->plan_mem);
   (void)hipFree(E->base);

@@ -18,6 +18,9 @@ hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
 hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const int* blkoff,
                        int nact, int blocks, int s, hipStream_t st, const int* act_end = nullptr,
                        int nt = 0);
+hipError_t prepare_step_ov2();
+hipError_t launch_step_ov2(int fp32, const Desc* d, const int* tileoff, int nact, int tiles, int s,
+                           size_t lds, hipStream_t st);
 hipError_t launch_moments(int ov, const Desc* d, int n, int smax, hipStream_t st);
 hipError_t launch_recon(int fp32, const Desc* d, int n, int kmax, const int32_t* force,
                         gfmc_step_record* recs, hipStream_t st);
@@ -55,6 +58,7 @@ gfmc_status gfmc_fail(gfmc_status s, const std::string& msg);
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kMaxLanes = 4;   // step lanes (streams) of a batch
+constexpr int kShapeTile2 = 3;  // launch shape: pair form, two Chebyshev steps per launch
 
 // ------------------------------------------------------- chain layout ----
 struct Derived {
@@ -73,7 +77,12 @@ struct Plan {
   int n = 0, fp32 = 0, smax = 0, kmax = 0, nmax = 0;
   int nt = 0;                          // non-temporal own loads and stores in the steps
   int ppt = 1;                         // site pairs per thread of the step kernel;
-                                       // 0: one LDS-resident workgroup per chain
+                                       // 0: one LDS-resident workgroup per chain;
+                                       // kShapeTile2: pair form, two steps per launch
+                                       // (step 1 and the partial sums as with 1)
+  std::vector<int> tileoff;            // kShapeTile2: tile offsets per sorted chain (n + 1)
+  int* d_tileoff = nullptr;            // ... device copy (batches only)
+  size_t tile_lds = 0;                 // kShapeTile2: dynamic LDS of the launches
   int resident = 0;                    // shape 0 in effect (every chain fits in LDS)
   int persist = 0;                     // > 0: a lone chain's steps in one launch of this
                                        // many working blocks on one die (persistent kernel);

@@ -122,6 +122,18 @@ __device__ inline void hop_spinor(const spn<T>& a, const spn<T>& b, const double
   im = (T)(sc * (ar * ci - ai * cr + br * di - bi * dr));
 }
 
+// (ar, ai) += (hr + i hi) a with the four products fused in a fixed order, so
+// that every form of the step (one step or two per launch, the LDS-resident
+// and the persistent kernels, whatever the compiler makes of the code around
+// it) forms every vector value bit for bit alike.
+template <typename T>
+__device__ inline void cmac(T hr, T hi, const cpx<T>& a, T& ar, T& ai) {
+  ar = fma(hr, a.x, ar);
+  ar = fma(-hi, a.y, ar);
+  ai = fma(hr, a.y, ai);
+  ai = fma(hi, a.x, ai);
+}
+
 // Block b of a grid of nb blocks runs on XCD b % 8; give each XCD a
 // contiguous range of logical blocks so that lattice planes that neighbour in
 // z are processed under the same L2.
@@ -278,6 +290,23 @@ __device__ inline void st_nt(GLOBAL cpx<double>* p, const cpx<double>& c) {
   d2v v = {c.x, c.y};
   __builtin_nontemporal_store(v, (GLOBAL d2v*)p);
 }
+// Device-coherent forms for the persistent kernel: relaxed device-scope
+// atomic loads of 8-byte words, which skip this compute unit's L1 and are
+// served by the L2, so values other blocks stored in the previous step are
+// read without invalidating any cache.
+__device__ inline uint64_t ld_dev8(const GLOBAL void* p) {
+  return __hip_atomic_load((const GLOBAL uint64_t*)p, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline cpx<float> ld_coh(const GLOBAL cpx<float>* p) {
+  const f2v v = __builtin_bit_cast(f2v, ld_dev8(p));
+  return {v.x, v.y};
+}
+__device__ inline cpx<double> ld_coh(const GLOBAL cpx<double>* p) {
+  const GLOBAL uint64_t* q = (const GLOBAL uint64_t*)p;
+  return {__builtin_bit_cast(double, ld_dev8(q)), __builtin_bit_cast(double, ld_dev8(q + 1))};
+}
+
 // Global storage of six values per site (the n-slots, the stored hopping
 // rows): planes of 16-byte items, item i of plane q at q * stride + i, so a
 // wave's access to one plane is one contiguous run (a 48- or 96-byte record
@@ -306,6 +335,18 @@ struct Planes<float> {
       f4v v = {r.v[2 * q].x, r.v[2 * q].y, r.v[2 * q + 1].x, r.v[2 * q + 1].y};
       p[q * stride + i] = v;
     }
+  }
+  __device__ six<float> ld_coh(size_t i) const {
+    six<float> r;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const GLOBAL uint64_t* w = (const GLOBAL uint64_t*)(p + q * stride + i);
+      const f2v a = __builtin_bit_cast(f2v, ld_dev8(w));
+      const f2v b = __builtin_bit_cast(f2v, ld_dev8(w + 1));
+      r.v[2 * q] = {a.x, a.y};
+      r.v[2 * q + 1] = {b.x, b.y};
+    }
+    return r;
   }
   __device__ six<float> ld_nt(size_t i) const {
     six<float> r;
@@ -344,6 +385,15 @@ struct Planes<double> {
       d2v v = {r.v[q].x, r.v[q].y};
       p[q * stride + i] = v;
     }
+  }
+  __device__ six<double> ld_coh(size_t i) const {
+    six<double> r;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const GLOBAL uint64_t* w = (const GLOBAL uint64_t*)(p + q * stride + i);
+      r.v[q] = {__builtin_bit_cast(double, ld_dev8(w)), __builtin_bit_cast(double, ld_dev8(w + 1))};
+    }
+    return r;
   }
   __device__ six<double> ld_nt(size_t i) const {
     six<double> r;
@@ -450,7 +500,7 @@ __device__ inline int chain_step(int s, const int* __restrict__ act_end, int c, 
 // directions) must have been issued.
 #define STEP_LOADS_ISSUED() __builtin_amdgcn_sched_barrier(0)
 
-template <typename T, bool FIRST, int PPT, bool HOPS, bool NT>
+template <typename T, bool FIRST, int PPT, bool HOPS, bool NT, bool COH = false>
 __device__ __forceinline__ void step_block(const Desc& D, const int lb, const int s,
                                            double (*xs)[16][17], double (*gsum)[256]) {
   const int L = D.L, hx = L >> 1, half = D.half;
@@ -503,7 +553,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         if (FIRST) { an[d].x = (nh[d] == o_half) ? (T)1 : (T)0; an[d].y = 0; }
-        else an[d] = ld(vo + (size_t)pn * half + nh[d]);
+        else an[d] = COH ? ld_coh(vo + (size_t)pn * half + nh[d]) : ld(vo + (size_t)pn * half + nh[d]);
       }
       if (!FIRST) pr = NT ? ld_nt(vo + (size_t)po * half + h) : ld(vo + (size_t)po * half + h);
       STEP_LOADS_ISSUED();
@@ -517,8 +567,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
         } else {
           hop_spinor(si, sj[d], hsc, hr, hi_);
         }
-        ar += hr * an[d].x - hi_ * an[d].y;
-        ai += hr * an[d].y + hi_ * an[d].x;
+        cmac(hr, hi_, an[d], ar, ai);
       }
       cpx<T> ao;
       ao.x = two * ar - pr.x;
@@ -560,7 +609,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
               an[g].v[e].y = 0;
             }
           } else {
-            an[g] = vn.ld((size_t)po * half + nh[g]);
+            an[g] = COH ? vn.ld_coh((size_t)po * half + nh[g]) : vn.ld((size_t)po * half + nh[g]);
           }
         }
         if (d0 + kGroup >= 6 && !FIRST) {   // the site's own values ride with the last group
@@ -580,8 +629,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
           }
 #pragma unroll
           for (int e = 0; e < 6; ++e) {
-            accr[e] += hr * an[g].v[e].x - hi_ * an[g].v[e].y;
-            acci[e] += hr * an[g].v[e].y + hi_ * an[g].v[e].x;
+            cmac(hr, hi_, an[g].v[e], accr[e], acci[e]);
           }
         }
       }
@@ -678,11 +726,18 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
 // microseconds each.  Blocks are dealt to the eight compute dies (XCDs) in
 // turn; the first block to start claims its die, and the first nb blocks on
 // that die take the work (the others return), so every block of the run
-// shares one L2 and the step barrier's counter lives there.  Between steps
-// each block releases its stores and acquires the others' at device scope
-// (the L2 write-back and the L1 and L2 invalidation the memory model
-// prescribes for visibility across compute units); one thread per block
-// counts in at the L2 and polls it past the L1.  Waits are bounded: on a
+// shares one L2 and the step barrier's counter lives there.  That L2 is the
+// point of coherence for all of them, so a step's stores are visible to the
+// other blocks once they have completed (the vector L1 writes through): each
+// wave waits for its stores, one thread per block counts in at the L2 and
+// polls it, and the next step reads its neighbours' values (stored by other
+// blocks) with device-scope loads, which skip the compute unit's L1 and are
+// served by the L2; the site's own values, stored by the same thread, and
+// the spinors, fixed during a proposal, load as usual.  No cache is written
+// back or invalidated: the device-scope fences that would (the L2 write-back
+// for other dies, the L1 and L2 invalidation) cost more per step than a
+// kernel launch, for visibility this run never needs.  Waits are
+// bounded: on a
 // timeout the run sets an error flag, every block returns, and the
 // reconstruction leaves the chain unchanged.
 constexpr int kBarrierSpins = 1 << 21;
@@ -692,15 +747,18 @@ __device__ inline unsigned xcd_id() {
 }
 
 __device__ inline bool die_barrier(unsigned* count, unsigned target, unsigned* err, int* ok_sh) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this wave's stores are visible
+  __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached the L2
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     for (int i = 0;
          __hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++i) {
+      // another block's time-out is checked every 64th poll (one load per poll)
       if (i >= kBarrierSpins ||
-          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
+          ((i & 63) == 63 &&
+           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u)) {
         __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         ok = 0;
         break;
@@ -710,7 +768,7 @@ __device__ inline bool die_barrier(unsigned* count, unsigned target, unsigned* e
     *ok_sh = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // no stale lines of others' stores
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   return *ok_sh != 0;
 }
 
@@ -735,8 +793,8 @@ __global__ __launch_bounds__(kStepThreads) void k_persist(const Desc* __restrict
   const int lb = tk;
   if (lb >= nb) return;
   for (int s = 1; s <= D.S; ++s) {
-    if (s == 1) step_block<T, true, 1, false, false>(D, lb, 1, xs, gsum);
-    else step_block<T, false, 1, false, false>(D, lb, s, xs, gsum);
+    if (s == 1) step_block<T, true, 1, false, false, true>(D, lb, 1, xs, gsum);
+    else step_block<T, false, 1, false, false, true>(D, lb, s, xs, gsum);
     if (s == D.S) break;
     if (!die_barrier(&bar[2], (unsigned)nb * (unsigned)s, &bar[3], &ok_sh)) return;
   }
@@ -850,8 +908,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const Desc* __restrict
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
-        ar += hv[d].x * an[d].x - hv[d].y * an[d].y;
-        ai += hv[d].x * an[d].y + hv[d].y * an[d].x;
+        cmac(hv[d].x, hv[d].y, an[d], ar, ai);
       }
       *dst = cpx<T>{two * ar - pr.x, two * ai - pr.y};
     }
@@ -1008,8 +1065,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
       for (int d = 0; d < 6; ++d) {
         T hr, hi_;
         hop_spinor(si, sj[d], hsc, hr, hi_);
-        ar += hr * an[d].x - hi_ * an[d].y;
-        ai += hr * an[d].y + hi_ * an[d].x;
+        cmac(hr, hi_, an[d], ar, ai);
       }
       ao.x = two * ar - pr.x;
       ao.y = two * ai - pr.y;
@@ -1037,8 +1093,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
       for (int d = 0; d < 6; ++d) {
         T hr, hi_;
         hop_spinor(si, sj[d], hsc, hr, hi_);
-        ar += hr * an[d].x - hi_ * an[d].y;
-        ai += hr * an[d].y + hi_ * an[d].x;
+        cmac(hr, hi_, an[d], ar, ai);
       }
       av.x = two * ar - pr.x;
       av.y = two * ai - pr.y;
@@ -1068,6 +1123,190 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
   if (threadIdx.x < kNP2) {
     const int t = threadIdx.x;
     D.part[((size_t)(s - 1) * kNP2 + t) * D.nblk + lb] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  }
+}
+
+// ------------------------------------------------ pair form, two steps ---
+// Steps s and s + 1 (s >= 2) of the pair form in one launch.  A block takes
+// a tile of ty x tz full x-rows of one chain.  Step s + 1 on the tile needs
+// step s on the tile and on one row around it, which needs the stored values
+// two rows out, so the block stages the tile with two halo rows on each side
+// in y and z (o-slot, v-slot and spinor of every site) in LDS, advances the
+// inner region by step s and the tile by step s + 1 there, and writes the
+// tile's slots back.  Per site and two steps that is 16 B of slots and 16 B
+// of spinor read and 16 B written (FP32), against 2 x 40 B for two one-step
+// launches; the halo rows are read again by the neighbouring tiles, mostly
+// from the L2 and the last-level cache.  The advance is k_step_ov's, term for
+// term (same neighbour order, hopping and fused products), so every vector
+// value agrees bit for bit with the one-step kernel; the block sums of a step
+// run over the tile's own sites, and the partial-sum slots of a chain beyond
+// its tile count are written as zeros.
+//
+// Tile-local site index: i = (lz * (ty + 4) + ly) * L + x, ly and lz the
+// staged row (halo included), so y neighbours are i +- L and z neighbours
+// i +- (ty + 4) L; x wraps within the row.  The tile origin (y0, z0) is a
+// multiple of the (even) tile size, so a staged site's parity is
+// (x + ly + lz) & 1, its global one.
+template <typename T>
+__device__ inline cpx<T> tile_advance(const cpx<T>* X, const spn<T>* S, int i, int x, int L,
+                                      int zs, double hsc) {
+  const int nb[6] = {(x + 1 == L) ? i + 1 - L : i + 1, (x == 0) ? i + L - 1 : i - 1,
+                     i + L, i - L, i + zs, i - zs};
+  const spn<T> si = S[i];
+  T ar = 0, ai = 0;
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    T hr, hi_;
+    hop_spinor(si, S[nb[d]], hsc, hr, hi_);
+    cmac(hr, hi_, X[nb[d]], ar, ai);
+  }
+  const cpx<T> pr = X[i];
+  return cpx<T>{(T)2 * ar - pr.x, (T)2 * ai - pr.y};
+}
+
+// One step over staged rows ly in [r0, ty + 4 - r0), lz in [r0, tz + 4 - r0)
+// (r0 = 1: the tile and one row around it; r0 = 2: the tile), in place: a
+// site of the parity that carries a^o_s advances its o-slot, a site of the
+// other parity its v-slot, and neither slot is read at that parity during the
+// step.  Sums over the tile's own sites: g[0] = |a^o_s|^2, g[1] = |a^v_s|^2,
+// g[2] + i g[3] = conj(a^o_{s-1}) a^v_s (a^o_{s-1} is the o-slot of the
+// v-site, not advanced in this step).
+template <typename T>
+__device__ inline void tile_step(cpx<T>* LO, cpx<T>* LV, const spn<T>* LS, int L, int ty, int tz,
+                                 int r0, int po, double hsc, double* g) {
+  const int wy = ty + 4, ry = ty + 4 - 2 * r0, n = ry * (tz + 4 - 2 * r0) * L;
+  for (int j = threadIdx.x; j < n; j += kTileThreads) {
+    const int r = j / L, x = j - r * L;
+    const int ly = r0 + r % ry, lz = r0 + r / ry;
+    const int i = (lz * wy + ly) * L + x;
+    const int p = (x + ly + lz) & 1;
+    cpx<T>* X = (p == po) ? LO : LV;
+    const cpx<T> nv = tile_advance(X, LS, i, x, L, wy * L, hsc);
+    X[i] = nv;
+    if (ly >= 2 && ly < ty + 2 && lz >= 2 && lz < tz + 2) {
+      const double nr = nv.x, ni = nv.y;
+      if (p == po) {
+        g[0] += nr * nr + ni * ni;
+      } else {
+        const cpx<T> ap = LO[i];
+        const double apr = ap.x, api = ap.y;
+        g[1] += nr * nr + ni * ni;
+        g[2] += apr * nr + api * ni;
+        g[3] += apr * ni - api * nr;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void k_step_ov2(const Desc* __restrict__ descs,
+                                                           const int* __restrict__ tileoff,
+                                                           int nact, int s) {
+  extern __shared__ __align__(16) unsigned char tile_smem[];
+  __shared__ double red[kTileThreads / 64][8];
+  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+  int c = 0;
+  {   // the chain of this tile, from the compact table of tile offsets
+    int lo = 0, hi = nact - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tileoff[mid] <= gb) lo = mid; else hi = mid - 1;
+    }
+    c = lo;
+  }
+  const Desc& D = descs[c];
+  const int tl = gb - tileoff[c];
+  const int L = D.L, hx = L >> 1, half = D.half, ty = D.tile_y, tz = D.tile_z;
+  const int ny = L / ty, ntiles = ny * (L / tz);
+  const int y0 = (tl % ny) * ty, z0 = (tl / ny) * tz;
+  const int wy = ty + 4, n2 = wy * (tz + 4) * L;
+  cpx<T>* LO = (cpx<T>*)tile_smem;
+  cpx<T>* LV = LO + n2;
+  spn<T>* LS = (spn<T>*)(LV + n2);
+  const int pO = D.ctl->parity_o;
+  const double hsc = -D.t / D.a;        // Ht = -(t/a) t_ij
+  const bool second = s + 1 <= D.S;
+  const GLOBAL spn<T>* sp = (const GLOBAL spn<T>*)D.spin;
+  GLOBAL cpx<T>* vo = (GLOBAL cpx<T>*)D.vec;               // o-slots [2][half]
+  GLOBAL cpx<T>* vv = (GLOBAL cpx<T>*)D.vec + D.N;         // v-slots [2][half]
+  // global slot of staged site i
+  auto gslot = [&](int i) -> size_t {
+    const int row = i / L, x = i - row * L;
+    int gy = y0 + row % wy - 2, gz = z0 + row / wy - 2;
+    gy += (gy < 0) ? L : 0;
+    gy -= (gy >= L) ? L : 0;
+    gz += (gz < 0) ? L : 0;
+    gz -= (gz >= L) ? L : 0;
+    return (size_t)((x + gy + gz) & 1) * half + (x >> 1) + (size_t)hx * (gy + L * gz);
+  };
+  // stage: kStage sites per thread with all their loads in flight together
+  constexpr int kStage = 6;
+  for (int i0 = 0; i0 < n2; i0 += kStage * kTileThreads) {
+    cpx<T> o[kStage], v[kStage];
+    spn<T> sj[kStage];
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int i = i0 + u * kTileThreads + (int)threadIdx.x;
+      const size_t gs = gslot(min(i, n2 - 1));   // in bounds; the tail is not stored
+      o[u] = ld(vo + gs);
+      v[u] = ld(vv + gs);
+      sj[u] = ld(sp + gs);
+    }
+    STEP_LOADS_ISSUED();
+#pragma unroll
+    for (int u = 0; u < kStage; ++u) {
+      const int i = i0 + u * kTileThreads + (int)threadIdx.x;
+      if (i < n2) {
+        LO[i] = o[u];
+        LV[i] = v[u];
+        LS[i] = sj[u];
+      }
+    }
+  }
+  __syncthreads();
+  double g[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  // step s over the tile and one row around it (the tile alone if it is the
+  // chain's last step), then step s + 1 over the tile
+  tile_step(LO, LV, LS, L, ty, tz, second ? 1 : 2, pO ^ (s & 1), hsc, g);
+  __syncthreads();
+  if (second) {
+    tile_step(LO, LV, LS, L, ty, tz, 2, pO ^ ((s + 1) & 1), hsc, g + 4);
+    __syncthreads();
+  }
+  // write the tile's slots back
+  const int n0 = ty * tz * L;
+  for (int j = threadIdx.x; j < n0; j += kTileThreads) {
+    const int r = j / L, x = j - r * L;
+    const int i = ((2 + r / ty) * wy + 2 + r % ty) * L + x;
+    const size_t gs = gslot(i);
+    st(vo + gs, LO[i]);
+    st(vv + gs, LV[i]);
+  }
+  // block sums: per wave by shuffles, then over the waves in order
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    double a = g[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+    if (lane == 0) red[w][q] = a;
+  }
+  __syncthreads();
+  const int nst = second ? 2 : 1;
+  if (threadIdx.x < 4 * nst) {
+    const int q = threadIdx.x;
+    double a = 0.0;
+    for (int k = 0; k < kTileThreads / 64; ++k) a += red[k][q];
+    const int ss = s + (q >> 2);
+    D.part[((size_t)(ss - 1) * kNP2 + (q & 3)) * D.nblk + tl] = a;
+  }
+  if (tl == 0) {   // partial-sum slots of this chain beyond its tiles
+    const int extra = D.nblk - ntiles;
+    for (int k = threadIdx.x; k < 4 * nst * extra; k += kTileThreads) {
+      const int q = k / extra, b = ntiles + k % extra;
+      const int ss = s + (q >> 2);
+      D.part[((size_t)(ss - 1) * kNP2 + (q & 3)) * D.nblk + b] = 0.0;
+    }
   }
 }
 
@@ -1663,6 +1902,33 @@ hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const
                 : launch_step_h<float, false>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st);
   return hops ? launch_step_h<double, true>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st)
               : launch_step_h<double, false>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st);
+}
+
+// The two-step pair kernel takes up to kTileLds of dynamic LDS (set once per
+// process, before its first launch).
+hipError_t prepare_step_ov2() {
+  static const hipError_t e = [] {
+    hipError_t r = hipFuncSetAttribute((const void*)k_step_ov2<float>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kTileLds);
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute((const void*)k_step_ov2<double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kTileLds);
+    return r;
+  }();
+  return e;
+}
+
+hipError_t launch_step_ov2(int fp32, const Desc* d, const int* tileoff, int nact, int tiles, int s,
+                           size_t lds, hipStream_t st) {
+  const hipError_t e = prepare_step_ov2();
+  if (e != hipSuccess) return e;
+  if (fp32)
+    hipLaunchKernelGGL(k_step_ov2<float>, dim3(tiles), dim3(kTileThreads), lds, st, d, tileoff,
+                       nact, s);
+  else
+    hipLaunchKernelGGL(k_step_ov2<double>, dim3(tiles), dim3(kTileThreads), lds, st, d, tileoff,
+                       nact, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_hops(int fp32, const Desc* d, int nmax, hipStream_t st) {

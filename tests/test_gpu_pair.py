@@ -192,3 +192,84 @@ def test_mixed_and_pair_chains_in_one_batch(g):
         for i in range(len(specs)):
             r, a = recs[q][i], alone[i][q]
             assert (r.site, r.accepted, r.dseff) == (a.site, a.accepted, a.dseff)
+
+
+# --------------------------------------------- two steps per launch (shape 3) --
+# (L, M, K): S = M/2 of 64, 45, 32 and 31 steps, so the chains drop out of the
+# two-step launches at different points, two of them with a last step alone
+TWO_STEP_SPECS = [(16, 128, 128), (8, 90, 128), (24, 64, 64), (16, 62, 64)]
+
+
+def _two_step_batch(g, prec, shape, vectors):
+    chs = []
+    for i, (L, M, K) in enumerate(TWO_STEP_SPECS):
+        ch = g.Chain(g.Params(L=L, M=M, K=K, precision=prec, vectors=vectors, seed=21,
+                              chain_id=i, beta=10.0))
+        th, ph = synth.random_angles(L ** 3, 40 + i)
+        ch.set_spins(th, ph)
+        chs.append(ch)
+    b = g.Batch(chs)
+    b.set_lanes(1)
+    b.set_tuning(shape)
+    assert b.tuning() == (shape, 1)
+    return chs, b
+
+
+@pytest.mark.parametrize("prec,vectors", [(0, 1), (1, 1), (1, 2)])
+def test_two_step_shape_matches_one_step_shape_and_oracle(g, prec, vectors):
+    # Shape 3 forms the same vector values as shape 1 (same arithmetic, term for
+    # term) and sums them per tile instead of per block: every proposal's
+    # Delta S agrees to rounding of the FP64 sums, the decisions and final
+    # spins are equal, and the first proposal's Delta S matches the oracle.
+    nprop = 3
+    runs = {}
+    for shape in (1, 3):
+        chs, b = _two_step_batch(g, prec, shape, vectors)
+        spins0 = [c.get_spins() for c in chs]
+        recs = b.step(nprop, records=True)
+        b.close()
+        runs[shape] = (recs, [c.get_spins() for c in chs], spins0)
+    r1, s1, spins0 = runs[1]
+    r3, s3, _ = runs[3]
+    for q in range(nprop):
+        for i in range(len(TWO_STEP_SPECS)):
+            a, b_ = r1[q][i], r3[q][i]
+            print(f"prop {q} chain {i}: dS {a.dseff:.12f} / {b_.dseff:.12f}", flush=True)
+            assert a.site == b_.site and a.theta_new == b_.theta_new and a.phi_new == b_.phi_new
+            assert abs(a.dseff - b_.dseff) < 1e-9 * max(1.0, abs(a.dseff))
+            assert a.accepted == b_.accepted
+    for (t1, p1), (t3, p3) in zip(s1, s3):
+        assert np.array_equal(t1, t3) and np.array_equal(p1, p3)
+    tol = 1e-10 if prec == 0 else 2e-5
+    for i, (L, M, K) in enumerate(TWO_STEP_SPECS):
+        m = oracle.Model(L=L, M=M, K=K, beta=10.0, seed=21, chain_id=i)
+        th, ph = spins0[i]
+        r = r3[0][i]
+        ref = (oracle.delta_seff(m, th, ph, r.site, r.theta_new, r.phi_new) if vectors == 1
+               else oracle.delta_seff_mixed(m, th, ph, r.site, r.theta_new, r.phi_new))
+        print(f"chain {i} L={L} M={M}: dS {r.dseff:.10f} oracle {ref:.10f}", flush=True)
+        assert abs(r.dseff - ref) < tol
+
+
+def test_two_step_shape_refusals(g):
+    def batch(L, M, vectors, prec=0):
+        ch = g.Chain(g.Params(L=L, M=M, precision=prec, vectors=vectors, seed=3))
+        return g.Batch([ch, g.Chain(g.Params(L=L, M=M, precision=prec, vectors=vectors,
+                                             seed=4))])
+    for L, vec in ((16, 0), (12, 1), (6, 1)):   # 7-vector form; too few blocks; L < 8
+        b = batch(L, 64, vec)
+        with pytest.raises(g.GfmcError) as e:
+            b.set_tuning(3)
+        assert e.value.status == g.GFMC_EINVAL
+        b.close()
+    b = batch(16, 64, 1)
+    b.set_tuning(3)
+    with pytest.raises(g.GfmcError) as e:
+        b.set_schedule(True)           # the two-step shape is lock-step only
+    assert e.value.status == g.GFMC_EINVAL
+    b.set_tuning(1)
+    b.set_schedule(True)
+    with pytest.raises(g.GfmcError) as e:
+        b.set_tuning(3)
+    assert e.value.status == g.GFMC_EINVAL
+    b.close()
