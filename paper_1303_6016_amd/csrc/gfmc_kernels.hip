@@ -105,14 +105,19 @@ __device__ inline spn<T> make_spinor(double th, double ph) {
 
 // sc <chi_i|chi_j> = sc t_ij with sc = -t/a: the element of the rescaled
 // Hamiltonian Ht (t_ij as in equation "ht", from the cached half-angle
-// factors), formed in FP64 and rounded once to the recursion precision T.
+// factors), each element rounded once to the recursion precision T.
 // In the FP32 recursion two roundings of the Hamiltonian dominate the error
 // of the moments, not the rounding of the vectors: a scale -2t/a rounded to
 // FP32 once multiplies every step's Ht by the same (1 + 4e-8), an error that
 // grows coherently with the moment order, and amplitudes summed in FP32
-// carry a few 1e-8 absolute error each.  Forming sc t_ij in FP64 and
-// rounding each element once (the steps then double it exactly) cuts the
-// FP32 moment error several-fold for the same bytes and instructions.
+// carry a few 1e-8 absolute error each.  Scaling each element by sc, not
+// the step's sum by 2 sc (the steps then double exactly), and carrying sc
+// as an FP32 pair hi + lo (so that its rounding acts on no element) removes
+// the coherent part.  FP32 forms t_ij in FP32 arithmetic and the scaled
+// element as fma(t, hi, t lo), keeping Ht exactly Hermitian; a float model
+// of the recursion puts its moment error within 15 % of forming sc t_ij in
+// FP64 and rounding once (whose FP64 products and conversions made the step
+// kernels' arithmetic their bound in the pair form); FP64 forms it directly.
 template <typename T>
 __device__ inline void hop_spinor(const spn<T>& a, const spn<T>& b, const double sc, T& re,
                                   T& im) {
@@ -120,6 +125,26 @@ __device__ inline void hop_spinor(const spn<T>& a, const spn<T>& b, const double
   const double cr = b.ar, ci = b.ai, dr = b.br, di = b.bi;
   re = (T)(sc * (ar * cr + ai * ci + br * dr + bi * di));
   im = (T)(sc * (ar * ci - ai * cr + br * di - bi * dr));
+}
+template <>
+__device__ inline void hop_spinor<float>(const spn<float>& a, const spn<float>& b,
+                                         const double sc, float& re, float& im) {
+  // Ht stays Hermitian bit for bit: the element for (j, i) must be the exact
+  // conjugate of the one for (i, j).  The real part's fused chain takes the
+  // same products in the same order either way; the imaginary part is formed
+  // from rounded products and their differences (no fusion), which only
+  // change sign when i and j swap.
+#pragma clang fp contract(off)
+  const float sh = (float)sc, sl = (float)(sc - (double)sh);   // kernel-invariant
+  float tr = a.bi * b.bi;
+  tr = fmaf(a.br, b.br, tr);
+  tr = fmaf(a.ai, b.ai, tr);
+  tr = fmaf(a.ar, b.ar, tr);
+  const float d1 = a.ar * b.ai - a.ai * b.ar;
+  const float d2 = a.br * b.bi - a.bi * b.br;
+  const float ti = d1 + d2;
+  re = fmaf(tr, sh, tr * sl);
+  im = fmaf(ti, sh, ti * sl);
 }
 
 // (ar, ai) += (hr + i hi) a with the four products fused in a fixed order, so
