@@ -477,6 +477,14 @@ def serving(g, seconds: float, mix: str = "small", seed: int = 2024, emit: bool 
                 round(r.t_done - (r.t_first_sweep if r.t_first_sweep >= 0 else r.t_admit), 1)
                 for r in cut if r.t_admit >= 0]
             rec_L["unfinished_queued"] = sum(1 for r in cut if r.t_admit < 0)
+            # the rate they ran at: proposals done in their open sweep, and the
+            # sweep time that rate projects (N proposals per sweep)
+            rec_L["unfinished_open_sweep_proposals"] = [
+                int(r.proposals % (Lk ** 3)) for r in cut if r.t_admit >= 0]
+            rec_L["unfinished_projected_sweep_s"] = [
+                round((r.t_done - (r.t_first_sweep if r.t_first_sweep >= 0 else r.t_admit)) *
+                      Lk ** 3 / max(1, r.proposals % (Lk ** 3)), 1)
+                for r in cut if r.t_admit >= 0]
         per_L[str(Lk)] = rec_L
     wait = np.array([r.t_admit - r.t_submit for r in res if r.t_admit >= 0])
     rec = {
@@ -673,18 +681,6 @@ def main():
     if args.fp32_accuracy:
         fp32_accuracy(g)
         return
-    sv = None
-    if args.serving_leg:
-        # the metric's p50/p99 sweep latency under continuous batching; run
-        # before the other legs, while this process holds no other streams, so
-        # that the engine's group streams get hardware queues of their own
-        note("serving (30 s of Poisson arrivals)")
-        try:
-            sv = serving(g, 30.0, "small", emit=False)
-        except Exception as e:   # the headline must still be reported
-            note(f"serving leg failed: {e}")
-            sv = {"error": str(e)}
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     temps = synth.temperature_ladder(NCHAIN, T_LO, T_HI)
@@ -907,20 +903,27 @@ def main():
     if args.small:
         note("4^3 and 16^3 workloads")
         out["small_configs"] = leg("small workloads", lambda: small_configs(g, torch, dev))
-    if sv is not None and "error" in sv:
-        out["serving"] = sv
-    elif sv is not None:
-        out["serving"] = {
-            "mix": "small", "workload": sv["config"]["workload"],
-            "arrival_window_s": sv["arrival_window_s"], "requests": sv["requests"],
-            "completed": sv["completed"], "sweep_latency_s": sv["sweep_latency_s"],
-            "queue_wait_s": sv["queue_wait_s"],
-            "mc_spin_updates_per_s": sv["mc_spin_updates_per_s"]}
+    batch.close()
+    if args.serving_leg:
+        # the metric's p50/p99 sweep latency under continuous batching; every
+        # batch of the other legs is closed (their streams released), so the
+        # engine's three streams and torch's get a hardware queue each
+        note("serving (30 s of Poisson arrivals)")
+        try:
+            sv = serving(g, 30.0, "small", emit=False)
+            out["serving"] = {
+                "mix": "small", "workload": sv["config"]["workload"],
+                "arrival_window_s": sv["arrival_window_s"], "requests": sv["requests"],
+                "completed": sv["completed"], "sweep_latency_s": sv["sweep_latency_s"],
+                "queue_wait_s": sv["queue_wait_s"],
+                "mc_spin_updates_per_s": sv["mc_spin_updates_per_s"]}
+        except Exception as e:   # the headline must still be reported
+            note(f"serving leg failed: {e}")
+            out["serving"] = {"error": str(e)}
 
     if not args.no_cpu_baseline:
         note("oracle on the host cores")
         out["cpu_baseline"] = leg("oracle baseline", cpu_baseline)
-    batch.close()
     print(json.dumps(out), flush=True)
 
 

@@ -129,6 +129,8 @@ void fill_desc(gfmc_chain* c) {
   D.nblk = c->d.nblk; D.kernel = c->p.kernel; D.proposal = c->p.proposal; D.log2K = c->d.log2K;
   D.vectors = c->p.vectors;
   D.hops = c->p.hoppings;
+  D.div_hx = make_fastdiv((uint32_t)(c->d.L / 2));
+  D.div_L = make_fastdiv((uint32_t)c->d.L);
   D.hop = c->d.hops ? (void*)(c->ws + c->l.hop) : nullptr;
   D.t = c->p.t; D.beta = c->p.beta; D.mu = c->p.mu; D.a = c->d.a; D.cone = c->p.cone_angle;
   D.lambda = c->d.lambda; D.seed = c->p.seed; D.chain_id = c->p.chain_id;

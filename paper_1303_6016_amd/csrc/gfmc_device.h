@@ -54,11 +54,23 @@ struct Ctl {
   unsigned bar[4];
 };
 
+// Division by a per-chain constant d for 0 <= n < 2^31: m = floor((2^32 - 1)
+// / d) makes the high word of n m undershoot n / d by at most one, which one
+// comparison corrects (the step kernels split every site index this way
+// instead of by a division instruction sequence).
+struct FastDiv {
+  uint32_t d, m;
+};
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
+  return FastDiv{d, (uint32_t)(0xffffffffu / d)};
+}
+
 // Per-chain descriptor (device table read by the batched kernels).
 struct Desc {
   int32_t L, N, half, M, S, K, nblk, kernel, proposal, log2K;
   int32_t vectors, hops;      // GFMC_VECTORS_*, GFMC_HOP_*
   int32_t tile_y, tile_z;    // two-step pair kernel: rows per tile in y and z
+  FastDiv div_hx, div_L;     // division by L/2 and by L (site index splitting)
   double t, beta, mu, a, cone, lambda;
   uint64_t seed, chain_id;
   double* theta;            // [N]

@@ -83,6 +83,34 @@ __device__ inline int nb_half(int x, int y, int z, int d, int L) {
   return half_index(x, y, z, L);
 }
 
+__device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  const uint32_t q = __umulhi(n, f.m);
+  return q + ((q + 1u) * f.d <= n ? 1u : 0u);
+}
+
+// Row coordinates of half-row index h: h = k + (L/2)(y + L z).
+__device__ inline void split_half(int h, const Desc& D, int& k, int& y, int& z) {
+  const int r = (int)fdiv((uint32_t)h, D.div_hx);
+  k = h - r * (D.L >> 1);
+  z = (int)fdiv((uint32_t)r, D.div_L);
+  y = r - z * D.L;
+}
+
+// Half-row indices of the six neighbours (the order of nb_half: x+1, x-1,
+// y+1, y-1, z+1, z-1) of the site with half-row index h, row coordinates
+// (k, y, z) and x = 2k + xb, by offsets from h: an x neighbour shares h or
+// is the next or previous entry of the row (wrapping within it), the y and z
+// neighbours are a row or a plane away (wrapping across the lattice).
+__device__ inline void nb6_half(int h, int k, int xb, int y, int z, int L, int nh[6]) {
+  const int hx = L >> 1, plane = hx * L, row = h - k;
+  nh[0] = xb ? ((k + 1 == hx) ? row : h + 1) : h;
+  nh[1] = xb ? h : ((k == 0) ? row + hx - 1 : h - 1);
+  nh[2] = (y + 1 == L) ? h - hx * (L - 1) : h + hx;
+  nh[3] = (y == 0) ? h + hx * (L - 1) : h - hx;
+  nh[4] = (z + 1 == L) ? h - plane * (L - 1) : h + plane;
+  nh[5] = (z == 0) ? h + plane * (L - 1) : h - plane;
+}
+
 // Hopping amplitude from the angles (equation "ht"), FP64.
 __device__ inline void hop_angles(double ti, double pi_, double tj, double pj, double& re,
                                   double& im) {
@@ -525,10 +553,19 @@ __device__ inline int chain_step(int s, const int* __restrict__ act_end, int c, 
 // directions) must have been issued.
 #define STEP_LOADS_ISSUED() __builtin_amdgcn_sched_barrier(0)
 
-template <typename T, bool FIRST, int PPT, bool HOPS, bool NT, bool COH = false>
+// Hook between a step's vector updates and its Gram sums (the persistent
+// kernel counts in at its step barrier there, so that the barrier's wait
+// overlaps the sums); the one-step kernels pass this no-op.
+struct NoArrive {
+  __device__ void operator()() const {}
+};
+
+template <typename T, bool FIRST, int PPT, bool HOPS, bool NT, bool COH = false,
+          typename Arrive = NoArrive>
 __device__ __forceinline__ void step_block(const Desc& D, const int lb, const int s,
-                                           double (*xs)[16][17], double (*gsum)[256]) {
-  const int L = D.L, hx = L >> 1, half = D.half;
+                                           double (*xs)[16][17], double (*gsum)[256],
+                                           const Arrive& arrive = Arrive()) {
+  const int L = D.L, half = D.half;
   const Ctl* ctl = D.ctl;
   const int pO = ctl->parity_o;
   const int po = pO ^ (s & 1);          // parity of the sites that carry a^o_s
@@ -547,6 +584,11 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
   // stored hopping rows t_{i, n_d(i)} (HOPS): six<T>[2][half]
   const Planes<T> hrow = planes<T>(D.hop, D.N);
 
+  // COH (persistent kernel): a neighbour value stored in the previous step by
+  // another block, that is on another compute unit, is read past this
+  // unit's L1; one this block stored went through the same L1 and loads as
+  // usual (each block keeps its site pairs from step to step)
+  auto nb_elsewhere = [&](int nhh) { return nhh / (kStepThreads * PPT) != lb; };
   double x[PPT][16];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
@@ -554,17 +596,16 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
     for (int i = 0; i < 16; ++i) x[p][i] = 0.0;
     const int h = (lb * PPT + p) * kStepThreads + (int)threadIdx.x;
     if (h >= half) continue;
-    const int k = h % hx, r = h / hx, y = r % L, z = r / L;
-    const int xo = 2 * k + ((y + z + po) & 1);
-    const int xn = 2 * k + ((y + z + pn) & 1);
+    int k, y, z;
+    split_half(h, D, k, y, z);
+    const int bo = (y + z + po) & 1, bn = bo ^ 1;   // x = 2k + b of the o- and n-site
     // a^o_s on the o-site.  Every load of the site is issued before its
     // arithmetic (one memory round trip): left to itself the compiler keeps
     // registers low by waiting for each direction's loads in turn, and the
     // kernel becomes bound by the latency of those round trips.
     {
       int nh[6];
-#pragma unroll
-      for (int d = 0; d < 6; ++d) nh[d] = nb_half(xo, y, z, d, L);
+      nb6_half(h, k, bo, y, z, L, nh);
       spn<T> si, sj[6];
       six<T> row;
       cpx<T> an[6], pr = {(T)0, (T)0};
@@ -578,7 +619,8 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         if (FIRST) { an[d].x = (nh[d] == o_half) ? (T)1 : (T)0; an[d].y = 0; }
-        else an[d] = COH ? ld_coh(vo + (size_t)pn * half + nh[d]) : ld(vo + (size_t)pn * half + nh[d]);
+        else if (COH && nb_elsewhere(nh[d])) an[d] = ld_coh(vo + (size_t)pn * half + nh[d]);
+        else an[d] = ld(vo + (size_t)pn * half + nh[d]);
       }
       if (!FIRST) pr = NT ? ld_nt(vo + (size_t)po * half + h) : ld(vo + (size_t)po * half + h);
       STEP_LOADS_ISSUED();
@@ -605,9 +647,11 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
     // a^{n_e}_s, e = 0..5, on the n-site: the six directions in groups of
     // kGroup, each group's loads issued together (six 16-value records at
     // once are too many registers to keep the occupancy; groups of two
-    // measured fastest on the HBM-resident batches)
+    // measured fastest on the HBM-resident batches).  The persistent kernel
+    // runs one wave per SIMD, so registers cost it no occupancy: it takes
+    // the directions in one group (FP32) or two (FP64).
     {
-      constexpr int kGroup = 2;
+      constexpr int kGroup = COH ? (sizeof(T) == 4 ? 6 : 3) : 2;
       spn<T> si;
       six<T> row;
       if (HOPS) row = hrow.ld((size_t)pn * half + h);
@@ -617,13 +661,15 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
       for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
       six<T> prev;
       cpx<T> aop;   // a^o_{s-1} at the n-site
+      int nhn[6];
+      nb6_half(h, k, bn, y, z, L, nhn);
 #pragma unroll
       for (int d0 = 0; d0 < 6; d0 += kGroup) {
         int nh[kGroup];
         spn<T> sj[kGroup];
         six<T> an[kGroup];
 #pragma unroll
-        for (int g = 0; g < kGroup; ++g) nh[g] = nb_half(xn, y, z, d0 + g, L);
+        for (int g = 0; g < kGroup; ++g) nh[g] = nhn[d0 + g];
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
           if (!HOPS) sj[g] = ld(sp_o + nh[g]);
@@ -634,7 +680,8 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
               an[g].v[e].y = 0;
             }
           } else {
-            an[g] = COH ? vn.ld_coh((size_t)po * half + nh[g]) : vn.ld((size_t)po * half + nh[g]);
+            if (COH && nb_elsewhere(nh[g])) an[g] = vn.ld_coh((size_t)po * half + nh[g]);
+            else an[g] = vn.ld((size_t)po * half + nh[g]);
           }
         }
         if (d0 + kGroup >= 6 && !FIRST) {   // the site's own values ride with the last group
@@ -687,6 +734,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
     }
   }
 
+  arrive();
   // Gram matrix of x over the block on the FP64 matrix core:
   // v_mfma_f64_16x16x4 with A = B = 4 columns (site pairs) of 16 components.
   // Each wave stages 16 site pairs at a time in LDS (4 rounds per PPT slice).
@@ -755,10 +803,12 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
 // point of coherence for all of them, so a step's stores are visible to the
 // other blocks once they have completed (the vector L1 writes through): each
 // wave waits for its stores, one thread per block counts in at the L2 and
-// polls it, and the next step reads its neighbours' values (stored by other
-// blocks) with device-scope loads, which skip the compute unit's L1 and are
-// served by the L2; the site's own values, stored by the same thread, and
-// the spinors, fixed during a proposal, load as usual.  No cache is written
+// polls it, and the next step reads the neighbour values that other blocks
+// stored with device-scope loads, which skip the compute unit's L1 and are
+// served by the L2; values this block stored (through the same L1) and the
+// spinors, fixed during a proposal, load as usual.  (Reading every
+// neighbour past the L1 sent the stencil's reuse, six loads per value, to
+// the L2 through the links of the few compute units a lone chain uses.)  No cache is written
 // back or invalidated: the device-scope fences that would (the L2 write-back
 // for other dies, the L1 and L2 invalidation) cost more per step than a
 // kernel launch, for visibility this run never needs.  Waits are
@@ -771,12 +821,24 @@ __device__ inline unsigned xcd_id() {
   return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 0xfu;   // HW_REG_XCC_ID, bits 3:0
 }
 
-__device__ inline bool die_barrier(unsigned* count, unsigned target, unsigned* err, int* ok_sh) {
-  __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached the L2
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __syncthreads();
+// The step barrier in two phases.  Arrive: every wave waits for its stores
+// of the step (they are then in the L2), and one thread counts the block in.
+// Wait: that thread polls the count, and the block proceeds once every block
+// of the run has arrived.  Between the two the block forms its Gram sums,
+// which no other block reads.
+struct DieArrive {
+  unsigned* count;
+  __device__ void operator()() const {
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached the L2
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+__device__ inline bool die_wait(unsigned* count, unsigned target, unsigned* err, int* ok_sh) {
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
     for (int i = 0;
          __hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++i) {
@@ -817,11 +879,12 @@ __global__ __launch_bounds__(kStepThreads) void k_persist(const Desc* __restrict
   __syncthreads();
   const int lb = tk;
   if (lb >= nb) return;
+  const DieArrive arrive{&bar[2]};
   for (int s = 1; s <= D.S; ++s) {
-    if (s == 1) step_block<T, true, 1, false, false, true>(D, lb, 1, xs, gsum);
-    else step_block<T, false, 1, false, false, true>(D, lb, s, xs, gsum);
+    if (s == 1) step_block<T, true, 1, false, false, true>(D, lb, 1, xs, gsum, arrive);
+    else step_block<T, false, 1, false, false, true>(D, lb, s, xs, gsum, arrive);
     if (s == D.S) break;
-    if (!die_barrier(&bar[2], (unsigned)nb * (unsigned)s, &bar[3], &ok_sh)) return;
+    if (!die_wait(&bar[2], (unsigned)nb * (unsigned)s, &bar[3], &ok_sh)) return;
   }
 }
 
@@ -1030,7 +1093,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
   const int s = chain_step(s_arg, act_end, c, D.S);
   if (s == 0) return;   // uniform over the block: the chain does not step now
   const int lb = gb - blkoff[c];
-  const int L = D.L, hx = L >> 1, half = D.half;
+  const int L = D.L, half = D.half;
   const Ctl* ctl = D.ctl;
   const int pO = ctl->parity_o;
   const int po = pO ^ (s & 1);          // parity of the sites that carry a^o_s
@@ -1064,16 +1127,17 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
   for (int p = 0; p < PPT; ++p) {
     const int h = (lb * PPT + p) * kStepThreads + (int)threadIdx.x;
     if (h >= half) continue;
-    const int k = h % hx, r = h / hx, y = r % L, z = r / L;
-    const int xo = 2 * k + ((y + z + po) & 1);
-    const int xn = 2 * k + ((y + z + pn) & 1);
+    int k, y, z;
+    split_half(h, D, k, y, z);
+    const int bo = (y + z + po) & 1, bn = bo ^ 1;   // x = 2k + b of the o- and v-site
     cpx<T> ao, av, aop;
     // each site's loads issued together, before its arithmetic (one memory
-    // round trip per site instead of one per direction)
+    // round trip per site instead of one per direction; issuing both sites'
+    // loads at once measured no faster in FP32 and slower in FP64, whose
+    // registers then halve the occupancy)
     {
       int nh[6];
-#pragma unroll
-      for (int d = 0; d < 6; ++d) nh[d] = nb_half(xo, y, z, d, L);
+      nb6_half(h, k, bo, y, z, L, nh);
       const spn<T> si = ld(sp_o + h);
       spn<T> sj[6];
       cpx<T> an[6], pr = {(T)0, (T)0};
@@ -1098,8 +1162,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
     }
     {
       int nh[6];
-#pragma unroll
-      for (int d = 0; d < 6; ++d) nh[d] = nb_half(xn, y, z, d, L);
+      nb6_half(h, k, bn, y, z, L, nh);
       const spn<T> si = ld(sp_n + h);
       spn<T> sj[6];
       cpx<T> an[6], pr = {(T)0, (T)0};
