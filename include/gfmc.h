@@ -352,13 +352,15 @@ gfmc_status gfmc_batch_get_form(gfmc_batch* batch, int32_t* resident, int32_t* p
 gfmc_status gfmc_batch_get_tuning(gfmc_batch* batch, int32_t* pairs_per_thread, int32_t* lanes);
 
 /* Time each step-kernel launch shape the batch's chains fit (shape 3 only
- * in the lock-step schedule; non-temporal access for the 7-vector kernel)
- * with one to four lanes over
- * `trial_steps` Chebyshev steps on the batch's current spins (no change of
- * chain state), keep the fastest, and remember it for later batches of the
- * same shape (precision, start vectors, hoppings, schedule, number of
- * chains, L and M of each chain).  chosen
- * (the shape) may be NULL; gfmc_batch_get_tuning reports the lanes. */
+ * in the lock-step schedule; non-temporal access for the 7-vector kernel;
+ * for a lone chain that fits one die, its persistent kernel) with one to
+ * four lanes over max(trial_steps, 64) Chebyshev steps (at most M/2 - 1) on
+ * the batch's current spins (no change of chain state), by host wall time
+ * (so that the host's launch rate counts where launches are short), keep
+ * the fastest, and remember it for later batches of the same shape
+ * (precision, start vectors, hoppings, schedule, number of chains, L and M
+ * of each chain).  chosen (the shape) may be NULL; gfmc_batch_get_tuning
+ * reports the lanes. */
 gfmc_status gfmc_batch_autotune(gfmc_batch* batch, int32_t trial_steps, int32_t* chosen);
 
 /* Timing of the Chebyshev step kernel over the last gfmc_batch_step call,

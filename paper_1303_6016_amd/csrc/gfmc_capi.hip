@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1383,16 +1384,6 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
   // trial launches between proposals leave the chains' state unchanged.
   int best = 1, best_lanes = 1, best_nt = 0;
   float best_ms = 1e30f;
-  struct Events {   // destroyed on every return path
-    hipEvent_t a = nullptr, b = nullptr;
-    ~Events() {
-      if (a) (void)hipEventDestroy(a);
-      if (b) (void)hipEventDestroy(b);
-    }
-  } ev;
-  HIPCHK(hipEventCreate(&ev.a));
-  HIPCHK(hipEventCreate(&ev.b));
-  hipEvent_t e0 = ev.a, e1 = ev.b;
   bool all_res = true, all_tile2 = !P.cont;
   for (auto* c : b->sorted) {
     all_res = all_res && resident_fits(c->d);
@@ -1408,30 +1399,43 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
       CHK(gfmc_batch_set_lanes(b, lanes));
       CHK(gfmc_batch_set_tuning(b, ppt));
       CHK(gfmc_batch_set_nontemporal(b, nt));
+      if (P.persist > 0 && nt) continue;   // the persistent kernel has no non-temporal form
+      // Host wall time of enqueueing and running the trial: where the launches
+      // are short the host's launch rate bounds a proposal, which GPU-side
+      // event times of a short burst miss (a lone 16^3 chain: 8 timed step
+      // launches looked faster than the persistent kernel, 512 in a row ran
+      // at half its rate).  Launch shapes time nsteps steps twice, the faster
+      // pass counting; one-launch shapes time a whole proposal, scaled.
+      const int nsteps = std::max(1, std::min(P.smax - 1, std::max(trial_steps, 64)));
+      auto wall_ms = [](std::chrono::steady_clock::time_point t0) {
+        return (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                t0).count();
+      };
       float ms = 0;
-      if (ppt == 0) {   // the resident kernel runs every step of a proposal in one launch
-        HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
-        HIPCHK(hipEventRecord(e0, P.stream));
-        HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
-        HIPCHK(hipEventRecord(e1, P.stream));
-        HIPCHK(hipEventSynchronize(e1));
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        ms = ms / std::max(1, P.smax) * std::min(P.smax - 1, trial_steps);
-      } else {
-        // a proposal state for the trial (the counter only advances in k_recon);
-        // the steps are timed twice and the faster pass counts
-        HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
-        CHK(enqueue_steps(P, 1, 1));
-        const int smax = std::max(2, std::min(P.smax, trial_steps + 1));
+      if (P.persist > 0 || ppt == 0) {   // one launch per proposal, timed twice
+        // (a kernel's first launch in a process also loads its code)
         ms = 1e30f;
         for (int rep = 0; rep < 2; ++rep) {
-          HIPCHK(hipEventRecord(e0, P.stream));
-          CHK(enqueue_steps(P, 2, smax));
-          HIPCHK(hipEventRecord(e1, P.stream));
-          HIPCHK(hipEventSynchronize(e1));
-          float t = 0;
-          HIPCHK(hipEventElapsedTime(&t, e0, e1));
-          ms = std::min(ms, t);
+          HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
+          HIPCHK(hipStreamSynchronize(P.stream));
+          const auto t0 = std::chrono::steady_clock::now();
+          if (P.persist > 0) HIPCHK(launch_persist(P.fp32, P.d_desc, P.persist, P.stream));
+          else HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
+          HIPCHK(hipStreamSynchronize(P.stream));
+          ms = std::min(ms, wall_ms(t0) / std::max(1, P.smax) * nsteps);
+          CHK(persist_check(P));
+        }
+      } else {
+        // a proposal state for the trial (the counter only advances in k_recon)
+        HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
+        CHK(enqueue_steps(P, 1, 1));
+        ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIPCHK(hipStreamSynchronize(P.stream));
+          const auto t0 = std::chrono::steady_clock::now();
+          CHK(enqueue_steps(P, 2, 1 + nsteps));
+          HIPCHK(hipStreamSynchronize(P.stream));
+          ms = std::min(ms, wall_ms(t0));
         }
       }
       if (ms < best_ms) { best_ms = ms; best = ppt; best_lanes = lanes; best_nt = nt; }

@@ -564,7 +564,8 @@ template <typename T, bool FIRST, int PPT, bool HOPS, bool NT, bool COH = false,
           typename Arrive = NoArrive>
 __device__ __forceinline__ void step_block(const Desc& D, const int lb, const int s,
                                            double (*xs)[16][17], double (*gsum)[256],
-                                           const Arrive& arrive = Arrive()) {
+                                           const Arrive& arrive = Arrive(),
+                                           const cpx<T> (*hp)[6] = nullptr) {
   const int L = D.L, half = D.half;
   const Ctl* ctl = D.ctl;
   const int pO = ctl->parity_o;
@@ -587,7 +588,10 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
   // COH (persistent kernel): a neighbour value stored in the previous step by
   // another block, that is on another compute unit, is read past this
   // unit's L1; one this block stored went through the same L1 and loads as
-  // usual (each block keeps its site pairs from step to step)
+  // usual (each block keeps its site pairs from step to step).  Its threads
+  // also keep their site pair's twelve hopping amplitudes in registers for
+  // the whole proposal (hp[q][d]: the site of parity q to its neighbour d,
+  // formed by the same hop_spinor), so its steps load no spinors.
   auto nb_elsewhere = [&](int nhh) { return nhh / (kStepThreads * PPT) != lb; };
   double x[PPT][16];
 #pragma unroll
@@ -611,7 +615,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
       cpx<T> an[6], pr = {(T)0, (T)0};
       if (HOPS) {
         row = hrow.ld((size_t)po * half + h);
-      } else {
+      } else if (!COH) {
         si = ld(sp_o + h);
 #pragma unroll
         for (int d = 0; d < 6; ++d) sj[d] = ld(sp_n + nh[d]);
@@ -631,6 +635,9 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
         if (HOPS) {
           hr = row.v[d].x;
           hi_ = row.v[d].y;
+        } else if (COH) {   // selects, not an indexed register array
+          hr = po ? hp[1][d].x : hp[0][d].x;
+          hi_ = po ? hp[1][d].y : hp[0][d].y;
         } else {
           hop_spinor(si, sj[d], hsc, hr, hi_);
         }
@@ -655,7 +662,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
       spn<T> si;
       six<T> row;
       if (HOPS) row = hrow.ld((size_t)pn * half + h);
-      else si = ld(sp_n + h);
+      else if (!COH) si = ld(sp_n + h);
       T accr[6], acci[6];
 #pragma unroll
       for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
@@ -672,7 +679,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
         for (int g = 0; g < kGroup; ++g) nh[g] = nhn[d0 + g];
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
-          if (!HOPS) sj[g] = ld(sp_o + nh[g]);
+          if (!HOPS && !COH) sj[g] = ld(sp_o + nh[g]);
           if (FIRST) {
 #pragma unroll
             for (int e = 0; e < 6; ++e) {
@@ -696,6 +703,9 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
           if (HOPS) {
             hr = row.v[d].x;
             hi_ = row.v[d].y;
+          } else if (COH) {
+            hr = pn ? hp[1][d].x : hp[0][d].x;
+            hi_ = pn ? hp[1][d].y : hp[0][d].y;
           } else {
             hop_spinor(si, sj[g], hsc, hr, hi_);
           }
@@ -879,10 +889,30 @@ __global__ __launch_bounds__(kStepThreads) void k_persist(const Desc* __restrict
   __syncthreads();
   const int lb = tk;
   if (lb >= nb) return;
+  // the twelve hopping amplitudes of this thread's site pair, fixed for the
+  // proposal: hp[q][d] from the site of parity q to its neighbour d
+  cpx<T> hp[2][6];
+  {
+    const int h = lb * kStepThreads + (int)threadIdx.x;
+    const int hh = h < D.half ? h : 0;   // threads past the lattice take none
+    int k, y, z;
+    split_half(hh, D, k, y, z);
+    const GLOBAL spn<T>* sp = (const GLOBAL spn<T>*)D.spin;
+    const double hsc = -D.t / D.a;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      int nh[6];
+      nb6_half(hh, k, (y + z + q) & 1, y, z, D.L, nh);
+      const spn<T> si = ld(sp + (size_t)q * D.half + hh);
+#pragma unroll
+      for (int d = 0; d < 6; ++d)
+        hop_spinor(si, ld(sp + (size_t)(q ^ 1) * D.half + nh[d]), hsc, hp[q][d].x, hp[q][d].y);
+    }
+  }
   const DieArrive arrive{&bar[2]};
   for (int s = 1; s <= D.S; ++s) {
-    if (s == 1) step_block<T, true, 1, false, false, true>(D, lb, 1, xs, gsum, arrive);
-    else step_block<T, false, 1, false, false, true>(D, lb, s, xs, gsum, arrive);
+    if (s == 1) step_block<T, true, 1, false, false, true>(D, lb, 1, xs, gsum, arrive, hp);
+    else step_block<T, false, 1, false, false, true>(D, lb, s, xs, gsum, arrive, hp);
     if (s == D.S) break;
     if (!die_wait(&bar[2], (unsigned)nb * (unsigned)s, &bar[3], &ok_sh)) return;
   }
