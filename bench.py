@@ -27,19 +27,18 @@ T_LO, T_HI = 0.02, 0.2
 SEED = 7
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per step round of this workload (one Chebyshev step of every chain:
-# one launch, or one per lane; the lanes split the same blocks, so the bytes
-# per round do not depend on them) from rocprofv3 FETCH_SIZE / WRITE_SIZE (one
-# counter per run), each scaled by what the same counter reads for a plain
-# 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); valid only for the kernel
-# source they were taken with (sha256 below), else reported as null.
-TRAFFIC_KERNEL_SHA256 = "791bf75ae47c22f5517ac59d2242aba8cddd4d8f383e494d27cc37b44015f55a"
-TRAFFIC_BYTES = {("k_step<float>", 1): 214111406,
-                 ("k_step<float>", 2): 221123713,
-                 ("k_step_ov<float>", 1): 84205356,
-                 ("k_step_ov<float>", 2): 84210730,
-                 ("k_step<float> stored rows", 1): 282612416,
-                 ("k_step<float> stored rows", 2): 289523476}
+# Bytes per step round (one Chebyshev step of every chain of the batch; the
+# lanes split the same blocks, so the bytes per round do not depend on them)
+# that the L2 exchanges with the memory fabric, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (one counter per run), each scaled by what the same counter reads
+# for a plain 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); keyed by kernel,
+# chains of 32^3, site pairs per thread and non-temporal access, and valid only
+# for the kernel source they were taken with (sha256 below), else null.
+TRAFFIC_KERNEL_SHA256 = "a73326d0c868bbaf39cc262ccbfe20980c35fba0a01f43e24db7d5711fa369d8"
+TRAFFIC_BYTES = {("k_step<float>", 64, 2, 0): 213055887,
+                 ("k_step_ov<float>", 64, 2, 0): 84213530,
+                 ("k_step<float>", 128, 1, 1): 422888266,
+                 ("k_step<double>", 64, 1, 1): 421339849}
 
 
 def note(msg: str):
@@ -109,12 +108,12 @@ def tune(batch, fixed: str):
         batch.autotune(64)
 
 
-def traffic_bytes(kernel: str, ppt: int):
+def traffic_bytes(kernel: str, chains: int, ppt: int, nt: int = 0):
     import hashlib
     src = os.path.join(ROOT, "paper_1303_6016_amd", "csrc", "gfmc_kernels.hip")
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != TRAFFIC_KERNEL_SHA256:
         return None
-    return TRAFFIC_BYTES.get((kernel, ppt))
+    return TRAFFIC_BYTES.get((kernel, chains, ppt, int(nt)))
 
 
 def host_cpu():
@@ -241,6 +240,7 @@ def hbm_regime(g, torch, dev, fixed: str, nprop: int = 2):
         kern = "k_step<float>" if prec == g.FP32_ACC64 else "k_step<double>"
         out.append({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "kernel": kern,
+                    "traffic": traffic_bytes(kern, nch, ppt, nt),
                     "workload": f"{nch} chains of 32^3, M=2048, "
                                 f"{'FP32 recursion / FP64 sums' if prec else 'FP64'}",
                     "working_set_bytes": ws, "pairs_per_thread": ppt, "lanes": lanes,
@@ -732,7 +732,7 @@ def main():
     bytes_per_round = NCHAIN * bytes_per_step
     achieved = bytes_per_round / avg_round_s / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes("k_step<float>", ppt),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes("k_step<float>", NCHAIN, ppt, nt),
             "kernel": "k_step<float>", "lanes": lanes,
             "round": "one Chebyshev step of all chains" +
                      (": two concurrent k_step launches, one per lane" if lanes == 2 else
@@ -823,7 +823,7 @@ def main():
             "roofline": {"bound": "hbm", "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": traffic_bytes(kern, pppt),
+                         "traffic": traffic_bytes(kern, NCHAIN, pppt),
                          "kernel": kern, "lanes": plan, "round": rnd,
                          "avg_round_us": pavg * 1e6,
                          "bytes_per_round": prop_bytes * nps / max(nl_tot, 1)}}
@@ -859,7 +859,7 @@ def main():
             "avg_round_us": havg * 1e6, "bytes_per_round": NCHAIN * hbytes,
             "achieved_GBs": NCHAIN * hbytes / havg / 1e9,
             "slowdown_vs_recompute": havg / avg_round_s,
-            "traffic": traffic_bytes("k_step<float> stored rows", ppt)}
+            "traffic": traffic_bytes("k_step<float> stored rows", NCHAIN, ppt)}
         hb.close()
         del hch
 
