@@ -175,6 +175,16 @@ __device__ inline void hop_spinor<float>(const spn<float>& a, const spn<float>& 
   im = fmaf(ti, sh, ti * sl);
 }
 
+// Per-field selects (a struct-valued ?: can go through scratch memory).
+template <typename T>
+__device__ inline spn<T> pick(bool c, const spn<T>& a, const spn<T>& b) {
+  return spn<T>{c ? a.ar : b.ar, c ? a.ai : b.ai, c ? a.br : b.br, c ? a.bi : b.bi};
+}
+template <typename T>
+__device__ inline cpx<T> pick(bool c, const cpx<T>& a, const cpx<T>& b) {
+  return cpx<T>{c ? a.x : b.x, c ? a.y : b.y};
+}
+
 // (ar, ai) += (hr + i hi) a with the four products fused in a fixed order, so
 // that every form of the step (one step or two per launch, the LDS-resident
 // and the persistent kernels, whatever the compiler makes of the code around
@@ -1161,29 +1171,48 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
     split_half(h, D, k, y, z);
     const int bo = (y + z + po) & 1, bn = bo ^ 1;   // x = 2k + b of the o- and v-site
     cpx<T> ao, av, aop;
-    // each site's loads issued together, before its arithmetic (one memory
-    // round trip per site instead of one per direction; issuing both sites'
-    // loads at once measured no faster in FP32 and slower in FP64, whose
-    // registers then halve the occupancy)
+    // Each site's loads are issued together, before its arithmetic (one
+    // memory round trip per site instead of one per direction; issuing both
+    // sites' loads at once measured no faster in FP32 and slower in FP64,
+    // whose registers then halve the occupancy).  One x neighbour of either
+    // site is the pair's other site (same half-row index, other parity):
+    // the o-site takes that neighbour's spinor and a^o_{s-1} from the
+    // v-site's own loads, the v-site takes the o-site's spinor, so a pair
+    // loads 26 values instead of 29 (the sums keep their order).
+    const spn<T> sio = ld(sp_o + h), siv = ld(sp_n + h);
     {
       int nh[6];
       nb6_half(h, k, bo, y, z, L, nh);
-      const spn<T> si = ld(sp_o + h);
+      const int dx = bo ? 0 : 1;   // the x direction whose neighbour is another pair
       spn<T> sj[6];
       cpx<T> an[6], pr = {(T)0, (T)0};
+      const spn<T> sjx = ld(sp_n + nh[dx]);
+      cpx<T> anx = {(T)0, (T)0};
+      if (FIRST) {
+        aop.x = (h == o_half) ? (T)1 : (T)0;
+        aop.y = 0;
+        anx.x = (nh[dx] == o_half) ? (T)1 : (T)0;
+      } else {
+        aop = ld(vo + (size_t)pn * half + h);
+        anx = ld(vo + (size_t)pn * half + nh[dx]);
+      }
 #pragma unroll
-      for (int d = 0; d < 6; ++d) {
+      for (int d = 2; d < 6; ++d) {
         sj[d] = ld(sp_n + nh[d]);
         if (FIRST) { an[d].x = (nh[d] == o_half) ? (T)1 : (T)0; an[d].y = 0; }
         else an[d] = ld(vo + (size_t)pn * half + nh[d]);
       }
       if (!FIRST) pr = ld(vo + (size_t)po * half + h);
       STEP_LOADS_ISSUED();
+      sj[0] = pick(bo, sjx, siv);
+      sj[1] = pick(bo, siv, sjx);
+      an[0] = pick(bo, anx, aop);
+      an[1] = pick(bo, aop, anx);
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         T hr, hi_;
-        hop_spinor(si, sj[d], hsc, hr, hi_);
+        hop_spinor(sio, sj[d], hsc, hr, hi_);
         cmac(hr, hi_, an[d], ar, ai);
       }
       ao.x = two * ar - pr.x;
@@ -1193,32 +1222,40 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
     {
       int nh[6];
       nb6_half(h, k, bn, y, z, L, nh);
-      const spn<T> si = ld(sp_n + h);
+      const int dx = bn ? 0 : 1;
       spn<T> sj[6];
       cpx<T> an[6], pr = {(T)0, (T)0};
+      const spn<T> sjx = ld(sp_o + nh[dx]);
+      cpx<T> anx, anh;   // the other-x neighbour's and the o-site's a^v_{s-1}
+      if (FIRST) {
+        anx = v0(nh[dx]);
+        anh = v0(h);
+      } else {
+        anx = ld(vv + (size_t)po * half + nh[dx]);
+        anh = ld(vv + (size_t)po * half + h);
+      }
 #pragma unroll
-      for (int d = 0; d < 6; ++d) {
+      for (int d = 2; d < 6; ++d) {
         sj[d] = ld(sp_o + nh[d]);
         an[d] = FIRST ? v0(nh[d]) : ld(vv + (size_t)po * half + nh[d]);
       }
-      if (!FIRST) {
-        pr = ld(vv + (size_t)pn * half + h);
-        aop = ld(vo + (size_t)pn * half + h);
-      }
+      if (!FIRST) pr = ld(vv + (size_t)pn * half + h);
       STEP_LOADS_ISSUED();
+      sj[0] = pick(bn, sjx, sio);
+      sj[1] = pick(bn, sio, sjx);
+      an[0] = pick(bn, anx, anh);
+      an[1] = pick(bn, anh, anx);
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
         T hr, hi_;
-        hop_spinor(si, sj[d], hsc, hr, hi_);
+        hop_spinor(siv, sj[d], hsc, hr, hi_);
         cmac(hr, hi_, an[d], ar, ai);
       }
       av.x = two * ar - pr.x;
       av.y = two * ai - pr.y;
       st(vv + (size_t)pn * half + h, av);
       if (FIRST) {
-        aop.x = (h == o_half) ? (T)1 : (T)0;
-        aop.y = 0;
         st(vo + (size_t)pn * half + h, aop);
         st(vv + (size_t)po * half + h, v0(h));
       }
