@@ -197,6 +197,22 @@ gfmc_status gfmc_get_spins(gfmc_chain* chain, double* theta, double* phi);
 gfmc_status gfmc_set_counter(gfmc_chain* chain, int64_t index);
 gfmc_status gfmc_get_counter(gfmc_chain* chain, int64_t* index);
 
+/* Failure detection.  Number of the chain's proposals whose Delta S_eff
+ * (eq. "d_seff2") came out non-finite since creation: each was rejected,
+ * whatever a forced decision said, and left the chain unchanged.  A growing
+ * count means the chain's state is corrupted (e.g. non-finite angles written
+ * into its workspace); other chains of a batch are unaffected.  Waits for the
+ * chain's stream.  EINVAL for NULL arguments. */
+gfmc_status gfmc_chain_nonfinite(gfmc_chain* chain, int64_t* count);
+
+/* Device addresses of the chain's spin angles theta, phi (N doubles each,
+ * site order as gfmc_set_spins) inside its caller-owned workspace, for reading
+ * them without a copy to the host.  Values written there bypass
+ * gfmc_set_spins's validation and the spinor cache (which gfmc_set_spins
+ * rebuilds); the library reads them when it forms a proposal's bond changes.
+ * EINVAL for NULL arguments. */
+gfmc_status gfmc_chain_device_angles(gfmc_chain* chain, double** theta, double** phi);
+
 /* Local moments mu_n^{jk} = <j|T_n(Ht)|k>, n < M, around `site` for the current
  * spins (no state change): the Chebyshev moments of Section 2.2 from M/2 steps
  * of the recursion (equation "recursive") with doubling (equation "mu2"),

@@ -79,6 +79,8 @@ _SIGS = {
     "gfmc_get_spins": [_vp, _P(_d), _P(_d)],
     "gfmc_set_counter": [_vp, _i64],
     "gfmc_get_counter": [_vp, _P(_i64)],
+    "gfmc_chain_nonfinite": [_vp, _P(_i64)],
+    "gfmc_chain_device_angles": [_vp, _P(_vp), _P(_vp)],
     "gfmc_moments": [_vp, _i32, _P(_d)],
     "gfmc_delta_seff": [_vp, _i32, _d, _d, _P(_d), _P(_d)],
     "gfmc_pair_moments": [_vp, _i32, _d, _d, _P(_d)],
@@ -255,6 +257,18 @@ class Chain:
         v = ctypes.c_int64()
         _check(lib().gfmc_get_counter(self.h, ctypes.byref(v)))
         return v.value
+
+    def nonfinite(self) -> int:
+        """Proposals rejected because their Delta S_eff was not finite."""
+        v = ctypes.c_int64()
+        _check(lib().gfmc_chain_nonfinite(self.h, ctypes.byref(v)))
+        return v.value
+
+    def device_angles(self):
+        """Device addresses (theta, phi) of the spin angles in the workspace."""
+        th, ph = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().gfmc_chain_device_angles(self.h, ctypes.byref(th), ctypes.byref(ph)))
+        return th.value, ph.value
 
     def moments(self, site: int) -> np.ndarray:
         out = np.zeros((self.p.M, 7, 7, 2))

@@ -780,6 +780,23 @@ gfmc_status gfmc_get_counter(gfmc_chain* c, int64_t* index) {
   return GFMC_OK;
 }
 
+gfmc_status gfmc_chain_nonfinite(gfmc_chain* c, int64_t* count) {
+  if (!c || !count) return fail(GFMC_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpyAsync(count, &c->desc.ctl->nonfinite, sizeof(*count), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_chain_device_angles(gfmc_chain* c, double** theta, double** phi) {
+  if (!c || !theta || !phi) return fail(GFMC_EINVAL, "NULL argument");
+  *theta = c->desc.theta;
+  *phi = c->desc.phi;
+  return GFMC_OK;
+}
+
 gfmc_status gfmc_moments(gfmc_chain* c, int32_t site, double* mu) {
   CHK(check_chain(c));
   if (site < 0 || site >= c->d.N) return fail(GFMC_EINVAL, "site out of range");

@@ -39,6 +39,7 @@ struct alignas(16) spn {   // chi = (alpha, beta) = (cos(th/2) e^{-i ph/2}, sin(
 struct Ctl {
   int64_t index;            // counter value of the next proposal
   int64_t accepted_total;   // accepted proposals since creation
+  int64_t nonfinite;        // proposals whose Delta S_eff was not finite (rejected)
   int32_t mode;             // 0 draw from the counter, 1 host-given site+angles, 2 site only
   int32_t site;             // proposed site o
   int32_t parity_o;         // (x+y+z) & 1 of o

@@ -617,24 +617,60 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
     // arithmetic (one memory round trip): left to itself the compiler keeps
     // registers low by waiting for each direction's loads in turn, and the
     // kernel becomes bound by the latency of those round trips.
+    //   One x neighbour of either site is the pair's other site (same
+    // half-row index, other parity): the o-site takes that neighbour's
+    // spinor and a^o_{s-1} from the n-site's own loads, the n-site takes the
+    // o-site's spinor (three loads fewer per pair; the sums keep their order).
+    // FP32 steps only: in FP64 the values held from one phase to the next
+    // cost more registers than the three loads save (measured slower).
+    constexpr bool DEDUP = sizeof(T) == 4;
+    spn<T> s_o, s_n;   // the pair's own spinors
+    cpx<T> aop;        // a^o_{s-1} at the n-site
     {
       int nh[6];
       nb6_half(h, k, bo, y, z, L, nh);
-      spn<T> si, sj[6];
+      const int dx = bo ? 0 : 1;   // the x direction whose neighbour is another pair
+      spn<T> sj[6];
       six<T> row;
       cpx<T> an[6], pr = {(T)0, (T)0};
       if (HOPS) {
         row = hrow.ld((size_t)po * half + h);
       } else if (!COH) {
-        si = ld(sp_o + h);
+        s_o = ld(sp_o + h);
+        if (DEDUP) {
+          s_n = ld(sp_n + h);
+          const spn<T> sjx = ld(sp_n + nh[dx]);
 #pragma unroll
-        for (int d = 0; d < 6; ++d) sj[d] = ld(sp_n + nh[d]);
+          for (int d = 2; d < 6; ++d) sj[d] = ld(sp_n + nh[d]);
+          sj[0] = pick(bo != 0, sjx, s_n);
+          sj[1] = pick(bo != 0, s_n, sjx);
+        } else {
+#pragma unroll
+          for (int d = 0; d < 6; ++d) sj[d] = ld(sp_n + nh[d]);
+        }
       }
+      if (FIRST) {
+        aop.x = (h == o_half) ? (T)1 : (T)0;
+        aop.y = 0;
 #pragma unroll
-      for (int d = 0; d < 6; ++d) {
-        if (FIRST) { an[d].x = (nh[d] == o_half) ? (T)1 : (T)0; an[d].y = 0; }
-        else if (COH && nb_elsewhere(nh[d])) an[d] = ld_coh(vo + (size_t)pn * half + nh[d]);
-        else an[d] = ld(vo + (size_t)pn * half + nh[d]);
+        for (int d = 0; d < 6; ++d) { an[d].x = (nh[d] == o_half) ? (T)1 : (T)0; an[d].y = 0; }
+      } else if (!DEDUP) {
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          if (COH && nb_elsewhere(nh[d])) an[d] = ld_coh(vo + (size_t)pn * half + nh[d]);
+          else an[d] = ld(vo + (size_t)pn * half + nh[d]);
+        }
+      } else {
+        aop = ld(vo + (size_t)pn * half + h);
+        const cpx<T> anx = (COH && nb_elsewhere(nh[dx])) ? ld_coh(vo + (size_t)pn * half + nh[dx])
+                                                          : ld(vo + (size_t)pn * half + nh[dx]);
+#pragma unroll
+        for (int d = 2; d < 6; ++d) {
+          if (COH && nb_elsewhere(nh[d])) an[d] = ld_coh(vo + (size_t)pn * half + nh[d]);
+          else an[d] = ld(vo + (size_t)pn * half + nh[d]);
+        }
+        an[0] = pick(bo != 0, anx, aop);
+        an[1] = pick(bo != 0, aop, anx);
       }
       if (!FIRST) pr = NT ? ld_nt(vo + (size_t)po * half + h) : ld(vo + (size_t)po * half + h);
       STEP_LOADS_ISSUED();
@@ -649,7 +685,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
           hr = po ? hp[1][d].x : hp[0][d].x;
           hi_ = po ? hp[1][d].y : hp[0][d].y;
         } else {
-          hop_spinor(si, sj[d], hsc, hr, hi_);
+          hop_spinor(s_o, sj[d], hsc, hr, hi_);
         }
         cmac(hr, hi_, an[d], ar, ai);
       }
@@ -669,17 +705,17 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
     // the directions in one group (FP32) or two (FP64).
     {
       constexpr int kGroup = COH ? (sizeof(T) == 4 ? 6 : 3) : 2;
-      spn<T> si;
+      static_assert(kGroup >= 2, "the first group holds both x directions");
       six<T> row;
       if (HOPS) row = hrow.ld((size_t)pn * half + h);
-      else if (!COH) si = ld(sp_n + h);
+      else if (!DEDUP && !COH) s_n = ld(sp_n + h);
       T accr[6], acci[6];
 #pragma unroll
       for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
       six<T> prev;
-      cpx<T> aop;   // a^o_{s-1} at the n-site
       int nhn[6];
       nb6_half(h, k, bn, y, z, L, nhn);
+      const int dxn = bn ? 0 : 1;   // the x direction whose neighbour is another pair
 #pragma unroll
       for (int d0 = 0; d0 < 6; d0 += kGroup) {
         int nh[kGroup];
@@ -687,9 +723,14 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
         six<T> an[kGroup];
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) nh[g] = nhn[d0 + g];
+        if (DEDUP && !HOPS && !COH && d0 == 0) {
+          const spn<T> sjx = ld(sp_o + nhn[dxn]);
+          sj[0] = pick(bn != 0, sjx, s_o);
+          sj[1] = pick(bn != 0, s_o, sjx);
+        }
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
-          if (!HOPS && !COH) sj[g] = ld(sp_o + nh[g]);
+          if (!HOPS && !COH && (!DEDUP || d0 + g >= 2)) sj[g] = ld(sp_o + nh[g]);
           if (FIRST) {
 #pragma unroll
             for (int e = 0; e < 6; ++e) {
@@ -703,7 +744,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
         }
         if (d0 + kGroup >= 6 && !FIRST) {   // the site's own values ride with the last group
           prev = NT ? vn.ld_nt((size_t)pn * half + h) : vn.ld((size_t)pn * half + h);
-          aop = ld(vo + (size_t)pn * half + h);
+          if (!DEDUP) aop = ld(vo + (size_t)pn * half + h);
         }
         STEP_LOADS_ISSUED();
 #pragma unroll
@@ -717,7 +758,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
             hr = pn ? hp[1][d].x : hp[0][d].x;
             hi_ = pn ? hp[1][d].y : hp[0][d].y;
           } else {
-            hop_spinor(si, sj[g], hsc, hr, hi_);
+            hop_spinor(s_n, sj[g], hsc, hr, hi_);
           }
 #pragma unroll
           for (int e = 0; e < 6; ++e) {
@@ -739,10 +780,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
       }
       if (NT) vn.st_nt((size_t)pn * half + h, out);
       else vn.st((size_t)pn * half + h, out);
-      if (FIRST) {
-        aop.x = (h == o_half) ? (T)1 : (T)0;
-        aop.y = 0;
-        // store a_0 on the sites that hold it from now on
+      if (FIRST) {   // store a_0 on the sites that hold it from now on
         st(vo + (size_t)pn * half + h, aop);
         six<T> u;
 #pragma unroll
@@ -1863,10 +1901,14 @@ __global__ __launch_bounds__(kReconThreads) void k_recon(const Desc* __restrict_
     ctl->dseff = ds;
     ctl->phase_top = ptop;
     if (ctl->mode == 0 && !failed) {
+      // a non-finite Delta S (corrupted chain state) is rejected whatever the
+      // forcing, and counted, so that the chain is flagged and left unchanged
+      const bool finite = isfinite(ds);
       const double u = ctl->u;
-      const int own = (ds <= 0.0 || u < exp(-ds)) ? 1 : 0;
+      const int own = (finite && (ds <= 0.0 || u < exp(-ds))) ? 1 : 0;
       const int f = force ? force[c] : -1;
-      const int acc = f < 0 ? own : (f ? 1 : 0);
+      const int acc = !finite ? 0 : (f < 0 ? own : (f ? 1 : 0));
+      if (!finite) ctl->nonfinite += 1;
       const int o = ctl->site;
       if (recs) {
         gfmc_step_record& R = recs[c];
