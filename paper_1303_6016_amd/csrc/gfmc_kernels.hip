@@ -1151,7 +1151,18 @@ __device__ inline double sum_run(const double* __restrict__ src, int n) {
 // P^{vv}_s = <a^v_s|a^v_s> and Q^{ov}_s = <a^o_{s-1}|a^v_s> (4 real numbers;
 // the pairs that vanish on a bipartite lattice are not formed) with wavefront
 // shuffles and one LDS step.
-template <typename T, bool FIRST, int PPT>
+//   A thread takes YP site pairs of one column: the same half-row index k in
+// rows y0 .. y0 + YP - 1 of one z-plane (y0 a multiple of YP; thread j of a
+// chain takes rows YP (j / (L/2)) onward, so the threads of a wave cover whole
+// row segments).  The pair's two sites alternate between the x offsets of a
+// row, so the y+1 neighbour of a pair's o-site is the next pair's v-site and
+// the y+1 neighbour of its v-site is the next pair's o-site (and the same for
+// y-1): inside a column those spinors and values come from the thread's own
+// loads.  A pair alone loads 26 values (own spinors, values and the x
+// neighbour that is the pair's other site shared as well); two pairs of a
+// column load 44.  Every site's sum runs over the six directions in the same
+// order as the other kernels, so the vector values do not depend on YP.
+template <typename T, bool FIRST, int YP>
 __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict__ descs,
                                                           const int* __restrict__ blkoff,
                                                           int nact, int s_arg,
@@ -1171,7 +1182,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
   const int s = chain_step(s_arg, act_end, c, D.S);
   if (s == 0) return;   // uniform over the block: the chain does not step now
   const int lb = gb - blkoff[c];
-  const int L = D.L, half = D.half;
+  const int L = D.L, half = D.half, hx = L >> 1;
   const Ctl* ctl = D.ctl;
   const int pO = ctl->parity_o;
   const int po = pO ^ (s & 1);          // parity of the sites that carry a^o_s
@@ -1200,109 +1211,148 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
       if (hh == sh[e]) { r.x += dr[e]; r.y += di[e]; }
     return r;
   };
+  auto ind = [&](int hh) {   // a^o_0 = |o> at half-row index hh (o's parity)
+    cpx<T> r;
+    r.x = (hh == o_half) ? (T)1 : (T)0;
+    r.y = 0;
+    return r;
+  };
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int p = 0; p < PPT; ++p) {
-    const int h = (lb * PPT + p) * kStepThreads + (int)threadIdx.x;
-    if (h >= half) continue;
-    int k, y, z;
-    split_half(h, D, k, y, z);
-    const int bo = (y + z + po) & 1, bn = bo ^ 1;   // x = 2k + b of the o- and v-site
-    cpx<T> ao, av, aop;
-    // Each site's loads are issued together, before its arithmetic (one
-    // memory round trip per site instead of one per direction; issuing both
-    // sites' loads at once measured no faster in FP32 and slower in FP64,
-    // whose registers then halve the occupancy).  One x neighbour of either
-    // site is the pair's other site (same half-row index, other parity):
-    // the o-site takes that neighbour's spinor and a^o_{s-1} from the
-    // v-site's own loads, the v-site takes the o-site's spinor, so a pair
-    // loads 26 values instead of 29 (the sums keep their order).
-    const spn<T> sio = ld(sp_o + h), siv = ld(sp_n + h);
-    {
-      int nh[6];
-      nb6_half(h, k, bo, y, z, L, nh);
-      const int dx = bo ? 0 : 1;   // the x direction whose neighbour is another pair
-      spn<T> sj[6];
-      cpx<T> an[6], pr = {(T)0, (T)0};
-      const spn<T> sjx = ld(sp_n + nh[dx]);
-      cpx<T> anx = {(T)0, (T)0};
-      if (FIRST) {
-        aop.x = (h == o_half) ? (T)1 : (T)0;
-        aop.y = 0;
-        anx.x = (nh[dx] == o_half) ? (T)1 : (T)0;
-      } else {
-        aop = ld(vo + (size_t)pn * half + h);
-        anx = ld(vo + (size_t)pn * half + nh[dx]);
-      }
-#pragma unroll
-      for (int d = 2; d < 6; ++d) {
-        sj[d] = ld(sp_n + nh[d]);
-        if (FIRST) { an[d].x = (nh[d] == o_half) ? (T)1 : (T)0; an[d].y = 0; }
-        else an[d] = ld(vo + (size_t)pn * half + nh[d]);
-      }
-      if (!FIRST) pr = ld(vo + (size_t)po * half + h);
-      STEP_LOADS_ISSUED();
-      sj[0] = pick(bo, sjx, siv);
-      sj[1] = pick(bo, siv, sjx);
-      an[0] = pick(bo, anx, aop);
-      an[1] = pick(bo, aop, anx);
-      T ar = 0, ai = 0;
-#pragma unroll
-      for (int d = 0; d < 6; ++d) {
-        T hr, hi_;
-        hop_spinor(sio, sj[d], hsc, hr, hi_);
-        cmac(hr, hi_, an[d], ar, ai);
-      }
-      ao.x = two * ar - pr.x;
-      ao.y = two * ai - pr.y;
-      st(vo + (size_t)po * half + h, ao);
+  const int j = lb * kStepThreads + (int)threadIdx.x;
+  if (j < half / YP) {
+    int k, y0, z, h0;
+    if (YP == 1) {
+      split_half(j, D, k, y0, z);
+      h0 = j;
+    } else {
+      const int r = (int)fdiv((uint32_t)j, D.div_hx);
+      k = j - r * hx;
+      const int R = r * YP;   // row index y + L z of the column's first pair
+      z = (int)fdiv((uint32_t)R, D.div_L);
+      y0 = R - z * L;
+      h0 = R * hx + k;
     }
-    {
-      int nh[6];
-      nb6_half(h, k, bn, y, z, L, nh);
-      const int dx = bn ? 0 : 1;
-      spn<T> sj[6];
-      cpx<T> an[6], pr = {(T)0, (T)0};
-      const spn<T> sjx = ld(sp_o + nh[dx]);
-      cpx<T> anx, anh;   // the other-x neighbour's and the o-site's a^v_{s-1}
-      if (FIRST) {
-        anx = v0(nh[dx]);
-        anh = v0(h);
-      } else {
-        anx = ld(vv + (size_t)po * half + nh[dx]);
-        anh = ld(vv + (size_t)po * half + h);
-      }
+    const int b0 = (y0 + z + po) & 1;   // x = 2k + b of the first pair's o-site
+    // Each phase's loads are issued together, before its arithmetic (one
+    // memory round trip per phase; issuing both phases' loads at once
+    // measured no faster in FP32 and slower in FP64, whose registers then
+    // halve the occupancy).
+    spn<T> sio[YP], siv[YP];
+    cpx<T> aop[YP], anh[YP], ao[YP], av[YP];
+    {   // a^o_s on the o-sites
+      int nh[YP][6];
+      spn<T> sj[YP][6], sjx[YP];
+      cpx<T> an[YP][6], anx[YP], pr[YP];
 #pragma unroll
-      for (int d = 2; d < 6; ++d) {
-        sj[d] = ld(sp_o + nh[d]);
-        an[d] = FIRST ? v0(nh[d]) : ld(vv + (size_t)po * half + nh[d]);
+      for (int q = 0; q < YP; ++q) {
+        const int h = h0 + q * hx, bo = b0 ^ (q & 1);
+        nb6_half(h, k, bo, y0 + q, z, L, nh[q]);
+        const int nx = bo ? nh[q][0] : nh[q][1];   // the x neighbour that is another pair
+        sio[q] = ld(sp_o + h);
+        siv[q] = ld(sp_n + h);
+        sjx[q] = ld(sp_n + nx);
+        if (FIRST) {
+          aop[q] = ind(h);
+          anx[q] = ind(nx);
+        } else {
+          aop[q] = ld(vo + (size_t)pn * half + h);
+          anx[q] = ld(vo + (size_t)pn * half + nx);
+        }
+#pragma unroll
+        for (int d = 2; d < 6; ++d) {
+          if ((d == 2 && q + 1 < YP) || (d == 3 && q > 0)) continue;   // inside the column
+          sj[q][d] = ld(sp_n + nh[q][d]);
+          an[q][d] = FIRST ? ind(nh[q][d]) : ld(vo + (size_t)pn * half + nh[q][d]);
+        }
+        pr[q].x = 0;
+        pr[q].y = 0;
+        if (!FIRST) pr[q] = ld(vo + (size_t)po * half + h);
       }
-      if (!FIRST) pr = ld(vv + (size_t)pn * half + h);
       STEP_LOADS_ISSUED();
-      sj[0] = pick(bn, sjx, sio);
-      sj[1] = pick(bn, sio, sjx);
-      an[0] = pick(bn, anx, anh);
-      an[1] = pick(bn, anh, anx);
-      T ar = 0, ai = 0;
 #pragma unroll
-      for (int d = 0; d < 6; ++d) {
-        T hr, hi_;
-        hop_spinor(siv, sj[d], hsc, hr, hi_);
-        cmac(hr, hi_, an[d], ar, ai);
-      }
-      av.x = two * ar - pr.x;
-      av.y = two * ai - pr.y;
-      st(vv + (size_t)pn * half + h, av);
-      if (FIRST) {
-        st(vo + (size_t)pn * half + h, aop);
-        st(vv + (size_t)po * half + h, v0(h));
+      for (int q = 0; q < YP; ++q) {
+        const int h = h0 + q * hx, bo = b0 ^ (q & 1);
+        // the other x direction's neighbour is the pair's own v-site
+        sj[q][0] = pick(bo, sjx[q], siv[q]);
+        sj[q][1] = pick(bo, siv[q], sjx[q]);
+        an[q][0] = pick(bo, anx[q], aop[q]);
+        an[q][1] = pick(bo, aop[q], anx[q]);
+        if (q + 1 < YP) { sj[q][2] = siv[q + 1]; an[q][2] = aop[q + 1]; }
+        if (q > 0) { sj[q][3] = siv[q - 1]; an[q][3] = aop[q - 1]; }
+        T ar = 0, ai = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          T hr, hi_;
+          hop_spinor(sio[q], sj[q][d], hsc, hr, hi_);
+          cmac(hr, hi_, an[q][d], ar, ai);
+        }
+        ao[q].x = two * ar - pr[q].x;
+        ao[q].y = two * ai - pr[q].y;
+        st(vo + (size_t)po * half + h, ao[q]);
       }
     }
-    const double aor = ao.x, aoi = ao.y, avr = av.x, avi = av.y, apr = aop.x, api = aop.y;
-    acc[0] += aor * aor + aoi * aoi;
-    acc[1] += avr * avr + avi * avi;
-    acc[2] += apr * avr + api * avi;
-    acc[3] += apr * avi - api * avr;
+    {   // a^v_s on the v-sites
+      int nh[YP][6];
+      spn<T> sj[YP][6], sjx[YP];
+      cpx<T> an[YP][6], anx[YP], pr[YP];
+#pragma unroll
+      for (int q = 0; q < YP; ++q) {
+        const int h = h0 + q * hx, bn = b0 ^ (q & 1) ^ 1;
+        nb6_half(h, k, bn, y0 + q, z, L, nh[q]);
+        const int nx = bn ? nh[q][0] : nh[q][1];
+        sjx[q] = ld(sp_o + nx);
+        if (FIRST) {
+          anh[q] = v0(h);
+          anx[q] = v0(nx);
+        } else {
+          anh[q] = ld(vv + (size_t)po * half + h);
+          anx[q] = ld(vv + (size_t)po * half + nx);
+        }
+#pragma unroll
+        for (int d = 2; d < 6; ++d) {
+          if ((d == 2 && q + 1 < YP) || (d == 3 && q > 0)) continue;
+          sj[q][d] = ld(sp_o + nh[q][d]);
+          an[q][d] = FIRST ? v0(nh[q][d]) : ld(vv + (size_t)po * half + nh[q][d]);
+        }
+        pr[q].x = 0;
+        pr[q].y = 0;
+        if (!FIRST) pr[q] = ld(vv + (size_t)pn * half + h);
+      }
+      STEP_LOADS_ISSUED();
+#pragma unroll
+      for (int q = 0; q < YP; ++q) {
+        const int h = h0 + q * hx, bn = b0 ^ (q & 1) ^ 1;
+        sj[q][0] = pick(bn, sjx[q], sio[q]);
+        sj[q][1] = pick(bn, sio[q], sjx[q]);
+        an[q][0] = pick(bn, anx[q], anh[q]);
+        an[q][1] = pick(bn, anh[q], anx[q]);
+        if (q + 1 < YP) { sj[q][2] = sio[q + 1]; an[q][2] = anh[q + 1]; }
+        if (q > 0) { sj[q][3] = sio[q - 1]; an[q][3] = anh[q - 1]; }
+        T ar = 0, ai = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          T hr, hi_;
+          hop_spinor(siv[q], sj[q][d], hsc, hr, hi_);
+          cmac(hr, hi_, an[q][d], ar, ai);
+        }
+        av[q].x = two * ar - pr[q].x;
+        av[q].y = two * ai - pr[q].y;
+        st(vv + (size_t)pn * half + h, av[q]);
+        if (FIRST) {
+          st(vo + (size_t)pn * half + h, aop[q]);
+          st(vv + (size_t)po * half + h, anh[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < YP; ++q) {
+      const double aor = ao[q].x, aoi = ao[q].y, avr = av[q].x, avi = av[q].y;
+      const double apr = aop[q].x, api = aop[q].y;
+      acc[0] += aor * aor + aoi * aoi;
+      acc[1] += avr * avr + avi * avi;
+      acc[2] += apr * avr + api * avi;
+      acc[3] += apr * avi - api * avr;
+    }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v)

@@ -217,38 +217,44 @@ def _two_step_batch(g, prec, shape, vectors):
 
 @pytest.mark.parametrize("prec,vectors", [(0, 1), (1, 1), (1, 2)])
 def test_two_step_shape_matches_one_step_shape_and_oracle(g, prec, vectors):
-    # Shape 3 forms the same vector values as shape 1 (same arithmetic, term for
-    # term) and sums them per tile instead of per block: every proposal's
-    # Delta S agrees to rounding of the FP64 sums, the decisions and final
-    # spins are equal, and the first proposal's Delta S matches the oracle.
+    # Shapes 2 (two site pairs of a y column per thread, sharing their y
+    # neighbours' loads) and 3 (two steps per launch) form the same vector
+    # values as shape 1 (same arithmetic, term for term) and sum them in
+    # another order: every proposal's Delta S agrees to rounding of the FP64
+    # sums, the decisions and final spins are equal, and the first proposal's
+    # Delta S matches the oracle.  L = 24 puts row ends inside blocks.
     nprop = 3
     runs = {}
-    for shape in (1, 3):
+    for shape in (1, 2, 3):
         chs, b = _two_step_batch(g, prec, shape, vectors)
         spins0 = [c.get_spins() for c in chs]
         recs = b.step(nprop, records=True)
         b.close()
         runs[shape] = (recs, [c.get_spins() for c in chs], spins0)
     r1, s1, spins0 = runs[1]
-    r3, s3, _ = runs[3]
-    for q in range(nprop):
-        for i in range(len(TWO_STEP_SPECS)):
-            a, b_ = r1[q][i], r3[q][i]
-            print(f"prop {q} chain {i}: dS {a.dseff:.12f} / {b_.dseff:.12f}", flush=True)
-            assert a.site == b_.site and a.theta_new == b_.theta_new and a.phi_new == b_.phi_new
-            assert abs(a.dseff - b_.dseff) < 1e-9 * max(1.0, abs(a.dseff))
-            assert a.accepted == b_.accepted
-    for (t1, p1), (t3, p3) in zip(s1, s3):
-        assert np.array_equal(t1, t3) and np.array_equal(p1, p3)
     tol = 1e-10 if prec == 0 else 2e-5
-    for i, (L, M, K) in enumerate(TWO_STEP_SPECS):
-        m = oracle.Model(L=L, M=M, K=K, beta=10.0, seed=21, chain_id=i)
-        th, ph = spins0[i]
-        r = r3[0][i]
-        ref = (oracle.delta_seff(m, th, ph, r.site, r.theta_new, r.phi_new) if vectors == 1
-               else oracle.delta_seff_mixed(m, th, ph, r.site, r.theta_new, r.phi_new))
-        print(f"chain {i} L={L} M={M}: dS {r.dseff:.10f} oracle {ref:.10f}", flush=True)
-        assert abs(r.dseff - ref) < tol
+    for shape in (2, 3):
+        r3, s3, _ = runs[shape]
+        for q in range(nprop):
+            for i in range(len(TWO_STEP_SPECS)):
+                a, b_ = r1[q][i], r3[q][i]
+                print(f"shape {shape} prop {q} chain {i}: dS {a.dseff:.12f} / {b_.dseff:.12f}",
+                      flush=True)
+                assert (a.site == b_.site and a.theta_new == b_.theta_new
+                        and a.phi_new == b_.phi_new)
+                assert abs(a.dseff - b_.dseff) < 1e-9 * max(1.0, abs(a.dseff))
+                assert a.accepted == b_.accepted
+        for (t1, p1), (t3, p3) in zip(s1, s3):
+            assert np.array_equal(t1, t3) and np.array_equal(p1, p3)
+        for i, (L, M, K) in enumerate(TWO_STEP_SPECS):
+            m = oracle.Model(L=L, M=M, K=K, beta=10.0, seed=21, chain_id=i)
+            th, ph = spins0[i]
+            r = r3[0][i]
+            ref = (oracle.delta_seff(m, th, ph, r.site, r.theta_new, r.phi_new) if vectors == 1
+                   else oracle.delta_seff_mixed(m, th, ph, r.site, r.theta_new, r.phi_new))
+            print(f"shape {shape} chain {i} L={L} M={M}: dS {r.dseff:.10f} oracle {ref:.10f}",
+                  flush=True)
+            assert abs(r.dseff - ref) < tol
 
 
 def test_two_step_shape_refusals(g):
