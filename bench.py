@@ -34,11 +34,11 @@ HBM_PEAK_GBS = 8000.0
 # for a plain 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); keyed by kernel,
 # chains of 32^3, site pairs per thread and non-temporal access, and valid only
 # for the kernel source they were taken with (sha256 below), else null.
-TRAFFIC_KERNEL_SHA256 = "a73326d0c868bbaf39cc262ccbfe20980c35fba0a01f43e24db7d5711fa369d8"
-TRAFFIC_BYTES = {("k_step<float>", 64, 2, 0): 213055887,
-                 ("k_step_ov<float>", 64, 2, 0): 84213530,
-                 ("k_step<float>", 128, 1, 1): 422888266,
-                 ("k_step<double>", 64, 1, 1): 421339849}
+TRAFFIC_KERNEL_SHA256 = "30562cece4617dd4df64360d1cd24d97b0121f17c1259030182522f83062c2b0"
+TRAFFIC_BYTES = {("k_step<float>", 64, 2, 0): 212672430,
+                 ("k_step_ov<float>", 64, 2, 0): 84205319,
+                 ("k_step<float>", 128, 1, 1): 422904346,
+                 ("k_step<double>", 64, 1, 1): 421323085}
 
 
 def note(msg: str):
