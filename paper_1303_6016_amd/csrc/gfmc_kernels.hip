@@ -570,12 +570,37 @@ struct NoArrive {
   __device__ void operator()() const {}
 };
 
+// The block's 49 Gram sums of step s from the 16 values of each thread's
+// site pair, left in LDS by step s (xw[wave][lane][component]): the same
+// v_mfma_f64_16x16x4 products, in the same order, as the staged form at the
+// end of step_block, so both give the same partial sums bit for bit.  Every
+// thread of the block must call it (it holds a block barrier).
+__device__ __forceinline__ void gram_rows(const Desc& D, const int lb, const int s,
+                                          double (*xw)[64][17], double (*gsum)[256]) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  d4v acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const double val = xw[w][16 * rr + 4 * m + (lane >> 4)][lane & 15];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) gsum[w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < kNP)
+    D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo(gsum, gram_combo_index(t));
+}
+
 template <typename T, bool FIRST, int PPT, bool HOPS, bool NT, bool COH = false,
           typename Arrive = NoArrive>
 __device__ __forceinline__ void step_block(const Desc& D, const int lb, const int s,
                                            double (*xs)[16][17], double (*gsum)[256],
                                            const Arrive& arrive = Arrive(),
-                                           const cpx<T> (*hp)[6] = nullptr) {
+                                           const cpx<T> (*hp)[6] = nullptr,
+                                           double (*xw)[64][17] = nullptr) {
   const int L = D.L, half = D.half;
   const Ctl* ctl = D.ctl;
   const int pO = ctl->parity_o;
@@ -602,14 +627,21 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
   // also keep their site pair's twelve hopping amplitudes in registers for
   // the whole proposal (hp[q][d]: the site of parity q to its neighbour d,
   // formed by the same hop_spinor), so its steps load no spinors.
+  //   It forms a step's Gram sums during the next step, while that step's
+  // loads are in flight (gram_rows, from the 16 values per thread it leaves
+  // in LDS): every thread of its blocks runs each step, a thread past the
+  // lattice on the last site pair with its stores and values dropped, so
+  // that the block barrier inside the sums is reached by all.
   auto nb_elsewhere = [&](int nhh) { return nhh / (kStepThreads * PPT) != lb; };
   double x[PPT][16];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) x[p][i] = 0.0;
-    const int h = (lb * PPT + p) * kStepThreads + (int)threadIdx.x;
-    if (h >= half) continue;
+    const int h0 = (lb * PPT + p) * kStepThreads + (int)threadIdx.x;
+    const bool valid = h0 < half;
+    if (!COH && !valid) continue;
+    const int h = valid ? h0 : half - 1;
     int k, y, z;
     split_half(h, D, k, y, z);
     const int bo = (y + z + po) & 1, bn = bo ^ 1;   // x = 2k + b of the o- and n-site
@@ -626,6 +658,14 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
     constexpr bool DEDUP = sizeof(T) == 4;
     spn<T> s_o, s_n;   // the pair's own spinors
     cpx<T> aop;        // a^o_{s-1} at the n-site
+    // The persistent kernel (one wave per SIMD, registers to spare) issues the
+    // n-site's loads with the o-site's in FP32: one memory round trip per
+    // step (16^3: 514 against 505 proposals/s; in FP64 the values overflow
+    // into the accumulation registers and it measured 4 % slower).
+    constexpr bool MERGE = COH && sizeof(T) == 4;
+    six<T> anm[6], prevm;   // the n-site's neighbour and own values (MERGE)
+    int nhn[6];   // the n-site's neighbours
+    if (MERGE) nb6_half(h, k, bn, y, z, L, nhn);
     {
       int nh[6];
       nb6_half(h, k, bo, y, z, L, nh);
@@ -660,6 +700,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
           if (COH && nb_elsewhere(nh[d])) an[d] = ld_coh(vo + (size_t)pn * half + nh[d]);
           else an[d] = ld(vo + (size_t)pn * half + nh[d]);
         }
+        if (MERGE) aop = ld(vo + (size_t)pn * half + h);
       } else {
         aop = ld(vo + (size_t)pn * half + h);
         const cpx<T> anx = (COH && nb_elsewhere(nh[dx])) ? ld_coh(vo + (size_t)pn * half + nh[dx])
@@ -673,7 +714,16 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
         an[1] = pick(bo != 0, aop, anx);
       }
       if (!FIRST) pr = NT ? ld_nt(vo + (size_t)po * half + h) : ld(vo + (size_t)po * half + h);
+      if (MERGE && !FIRST) {
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+          if (nb_elsewhere(nhn[g])) anm[g] = vn.ld_coh((size_t)po * half + nhn[g]);
+          else anm[g] = vn.ld((size_t)po * half + nhn[g]);
+        }
+        prevm = vn.ld((size_t)pn * half + h);
+      }
       STEP_LOADS_ISSUED();
+      if (COH && !FIRST) gram_rows(D, lb, s - 1, xw, gsum);   // the previous step's sums
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
@@ -692,8 +742,12 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
       cpx<T> ao;
       ao.x = two * ar - pr.x;
       ao.y = two * ai - pr.y;
-      if (NT) st_nt(vo + (size_t)po * half + h, ao);
-      else st(vo + (size_t)po * half + h, ao);
+      if (!valid) {
+      } else if (NT) {
+        st_nt(vo + (size_t)po * half + h, ao);
+      } else {
+        st(vo + (size_t)po * half + h, ao);
+      }
       x[p][14] = (double)ao.x;
       x[p][15] = (double)ao.y;
     }
@@ -702,7 +756,8 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
     // once are too many registers to keep the occupancy; groups of two
     // measured fastest on the HBM-resident batches).  The persistent kernel
     // runs one wave per SIMD, so registers cost it no occupancy: it takes
-    // the directions in one group (FP32) or two (FP64).
+    // the directions in one group (FP32, loaded with the o-site's values) or
+    // two (FP64).
     {
       constexpr int kGroup = COH ? (sizeof(T) == 4 ? 6 : 3) : 2;
       static_assert(kGroup >= 2, "the first group holds both x directions");
@@ -713,8 +768,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
 #pragma unroll
       for (int e = 0; e < 6; ++e) { accr[e] = 0; acci[e] = 0; }
       six<T> prev;
-      int nhn[6];
-      nb6_half(h, k, bn, y, z, L, nhn);
+      if (!MERGE) nb6_half(h, k, bn, y, z, L, nhn);
       const int dxn = bn ? 0 : 1;   // the x direction whose neighbour is another pair
 #pragma unroll
       for (int d0 = 0; d0 < 6; d0 += kGroup) {
@@ -738,13 +792,18 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
               an[g].v[e].y = 0;
             }
           } else {
-            if (COH && nb_elsewhere(nh[g])) an[g] = vn.ld_coh((size_t)po * half + nh[g]);
+            if (MERGE) an[g] = anm[d0 + g];
+            else if (COH && nb_elsewhere(nh[g])) an[g] = vn.ld_coh((size_t)po * half + nh[g]);
             else an[g] = vn.ld((size_t)po * half + nh[g]);
           }
         }
         if (d0 + kGroup >= 6 && !FIRST) {   // the site's own values ride with the last group
-          prev = NT ? vn.ld_nt((size_t)pn * half + h) : vn.ld((size_t)pn * half + h);
-          if (!DEDUP) aop = ld(vo + (size_t)pn * half + h);
+          if (MERGE) {
+            prev = prevm;
+          } else {
+            prev = NT ? vn.ld_nt((size_t)pn * half + h) : vn.ld((size_t)pn * half + h);
+            if (!DEDUP) aop = ld(vo + (size_t)pn * half + h);
+          }
         }
         STEP_LOADS_ISSUED();
 #pragma unroll
@@ -778,9 +837,13 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
         x[p][2 * e] = (double)out.v[e].x;
         x[p][2 * e + 1] = (double)out.v[e].y;
       }
-      if (NT) vn.st_nt((size_t)pn * half + h, out);
-      else vn.st((size_t)pn * half + h, out);
-      if (FIRST) {   // store a_0 on the sites that hold it from now on
+      if (!valid) {
+      } else if (NT) {
+        vn.st_nt((size_t)pn * half + h, out);
+      } else {
+        vn.st((size_t)pn * half + h, out);
+      }
+      if (FIRST && valid) {   // store a_0 on the sites that hold it from now on
         st(vo + (size_t)pn * half + h, aop);
         six<T> u;
 #pragma unroll
@@ -790,8 +853,18 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
       x[p][12] = (double)aop.x;
       x[p][13] = (double)aop.y;
     }
+    if (!valid)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[p][i] = 0.0;
   }
 
+  if (COH) {   // the sums of this step are formed during the next one
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) xw[threadIdx.x >> 6][lane][i] = x[0][i];
+    arrive();
+    return;
+  }
   arrive();
   // Gram matrix of x over the block on the FP64 matrix core:
   // v_mfma_f64_16x16x4 with A = B = 4 columns (site pairs) of 16 components.
@@ -919,7 +992,7 @@ __device__ inline bool die_wait(unsigned* count, unsigned target, unsigned* err,
 
 template <typename T>
 __global__ __launch_bounds__(kStepThreads) void k_persist(const Desc* __restrict__ descs, int nb) {
-  __shared__ double xs[4][16][17];
+  __shared__ double xw[4][64][17];   // each thread's 16 values of the last step
   __shared__ double gsum[4][256];
   __shared__ int tk, ok_sh;
   const Desc& D = descs[0];
@@ -959,11 +1032,12 @@ __global__ __launch_bounds__(kStepThreads) void k_persist(const Desc* __restrict
   }
   const DieArrive arrive{&bar[2]};
   for (int s = 1; s <= D.S; ++s) {
-    if (s == 1) step_block<T, true, 1, false, false, true>(D, lb, 1, xs, gsum, arrive, hp);
-    else step_block<T, false, 1, false, false, true>(D, lb, s, xs, gsum, arrive, hp);
+    if (s == 1) step_block<T, true, 1, false, false, true>(D, lb, 1, nullptr, gsum, arrive, hp, xw);
+    else step_block<T, false, 1, false, false, true>(D, lb, s, nullptr, gsum, arrive, hp, xw);
     if (s == D.S) break;
     if (!die_wait(&bar[2], (unsigned)nb * (unsigned)s, &bar[3], &ok_sh)) return;
   }
+  gram_rows(D, lb, D.S, xw, gsum);   // the last step's sums
 }
 
 // Census of the dies a grid of `blocks` lands on: counts[die] += 1 per block.
