@@ -441,8 +441,13 @@ gfmc_status gfmc_engine_destroy(gfmc_engine* engine);
 /* ----------------------------------------------------- allocation-free --
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): Delta S_eff
- * exactly as gfmc_delta_seff computes it (same kernels, same launch shape,
- * same value), for the spins in the caller's device arrays d_theta[N] and
+ * as gfmc_delta_seff computes it, with the kernels and launch shape of such a
+ * chain in a batch (the LDS-resident kernel where it fits, else one step
+ * launch per Chebyshev step: the same value bit for bit as gfmc_delta_seff
+ * where that takes the same shape; on a lone multi-block chain small enough
+ * for one compute die gfmc_delta_seff runs the persistent kernel, whose block
+ * sums group the sites differently, and the two agree to rounding of the FP64
+ * sums), for the spins in the caller's device arrays d_theta[N] and
  * d_phi[N] (FP64, read only) and the move of `site` to (theta_new, phi_new),
  * with no chain handle and no workspace.  Every intermediate buffer lives in
  * a static device array of the library, 64 MiB per device, held from the

@@ -44,6 +44,10 @@ int fp32_max_moments(int L) {
 }
 constexpr double kFp32MaxBetaT = 50.0;
 
+static int persist_threads(const Derived& d);
+static int persist_blocks(const Derived& d);
+static bool persist_fits(const Derived& d);
+
 gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   if (!p) return fail(GFMC_EINVAL, "params is NULL");
   if (p->L < 2 || p->L > 256 || (p->L & 1))
@@ -96,6 +100,9 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
   d.a = p->scale_a > 0 ? p->scale_a : 6.0 * p->t / (1.0 - 0.01);
   d.lambda = p->lorentz_lambda > 0 ? p->lorentz_lambda : 4.0;
   if (d.a < 6.0 * p->t) return fail(GFMC_EINVAL, "scale_a must be >= 6t (spectrum inside [-1,1])");
+  // partial-sum slots per step: the most blocks any step form of the chain
+  // uses (the persistent kernel's blocks are smaller than the launched ones)
+  d.part_blocks = persist_fits(d) ? std::max(d.nblk, persist_blocks(d)) : d.nblk;
   return GFMC_OK;
 }
 
@@ -115,7 +122,7 @@ Layout layout_of(const Derived& d) {
   l.spin = take((size_t)d.N * 4 * tsz);
   l.hop = take(d.hops ? (size_t)d.N * 6 * 2 * tsz : 0);
   l.vec = take((size_t)(d.ov ? 2 : 7) * d.N * 2 * tsz);
-  l.part = take((size_t)d.S * d.nblk * (d.ov ? kNP2 : kNP) * 8);
+  l.part = take((size_t)d.S * d.part_blocks * (d.ov ? kNP2 : kNP) * 8);
   l.mom = take((size_t)d.M * (d.ov ? 3 : 49) * 16);
   l.gscr = take((size_t)4 * d.K * 16);
   l.tab = take(((size_t)d.M + 2 * (size_t)d.K + (size_t)d.K + 2 * (size_t)d.K) * 8);
@@ -176,11 +183,26 @@ bool resident_ok(const Derived& d) { return resident_fits(d); }
 
 // The persistent single-chain kernel keeps a chain's steps on one die: the
 // chain's vectors and spinors must fit well inside that die's 4 MB L2, and
-// its blocks (one site pair per thread) within the die's 32 compute units.
+// its blocks (one site pair per thread) at most one to each of the die's 32
+// compute units.  Threads per block: 64 while that gives at most 16 blocks,
+// else the fewer of 128 and 256 that gives at most 32 (measured, M = 1024,
+// proposals/s with 64 / 128 / 256: 12^3 FP64 592 / 489 / 434; 16^3 FP64
+// 532 / 564 / 487; 20^3 FP64 - / 434 / 369; 24^3 FP32 - / - / 506).
+static int persist_threads(const Derived& d) {
+  auto blocks = [&](int bt) { return (d.half + bt - 1) / bt; };
+  if (blocks(64) <= 16) return 64;
+  for (int bt : {128, 256})
+    if (blocks(bt) <= kPersistMaxBlocks) return bt;
+  return 0;
+}
+static int persist_blocks(const Derived& d) {
+  const int bt = persist_threads(d);
+  return bt ? (d.half + bt - 1) / bt : 0;
+}
 static bool persist_fits(const Derived& d) {
   const size_t bytes = (size_t)d.N * (d.fp32 ? 72 : 144);
   return !d.ov && !d.hops && !resident_fits(d) && bytes <= ((size_t)3 << 20) &&
-         blocks_of(d, 1) <= 32;
+         persist_threads(d) > 0;
 }
 
 // Blocks are dealt to the dies in turn; the persistent kernel relies on a
@@ -271,7 +293,8 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   P.persist_ctl = nullptr;
   if (P.allow_persist && P.n == 1 && !P.resident && P.ppt == 1 && P.lanes <= 1 && P.d_mag &&
       !P.gexec && persist_fits(sorted[0]->d)) {
-    P.persist = -blocks_of(sorted[0]->d, 1);
+    P.persist = -persist_blocks(sorted[0]->d);
+    P.persist_threads = persist_threads(sorted[0]->d);
     P.persist_ctl = sorted[0]->desc.ctl;
   }
   for (int i = 0; i < P.n; ++i) {
@@ -441,7 +464,7 @@ gfmc_status enqueue_proposal(Plan& P, const int32_t* d_force, gfmc_step_record* 
   if (P.resident) {
     HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
   } else if (P.persist > 0) {
-    HIPCHK(launch_persist(P.fp32, P.d_desc, P.persist, P.stream));
+    HIPCHK(launch_persist(P.fp32, P.d_desc, P.persist, P.persist_threads, P.stream));
   } else {
     CHK(enqueue_steps(P, 1, P.smax));
   }
@@ -1436,7 +1459,8 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
           HIPCHK(launch_propose(P.d_desc, P.n, P.stream));
           HIPCHK(hipStreamSynchronize(P.stream));
           const auto t0 = std::chrono::steady_clock::now();
-          if (P.persist > 0) HIPCHK(launch_persist(P.fp32, P.d_desc, P.persist, P.stream));
+          if (P.persist > 0)
+            HIPCHK(launch_persist(P.fp32, P.d_desc, P.persist, P.persist_threads, P.stream));
           else HIPCHK(launch_resident(P.fp32, P.d_desc, P.n, P.res_lds, P.stream));
           HIPCHK(hipStreamSynchronize(P.stream));
           ms = std::min(ms, wall_ms(t0) / std::max(1, P.smax) * nsteps);

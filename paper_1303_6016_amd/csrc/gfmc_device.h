@@ -9,6 +9,10 @@
 namespace gfmc {
 
 constexpr int kStepThreads = 256;   // threads per block of the Chebyshev step kernel
+constexpr int kStepWaves = kStepThreads / 64;
+// The persistent lone-chain kernel runs blocks of 64, 128 or 256 threads, at
+// most one per compute unit of one die.
+constexpr int kPersistMaxBlocks = 32;
 constexpr int kResThreads = 1024;   // threads of the LDS-resident workgroup (4 waves per SIMD)
 constexpr int kNP = 49;             // moment partial sums per block and step (7 site vectors)
 constexpr int kNP2 = 4;             // ... for the pair {o, v}

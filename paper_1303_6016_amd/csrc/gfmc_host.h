@@ -28,7 +28,7 @@ hipError_t launch_spinors(int fp32, const Desc* d, int n, int nmax, hipStream_t 
 hipError_t launch_hops(int fp32, const Desc* d, int nmax, hipStream_t st);
 hipError_t launch_resident(int fp32, const Desc* d, int n, size_t lds, hipStream_t st);
 // Persistent single-chain step run (cooperative launch of 8 nb blocks, nb work).
-hipError_t launch_persist(int fp32, const Desc* d, int nb, hipStream_t st);
+hipError_t launch_persist(int fp32, const Desc* d, int nb, int threads, hipStream_t st);
 // counts[die] (16 unsigned, zeroed by the caller) += blocks landing on each die.
 hipError_t launch_die_census(unsigned* counts, int blocks, hipStream_t st);
 hipError_t launch_init_spins(const Desc* d, int nmax, int mode, hipStream_t st);
@@ -63,6 +63,7 @@ constexpr int kShapeTile2 = 3;  // launch shape: pair form, two Chebyshev steps 
 // ------------------------------------------------------- chain layout ----
 struct Derived {
   int L, N, half, M, S, K, log2K, nblk, fp32, ov, hops;
+  int part_blocks;   // partial-sum slots per step (the most blocks of any step form)
   double a, lambda;
 };
 
@@ -89,6 +90,7 @@ struct Plan {
                                        // < 0: candidate, pending the die census
   bool allow_persist = false;          // chain and batch plans (not the engine's groups)
   Ctl* persist_ctl = nullptr;          // the lone chain's control block (timeout flag)
+  int persist_threads = 0;             // threads per block of the persistent kernel
   size_t res_lds = 0;                  // dynamic LDS of the resident kernel
   int ov = 0;                          // start vectors {o, v} instead of the 7 sites
   int hops = 0;                        // stored hopping table instead of recompute

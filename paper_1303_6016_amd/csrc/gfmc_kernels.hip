@@ -534,9 +534,16 @@ __device__ inline Combo gram_combo_index(int t) {
   return (q & 1) ? Combo{12 * 16 + 2 * e + 1, 13 * 16 + 2 * e, -1.0}
                  : Combo{12 * 16 + 2 * e, 13 * 16 + 2 * e + 1, 1.0};
 }
+// Sum over the NW waves' Gram matrices (in wave order) of the entries of one
+// of the 49 sums.
+template <int NW = 4>
 __device__ inline double gram_combo(const double (*gsum)[256], const Combo& k) {
-  const double a = gsum[0][k.p1] + gsum[1][k.p1] + gsum[2][k.p1] + gsum[3][k.p1];
-  const double b = gsum[0][k.p2] + gsum[1][k.p2] + gsum[2][k.p2] + gsum[3][k.p2];
+  double a = gsum[0][k.p1], b = gsum[0][k.p2];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    a += gsum[w][k.p1];
+    b += gsum[w][k.p2];
+  }
   return a + k.sg * b;
 }
 
@@ -555,7 +562,7 @@ __device__ inline int chain_step(int s, const int* __restrict__ act_end, int c, 
   return sl == 1 ? 0 : sl;
 }
 
-// Step s of the chain D on its logical block lb (kStepThreads threads, PPT
+// Step s of the chain D on its logical block lb (BT threads, PPT
 // half-row indices per thread): the stencil, the in-place update and the
 // block's 49 Gram sums.  Shared by the one-launch-per-step kernel and the
 // persistent single-chain kernel.
@@ -575,6 +582,7 @@ struct NoArrive {
 // v_mfma_f64_16x16x4 products, in the same order, as the staged form at the
 // end of step_block, so both give the same partial sums bit for bit.  Every
 // thread of the block must call it (it holds a block barrier).
+template <int NW>
 __device__ __forceinline__ void gram_rows(const Desc& D, const int lb, const int s,
                                           double (*xw)[64][17], double (*gsum)[256]) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -591,11 +599,11 @@ __device__ __forceinline__ void gram_rows(const Desc& D, const int lb, const int
   __syncthreads();
   const int t = threadIdx.x;
   if (t < kNP)
-    D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo(gsum, gram_combo_index(t));
+    D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo<NW>(gsum, gram_combo_index(t));
 }
 
 template <typename T, bool FIRST, int PPT, bool HOPS, bool NT, bool COH = false,
-          typename Arrive = NoArrive>
+          typename Arrive = NoArrive, int BT = kStepThreads>
 __device__ __forceinline__ void step_block(const Desc& D, const int lb, const int s,
                                            double (*xs)[16][17], double (*gsum)[256],
                                            const Arrive& arrive = Arrive(),
@@ -632,13 +640,14 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
   // in LDS): every thread of its blocks runs each step, a thread past the
   // lattice on the last site pair with its stores and values dropped, so
   // that the block barrier inside the sums is reached by all.
-  auto nb_elsewhere = [&](int nhh) { return nhh / (kStepThreads * PPT) != lb; };
+  constexpr int NW = BT / 64;   // waves per block
+  auto nb_elsewhere = [&](int nhh) { return nhh / (BT * PPT) != lb; };
   double x[PPT][16];
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) x[p][i] = 0.0;
-    const int h0 = (lb * PPT + p) * kStepThreads + (int)threadIdx.x;
+    const int h0 = (lb * PPT + p) * BT + (int)threadIdx.x;
     const bool valid = h0 < half;
     if (!COH && !valid) continue;
     const int h = valid ? h0 : half - 1;
@@ -723,7 +732,7 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
         prevm = vn.ld((size_t)pn * half + h);
       }
       STEP_LOADS_ISSUED();
-      if (COH && !FIRST) gram_rows(D, lb, s - 1, xw, gsum);   // the previous step's sums
+      if (COH && !FIRST) gram_rows<NW>(D, lb, s - 1, xw, gsum);   // the previous step's sums
       T ar = 0, ai = 0;
 #pragma unroll
       for (int d = 0; d < 6; ++d) {
@@ -899,15 +908,15 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
   __syncthreads();
   const int t = threadIdx.x;
   if (t < kNP)
-    D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo(gsum, gram_combo_index(t));
+    D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo<NW>(gsum, gram_combo_index(t));
 }
 
 template <typename T, bool FIRST, int PPT, bool HOPS, bool NT>
 __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ descs,
                                                        const int* __restrict__ blkoff, int nact,
                                                        int s_arg, const int* __restrict__ act_end) {
-  __shared__ double xs[4][16][17];
-  __shared__ double gsum[4][256];
+  __shared__ double xs[kStepWaves][16][17];
+  __shared__ double gsum[kStepWaves][256];
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
   int c = 0;
   {
@@ -990,10 +999,11 @@ __device__ inline bool die_wait(unsigned* count, unsigned target, unsigned* err,
   return *ok_sh != 0;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kStepThreads) void k_persist(const Desc* __restrict__ descs, int nb) {
-  __shared__ double xw[4][64][17];   // each thread's 16 values of the last step
-  __shared__ double gsum[4][256];
+template <typename T, int BT>
+__global__ __launch_bounds__(BT) void k_persist(const Desc* __restrict__ descs, int nb) {
+  constexpr int NW = BT / 64;
+  __shared__ double xw[NW][64][17];   // each thread's 16 values of the last step
+  __shared__ double gsum[NW][256];
   __shared__ int tk, ok_sh;
   const Desc& D = descs[0];
   unsigned* bar = D.ctl->bar;
@@ -1014,7 +1024,7 @@ __global__ __launch_bounds__(kStepThreads) void k_persist(const Desc* __restrict
   // proposal: hp[q][d] from the site of parity q to its neighbour d
   cpx<T> hp[2][6];
   {
-    const int h = lb * kStepThreads + (int)threadIdx.x;
+    const int h = lb * BT + (int)threadIdx.x;
     const int hh = h < D.half ? h : 0;   // threads past the lattice take none
     int k, y, z;
     split_half(hh, D, k, y, z);
@@ -1032,12 +1042,16 @@ __global__ __launch_bounds__(kStepThreads) void k_persist(const Desc* __restrict
   }
   const DieArrive arrive{&bar[2]};
   for (int s = 1; s <= D.S; ++s) {
-    if (s == 1) step_block<T, true, 1, false, false, true>(D, lb, 1, nullptr, gsum, arrive, hp, xw);
-    else step_block<T, false, 1, false, false, true>(D, lb, s, nullptr, gsum, arrive, hp, xw);
+    if (s == 1)
+      step_block<T, true, 1, false, false, true, DieArrive, BT>(D, lb, 1, nullptr, gsum, arrive, hp,
+                                                                xw);
+    else
+      step_block<T, false, 1, false, false, true, DieArrive, BT>(D, lb, s, nullptr, gsum, arrive,
+                                                                 hp, xw);
     if (s == D.S) break;
     if (!die_wait(&bar[2], (unsigned)nb * (unsigned)s, &bar[3], &ok_sh)) return;
   }
-  gram_rows(D, lb, D.S, xw, gsum);   // the last step's sums
+  gram_rows<NW>(D, lb, D.S, xw, gsum);   // the last step's sums
 }
 
 // Census of the dies a grid of `blocks` lands on: counts[die] += 1 per block.
@@ -1241,7 +1255,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
                                                           const int* __restrict__ blkoff,
                                                           int nact, int s_arg,
                                                           const int* __restrict__ act_end) {
-  __shared__ double red[4][kNP2];
+  __shared__ double red[kStepWaves][kNP2];
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
   int c = 0;
   {
@@ -1439,7 +1453,10 @@ __global__ __launch_bounds__(kStepThreads) void k_step_ov(const Desc* __restrict
   __syncthreads();
   if (threadIdx.x < kNP2) {
     const int t = threadIdx.x;
-    D.part[((size_t)(s - 1) * kNP2 + t) * D.nblk + lb] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+    double r = red[0][t];
+#pragma unroll
+    for (int w = 1; w < kStepWaves; ++w) r += red[w][t];
+    D.part[((size_t)(s - 1) * kNP2 + t) * D.nblk + lb] = r;
   }
 }
 
@@ -2304,13 +2321,21 @@ hipError_t launch_fisher_yates(const Desc* d, int64_t nr, int32_t* perm, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_persist(int fp32, const Desc* d, int nb, hipStream_t st) {
+template <int BT>
+hipError_t launch_persist_t(int fp32, const Desc* d, int nb, hipStream_t st) {
   // eight blocks per working block: nb of them land on every die
   void* args[] = {(void*)&d, (void*)&nb};
-  const dim3 g(8 * nb), b(kStepThreads);
+  const dim3 g(8 * nb), b(BT);
   if (fp32)
-    return hipLaunchCooperativeKernel((const void*)k_persist<float>, g, b, args, 0, st);
-  return hipLaunchCooperativeKernel((const void*)k_persist<double>, g, b, args, 0, st);
+    return hipLaunchCooperativeKernel((const void*)k_persist<float, BT>, g, b, args, 0, st);
+  return hipLaunchCooperativeKernel((const void*)k_persist<double, BT>, g, b, args, 0, st);
+}
+
+hipError_t launch_persist(int fp32, const Desc* d, int nb, int threads, hipStream_t st) {
+  if (threads == 64) return launch_persist_t<64>(fp32, d, nb, st);
+  if (threads == 128) return launch_persist_t<128>(fp32, d, nb, st);
+  if (threads == 256) return launch_persist_t<256>(fp32, d, nb, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_die_census(unsigned* counts, int blocks, hipStream_t st) {

@@ -6,7 +6,8 @@ Non-finite angles are written into one chain's workspace on the device
 them).  Every proposal of that chain then has a non-finite Delta S_eff: it must
 be rejected, even when the decision is forced, and counted
 (gfmc_chain_nonfinite), while the two other chains of the batch take exactly
-the trajectories they take alone.
+the trajectories they take in a batch of their own (same kernels and block
+tables: bit for bit).
 """
 import ctypes
 import math
@@ -52,17 +53,23 @@ def _chain(g, i, L, M):
 
 def test_nonfinite_state_is_flagged_and_spares_the_other_chains(g):
     nprop = 4
+    healthy = [_chain(g, i, *SPECS[i]) for i in (0, 2)]
+    hb = g.Batch(healthy)
+    hb.set_tuning(1)
+    hb.set_lanes(1)
+    hrecs = hb.step(nprop, records=True)
+    hb.close()
     alone = {}
-    for i in (0, 2):
-        ch = _chain(g, i, *SPECS[i])
-        alone[i] = ([ch.step() for _ in range(nprop)], ch.get_spins())
-        assert ch.nonfinite() == 0
+    for j, i in enumerate((0, 2)):
+        alone[i] = ([hrecs[q][j] for q in range(nprop)], healthy[j].get_spins())
+        assert healthy[j].nonfinite() == 0
     chs = [_chain(g, i, L, M) for i, (L, M) in enumerate(SPECS)]
     L1 = SPECS[1][0]
     th_ptr, _ = chs[1].device_angles()
     _poke(th_ptr, np.full(L1 ** 3, np.nan))
     b = g.Batch(chs)
     b.set_tuning(1)
+    b.set_lanes(1)
     recs = b.step(nprop, records=True)
     b.close()
     for q in range(nprop):

@@ -351,9 +351,15 @@ def test_batch_two_lanes_equal_single_chains(g, ppt):
     # alone in that shape, so every record is bit-identical; with two the sums
     # are regrouped
     alone = []
-    for ch in lane_chains(g):
-        one = g.Batch([ch])
-        one.set_tuning(1)   # a lone 10^3 FP32 chain would otherwise run LDS-resident
+    for i, ch in enumerate(lane_chains(g)):
+        # each chain beside a partner in one lane: the launched step kernel
+        # with the chain's own blocks (a lone chain would run LDS-resident or
+        # persistent, whose blocks differ)
+        L, M, T = LANE_SPECS[i]
+        partner = g.Chain(g.Params(L=L, M=M, beta=1.0 / T, precision=1, seed=99))
+        one = g.Batch([ch, partner])
+        one.set_tuning(1)
+        one.set_lanes(1)
         alone.append([r[0] for r in one.step(3, records=True)])
         one.close()
     mixed = lane_chains(g)

@@ -111,8 +111,11 @@ def test_step_granular_uneven_counts_and_validation(g):
 def test_lone_chain_persistent_run_equals_step_launches(g, L, M, prec):
     # A lone chain that fits one compute die runs all M/2 steps of a proposal
     # in one persistent launch; the same chain beside another one in a batch
-    # runs one launch per step.  Same step code and block table: the
-    # trajectories must agree bit for bit, and with the oracle's moments.
+    # runs one launch per step.  Same step arithmetic, so the vectors agree
+    # bit for bit; the persistent kernel's blocks are half the size, so its
+    # block partial sums group the sites differently and Delta S agrees to
+    # rounding of the FP64 sums.  Decisions and spins must be equal, and the
+    # moments must match the oracle's.
     import oracle
     import synth
     p = g.Params(L=L, M=M, beta=20.0, precision=prec, seed=5, chain_id=2)
@@ -136,7 +139,8 @@ def test_lone_chain_persistent_run_equals_step_launches(g, L, M, prec):
     brecs = b.step(4, records=True)
     b.close()
     for q in range(4):
-        assert brecs[q][0].site == recs[q].site and brecs[q][0].dseff == recs[q].dseff
+        assert brecs[q][0].site == recs[q].site
+        assert abs(brecs[q][0].dseff - recs[q].dseff) <= 1e-11 * max(1.0, abs(recs[q].dseff))
         assert brecs[q][0].accepted == recs[q].accepted
     t1, p1 = lone.get_spins()
     t2, p2 = a.get_spins()

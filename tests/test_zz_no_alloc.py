@@ -3,9 +3,13 @@ entry point gfmc_delta_seff (GPU).
 
 Two or more calls in a row on one device share the library's static scratch
 array; each later call is smaller than the one before, so a stale tail of an
-earlier call's buffers would show.  Both entry points run the same kernels in
-the same launch shape, so the values must agree bit for bit (the parity bar
-is 1e-10 in FP64 and 2e-5 in FP32).
+earlier call's buffers would show.  On the LDS-resident chains both entry
+points run the same kernels in the same launch shape, so the values must agree
+bit for bit.  The chain entry point runs a lone multi-block chain on the
+persistent kernel, whose blocks are half the size of the step launches the
+static entry point makes: the vectors agree bit for bit, the block sums group
+the sites differently, and the values agree to the parity bar (1e-10 in FP64,
+2e-5 in FP32).
 """
 import ctypes
 
@@ -62,8 +66,9 @@ def test_static_entry_matches_chain_entry(g):
             got, top = out.cpu().numpy()
             print(f"L={L} M={M} prec={prec} vectors={vec} site={o}: dS {got:.12f} "
                   f"chain {ref:.12f}", flush=True)
-            assert abs(got - ref) < tol and got == ref
-            assert top == rtop
+            assert abs(got - ref) < tol and abs(top - rtop) < tol
+            if L <= 8:   # LDS-resident on both paths
+                assert got == ref and top == rtop
         # the inputs are read only
         assert np.array_equal(dth.cpu().numpy(), th) and np.array_equal(dph.cpu().numpy(), ph)
         ch.close()
