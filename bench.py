@@ -32,13 +32,14 @@ HBM_PEAK_GBS = 8000.0
 # that the L2 exchanges with the memory fabric, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (one counter per run), each scaled by what the same counter reads
 # for a plain 1 GiB device copy (FETCH x 2.0, WRITE x 1.0); keyed by kernel,
-# chains of 32^3, site pairs per thread and non-temporal access, and valid only
-# for the kernel source they were taken with (sha256 below), else null.
+# chains of 32^3, site pairs per thread, non-temporal access and threads per
+# block, and valid only for the kernel source they were taken with (sha256
+# below), else null.
 TRAFFIC_KERNEL_SHA256 = "30562cece4617dd4df64360d1cd24d97b0121f17c1259030182522f83062c2b0"
-TRAFFIC_BYTES = {("k_step<float>", 64, 2, 0): 212672430,
-                 ("k_step_ov<float>", 64, 2, 0): 84205319,
-                 ("k_step<float>", 128, 1, 1): 422904346,
-                 ("k_step<double>", 64, 1, 1): 421323085}
+TRAFFIC_BYTES = {("k_step<float>", 64, 2, 0, 256): 212672430,
+                 ("k_step_ov<float>", 64, 2, 0, 256): 84205319,
+                 ("k_step<float>", 128, 1, 1, 256): 422904346,
+                 ("k_step<double>", 64, 1, 1, 256): 421323085}
 
 
 def note(msg: str):
@@ -55,8 +56,8 @@ def parse():
     ap.add_argument("--no-fp64-single", action="store_true")
     ap.add_argument("--graph", type=int, default=0, help="replay one proposal as a HIP graph")
     ap.add_argument("--tuning", type=str, default="",
-                    help="PPT,LANES[,NT]: fix the launch shape, step lanes and non-temporal access "
-                         "instead of autotuning")
+                    help="PPT,LANES[,NT[,BLOCK_THREADS]]: fix the launch shape, step lanes, "
+                         "non-temporal access and step-kernel block size instead of autotuning")
     ap.add_argument("--pair", type=int, default=1,
                     help="also time the {o, v} start-vector form on the same workload")
     ap.add_argument("--pair-tuning", type=str, default="",
@@ -96,11 +97,13 @@ def parse():
 
 
 def tune(batch, fixed: str):
-    """Autotune the batch, or fix (pairs per thread, lanes) from "PPT,LANES"."""
+    """Autotune the batch, or fix it from "PPT,LANES[,NT[,BLOCK_THREADS]]"."""
     if fixed:
         vals = [int(v) for v in fixed.split(",")]
         ppt, lanes = vals[0], vals[1]
         batch.set_lanes(lanes)
+        if len(vals) > 3:
+            batch.set_block_threads(vals[3])
         batch.set_tuning(ppt)
         if len(vals) > 2:
             batch.set_nontemporal(bool(vals[2]))
@@ -108,12 +111,12 @@ def tune(batch, fixed: str):
         batch.autotune(64)
 
 
-def traffic_bytes(kernel: str, chains: int, ppt: int, nt: int = 0):
+def traffic_bytes(kernel: str, chains: int, ppt: int, nt: int = 0, bt: int = 256):
     import hashlib
     src = os.path.join(ROOT, "paper_1303_6016_amd", "csrc", "gfmc_kernels.hip")
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != TRAFFIC_KERNEL_SHA256:
         return None
-    return TRAFFIC_BYTES.get((kernel, chains, ppt, int(nt)))
+    return TRAFFIC_BYTES.get((kernel, chains, ppt, int(nt), int(bt)))
 
 
 def host_cpu():
@@ -225,6 +228,7 @@ def hbm_regime(g, torch, dev, fixed: str, nprop: int = 2):
         tune(b, fixed)
         ppt, lanes = b.tuning()
         nt = b.form()["nontemporal"]
+        bt = b.block_threads()
         b.step(1)
         torch.cuda.synchronize()
         ms_tot, nl_tot = 0.0, 0
@@ -240,11 +244,11 @@ def hbm_regime(g, torch, dev, fixed: str, nprop: int = 2):
         kern = "k_step<float>" if prec == g.FP32_ACC64 else "k_step<double>"
         out.append({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "kernel": kern,
-                    "traffic": traffic_bytes(kern, nch, ppt, nt),
+                    "traffic": traffic_bytes(kern, nch, ppt, nt, bt),
                     "workload": f"{nch} chains of 32^3, M=2048, "
                                 f"{'FP32 recursion / FP64 sums' if prec else 'FP64'}",
                     "working_set_bytes": ws, "pairs_per_thread": ppt, "lanes": lanes,
-                    "nontemporal": nt,
+                    "nontemporal": nt, "block_threads": bt,
                     "avg_round_us": avg * 1e6, "bytes_per_round": nch * bps,
                     "rounds_timed": nl_tot})
         b.close()
@@ -695,6 +699,7 @@ def main():
     tune(batch, args.tuning)
     ppt, lanes = batch.tuning()
     nt = batch.form()["nontemporal"]
+    bt = batch.block_threads()
     if args.graph:
         batch.use_graph(True)
     stream = batch.stream
@@ -732,7 +737,7 @@ def main():
     bytes_per_round = NCHAIN * bytes_per_step
     achieved = bytes_per_round / avg_round_s / 1e9
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes("k_step<float>", NCHAIN, ppt, nt),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_bytes("k_step<float>", NCHAIN, ppt, nt, bt),
             "kernel": "k_step<float>", "lanes": lanes,
             "round": "one Chebyshev step of all chains" +
                      (": two concurrent k_step launches, one per lane" if lanes == 2 else
@@ -763,7 +768,8 @@ def main():
         "config": {"workload": "32^3 lattice x 64 chains, M=2048, FP32 recursion / FP64 moment "
                                "sums, T=0.02..0.2 t, uniform-sphere starts (seed 7)",
                    "L": L, "M": M, "chains": NCHAIN, "graph": bool(args.graph),
-                   "pairs_per_thread": ppt, "lanes": lanes, "nontemporal": nt},
+                   "pairs_per_thread": ppt, "lanes": lanes, "nontemporal": nt,
+                   "block_threads": bt},
         "mc_spin_updates_per_s": args.steps * NCHAIN / total_s,
         "step_latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "sweep_latency_s": {"p50": float(np.percentile(lat, 50)) * N,
@@ -772,10 +778,6 @@ def main():
         "wall_s": wall,
         "roofline": roof,
     }
-    # the step kernel's block size is fixed (256 threads, 4 waves); the
-    # autotuner varies site pairs per thread, lanes and non-temporal access
-    out["config"]["block_threads"] = 256
-
     # the other form of the same work: each proposal replayed as one captured
     # HIP graph (the headline above launches directly)
     if not args.graph:

@@ -355,6 +355,17 @@ gfmc_status gfmc_batch_set_schedule(gfmc_batch* batch, int32_t step_granular);
  * {0, 1}. */
 gfmc_status gfmc_batch_set_nontemporal(gfmc_batch* batch, int32_t on);
 
+/* Threads per block of the launched Chebyshev step kernel (launch shapes 1
+ * and 2; the LDS-resident and persistent kernels have block sizes of their
+ * own): 256 (default) or, for the 7-vector form with recomputed hoppings,
+ * 512.  The block partial sums of the moments then group the sites
+ * differently (results agree to rounding of the FP64 sums; the vectors bit
+ * for bit).  gfmc_batch_autotune chooses it with the launch shape.  EINVAL
+ * for other values, or 512 with the pair or mixed start vectors or stored
+ * hoppings. */
+gfmc_status gfmc_batch_set_block_threads(gfmc_batch* batch, int32_t threads);
+gfmc_status gfmc_batch_get_block_threads(gfmc_batch* batch, int32_t* threads);
+
 /* Execution form in effect: *resident = 1 when every chain runs all its
  * steps in one LDS-resident workgroup; *persistent = the number of working
  * blocks when a lone chain runs all its steps in one persistent launch on
@@ -368,8 +379,9 @@ gfmc_status gfmc_batch_get_form(gfmc_batch* batch, int32_t* resident, int32_t* p
 gfmc_status gfmc_batch_get_tuning(gfmc_batch* batch, int32_t* pairs_per_thread, int32_t* lanes);
 
 /* Time each step-kernel launch shape the batch's chains fit (shape 3 only
- * in the lock-step schedule; non-temporal access for the 7-vector kernel;
- * for a lone chain that fits one die, its persistent kernel) with one to
+ * in the lock-step schedule; non-temporal access and 512-thread blocks for
+ * the 7-vector kernel; for a lone chain that fits one die, its persistent
+ * kernel) with one to
  * four lanes over max(trial_steps, 64) Chebyshev steps (at most M/2 - 1) on
  * the batch's current spins (no change of chain state), by host wall time
  * (so that the host's launch rate counts where launches are short), keep

@@ -102,6 +102,8 @@ _SIGS = {
     "gfmc_batch_set_schedule": [_vp, _i32],
     "gfmc_batch_get_form": [_vp, _P(_i32), _P(_i32), _P(_i32), _P(_i32)],
     "gfmc_batch_set_nontemporal": [_vp, _i32],
+    "gfmc_batch_set_block_threads": [_vp, _i32],
+    "gfmc_batch_get_block_threads": [_vp, _P(_i32)],
     "gfmc_batch_get_tuning": [_vp, _P(_i32), _P(_i32)],
     "gfmc_batch_autotune": [_vp, _i32, _P(_i32)],
     "gfmc_engine_create": [ctypes.c_int, _sz, _i32, _P(_vp)],
@@ -396,6 +398,15 @@ class Batch:
 
     def set_nontemporal(self, on: bool):
         _check(lib().gfmc_batch_set_nontemporal(self.h, 1 if on else 0))
+
+    def set_block_threads(self, threads: int):
+        """Threads per block of the launched step kernel: 256 or 512."""
+        _check(lib().gfmc_batch_set_block_threads(self.h, threads))
+
+    def block_threads(self) -> int:
+        v = ctypes.c_int32()
+        _check(lib().gfmc_batch_get_block_threads(self.h, ctypes.byref(v)))
+        return v.value
 
     def tuning(self):
         """(launch shape, lanes) in effect."""

@@ -155,8 +155,8 @@ void fill_desc(gfmc_chain* c) {
 
 // Blocks of a one-step launch with ppt site pairs per thread (the two-step
 // pair shape runs its first step, and sizes its partial sums, as shape 1).
-static int blocks_of(const Derived& d, int ppt) {
-  const int per = kStepThreads * (ppt < 1 ? 1 : ppt > 2 ? 1 : ppt);
+static int blocks_of(const Derived& d, int ppt, int bt = kStepThreads) {
+  const int per = bt * (ppt < 1 ? 1 : ppt > 2 ? 1 : ppt);
   return (d.half + per - 1) / per;
 }
 
@@ -248,7 +248,9 @@ gfmc_status upload_plan(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   std::vector<Desc> ds(sorted.size());
   for (size_t i = 0; i < sorted.size(); ++i) {
     ds[i] = sorted[i]->desc;
-    ds[i].nblk = P.persist > 0 ? P.persist : P.resident ? 1 : blocks_of(sorted[i]->d, P.ppt);
+    ds[i].nblk = P.persist > 0  ? P.persist
+                 : P.resident   ? 1
+                                : blocks_of(sorted[i]->d, P.ppt, P.step_threads);
     if (P.ppt == kShapeTile2) {
       int ty = 0, tz = 0;
       tile_dims(sorted[i]->d.L, sorted[i]->d.fp32, &ty, &tz);
@@ -299,7 +301,7 @@ void plan_shape(Plan& P, const std::vector<gfmc_chain*>& sorted) {
   }
   for (int i = 0; i < P.n; ++i) {
     P.S[i] = sorted[i]->d.S;
-    P.blkoff[i + 1] = P.blkoff[i] + blocks_of(sorted[i]->d, P.ppt);
+    P.blkoff[i + 1] = P.blkoff[i] + blocks_of(sorted[i]->d, P.ppt, P.step_threads);
     P.smax = std::max(P.smax, P.S[i]);
     P.kmax = std::max(P.kmax, sorted[i]->d.K);
     P.nmax = std::max(P.nmax, sorted[i]->d.N);
@@ -404,7 +406,7 @@ gfmc_status enqueue_steps(Plan& P, int s_first, int s_last) {
       while (nact > 0 && P.S[nact - 1] < s) --nact;
       if (nact == 0) break;
       HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc, P.d_blkoff, nact, P.blkoff[nact],
-                         s, P.stream, nullptr, P.nt));
+                         s, P.stream, nullptr, P.nt, P.step_threads));
     }
     return GFMC_OK;
   }
@@ -419,7 +421,8 @@ gfmc_status enqueue_steps(Plan& P, int s_first, int s_last) {
       while (nact[l] > 0 && P.S[f + nact[l] - 1] < s) --nact[l];
       if (nact[l] == 0) continue;
       HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc + f, P.d_lane_blkoff[l], nact[l],
-                         P.lane_blkoff[l][nact[l]], s, P.lane_stream[l], nullptr, P.nt));
+                         P.lane_blkoff[l][nact[l]], s, P.lane_stream[l], nullptr, P.nt,
+                         P.step_threads));
     }
   for (int l = 0; l < k; ++l) {
     HIPCHK(hipEventRecord(P.join[l], P.lane_stream[l]));
@@ -517,7 +520,7 @@ gfmc_status enqueue_window(Plan& P, int rounds, const int* cap, int* props, bool
     hipStream_t st = lane_st(C.lane);
     HIPCHK(launch_propose(P.d_desc + C.first, C.n, st));
     HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc + C.first, C.d_blkoff, C.n,
-                       C.blkoff[C.n], 1, st));
+                       C.blkoff[C.n], 1, st, nullptr, 0, P.step_threads));
     return GFMC_OK;
   };
   auto finish = [&](size_t q) -> gfmc_status {
@@ -544,7 +547,7 @@ gfmc_status enqueue_window(Plan& P, int rounds, const int* cap, int* props, bool
       for (int i = f; i < f + nl && !any; ++i) any = r <= act[i] && (r - 1) % P.S[i] != 0;
       if (any)
         HIPCHK(launch_step(P.fp32, P.ov, P.hops, P.ppt, P.d_desc + f, bo, nl, blocks, r,
-                           lane_st(l), P.d_act_end + f, P.nt));
+                           lane_st(l), P.d_act_end + f, P.nt, P.step_threads));
     }
     for (size_t q = 0; q < P.coh.size(); ++q) {
       const int S = P.coh[q].S;
@@ -1389,6 +1392,31 @@ gfmc_status gfmc_batch_set_nontemporal(gfmc_batch* b, int32_t on) {
   return GFMC_OK;
 }
 
+gfmc_status gfmc_batch_set_block_threads(gfmc_batch* b, int32_t threads) {
+  if (!b) return fail(GFMC_EINVAL, "batch is NULL");
+  if (threads != kStepThreads && threads != 512)
+    return fail(GFMC_EINVAL, "threads must be 256 or 512");
+  Plan& P = b->plan;
+  if (threads != kStepThreads && (P.ov || P.hops))
+    return fail(GFMC_EINVAL, "512-thread blocks run the 7-vector form with recomputed hoppings "
+                             "only");
+  HIPCHK(hipStreamSynchronize(P.stream));
+  P.step_threads = threads;
+  plan_shape(P, b->sorted);
+  CHK(upload_plan(P, b->sorted));
+  const bool g = b->use_graph;
+  drop_graph(P);
+  b->use_graph = false;
+  if (g) return gfmc_batch_use_graph(b, 1);
+  return GFMC_OK;
+}
+
+gfmc_status gfmc_batch_get_block_threads(gfmc_batch* b, int32_t* threads) {
+  if (!b || !threads) return fail(GFMC_EINVAL, "NULL argument");
+  *threads = b->plan.step_threads;
+  return GFMC_OK;
+}
+
 gfmc_status gfmc_batch_get_tuning(gfmc_batch* b, int32_t* pairs_per_thread, int32_t* lanes) {
   if (!b || !pairs_per_thread || !lanes) return fail(GFMC_EINVAL, "NULL argument");
   *pairs_per_thread = b->plan.resident ? 0 : b->plan.ppt;
@@ -1414,32 +1442,38 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
     for (auto& kv : g_tune_cache)
       if (kv.first == key) hit = kv.second;
   }
-  if (hit.first >= 0) {   // second = lanes + 16 x non-temporal
+  if (hit.first >= 0) {   // second = lanes + 16 x non-temporal + 32 x (512-thread blocks)
     if (chosen) *chosen = hit.first;
     CHK(gfmc_batch_set_lanes(b, hit.second & 15));
-    CHK(gfmc_batch_set_nontemporal(b, hit.second >> 4));
+    CHK(gfmc_batch_set_nontemporal(b, (hit.second >> 4) & 1));
+    CHK(gfmc_batch_set_block_threads(b, (hit.second >> 5) ? 512 : kStepThreads));
     return gfmc_batch_set_tuning(b, hit.first);
   }
   // The step kernel only touches per-proposal scratch (vectors, partials), so
   // trial launches between proposals leave the chains' state unchanged.
-  int best = 1, best_lanes = 1, best_nt = 0;
+  int best = 1, best_lanes = 1, best_nt = 0, best_bt = kStepThreads;
   float best_ms = 1e30f;
   bool all_res = true, all_tile2 = !P.cont;
   for (auto* c : b->sorted) {
     all_res = all_res && resident_fits(c->d);
     all_tile2 = all_tile2 && tile2_fits(c->d);
   }
+  for (int bt : {kStepThreads, 512})
   for (int ppt : {0, 1, 2, kShapeTile2})
    for (int nt = 0; nt <= 1; ++nt) {
     if (ppt == 0 && !all_res) continue;
     if (ppt == kShapeTile2 && !all_tile2) continue;
     if (nt && (ppt == 0 || P.ov)) continue;   // the 7-vector multi-block kernel only
+    // 512-thread blocks: the 7-vector multi-block kernel with recomputed hoppings
+    if (bt != kStepThreads && (ppt == 0 || ppt == kShapeTile2 || P.ov || P.hops)) continue;
     for (int lanes = 1; lanes <= kMaxLanes; ++lanes) {
       if (lanes >= 2 && (ppt == 0 || ppt == kShapeTile2 || P.n < lanes)) continue;
       CHK(gfmc_batch_set_lanes(b, lanes));
+      CHK(gfmc_batch_set_block_threads(b, bt));
       CHK(gfmc_batch_set_tuning(b, ppt));
       CHK(gfmc_batch_set_nontemporal(b, nt));
       if (P.persist > 0 && nt) continue;   // the persistent kernel has no non-temporal form
+      if (P.persist > 0 && bt != kStepThreads) continue;   // its blocks are its own
       // Host wall time of enqueueing and running the trial: where the launches
       // are short the host's launch rate bounds a proposal, which GPU-side
       // event times of a short burst miss (a lone 16^3 chain: 8 timed step
@@ -1479,16 +1513,24 @@ gfmc_status gfmc_batch_autotune(gfmc_batch* b, int32_t trial_steps, int32_t* cho
           ms = std::min(ms, wall_ms(t0));
         }
       }
-      if (ms < best_ms) { best_ms = ms; best = ppt; best_lanes = lanes; best_nt = nt; }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = ppt;
+        best_lanes = lanes;
+        best_nt = nt;
+        best_bt = bt;
+      }
     }
    }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache.push_back({key, {best, best_lanes + 16 * best_nt}});
+    g_tune_cache.push_back(
+        {key, {best, best_lanes + 16 * best_nt + (best_bt != kStepThreads ? 32 : 0)}});
   }
   if (chosen) *chosen = best;
   CHK(gfmc_batch_set_lanes(b, best_lanes));
   CHK(gfmc_batch_set_nontemporal(b, best_nt));
+  CHK(gfmc_batch_set_block_threads(b, best_bt));
   return gfmc_batch_set_tuning(b, best);
 }
 

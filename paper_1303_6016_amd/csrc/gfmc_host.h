@@ -15,9 +15,11 @@ hipError_t launch_propose(const Desc* d, int n, hipStream_t st);
 // chain c takes step (s - 1) mod S_c + 1 while s <= act_end[c] (never step 1).
 // nt: non-temporal loads of each site's own a_{s-2} and stores of a_s (steps >= 2
 // of the 7-vector kernel; pays where the batch streams from HBM).
+// bt: threads per block of the step kernel (kStepThreads, or 512 for the
+// 7-vector form with recomputed hoppings).
 hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const int* blkoff,
                        int nact, int blocks, int s, hipStream_t st, const int* act_end = nullptr,
-                       int nt = 0);
+                       int nt = 0, int bt = kStepThreads);
 hipError_t prepare_step_ov2();
 hipError_t launch_step_ov2(int fp32, const Desc* d, const int* tileoff, int nact, int tiles, int s,
                            size_t lds, hipStream_t st);
@@ -91,6 +93,7 @@ struct Plan {
   bool allow_persist = false;          // chain and batch plans (not the engine's groups)
   Ctl* persist_ctl = nullptr;          // the lone chain's control block (timeout flag)
   int persist_threads = 0;             // threads per block of the persistent kernel
+  int step_threads = kStepThreads;     // threads per block of the launched step kernel
   size_t res_lds = 0;                  // dynamic LDS of the resident kernel
   int ov = 0;                          // start vectors {o, v} instead of the 7 sites
   int hops = 0;                        // stored hopping table instead of recompute

@@ -911,12 +911,12 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
     D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo<NW>(gsum, gram_combo_index(t));
 }
 
-template <typename T, bool FIRST, int PPT, bool HOPS, bool NT>
-__global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ descs,
-                                                       const int* __restrict__ blkoff, int nact,
-                                                       int s_arg, const int* __restrict__ act_end) {
-  __shared__ double xs[kStepWaves][16][17];
-  __shared__ double gsum[kStepWaves][256];
+template <typename T, bool FIRST, int PPT, bool HOPS, bool NT, int BT = kStepThreads>
+__global__ __launch_bounds__(BT) void k_step(const Desc* __restrict__ descs,
+                                             const int* __restrict__ blkoff, int nact, int s_arg,
+                                             const int* __restrict__ act_end) {
+  __shared__ double xs[BT / 64][16][17];
+  __shared__ double gsum[BT / 64][256];
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
   int c = 0;
   {
@@ -930,7 +930,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(const Desc* __restrict__ 
   const Desc& D = descs[c];
   const int s = chain_step(s_arg, act_end, c, D.S);
   if (s == 0) return;   // uniform over the block: the chain does not step now
-  step_block<T, FIRST, PPT, HOPS, NT>(D, gb - blkoff[c], s, xs, gsum);
+  step_block<T, FIRST, PPT, HOPS, NT, false, NoArrive, BT>(D, gb - blkoff[c], s, xs, gsum);
 }
 
 // ------------------------------------------- persistent single chain ---
@@ -2202,44 +2202,61 @@ hipError_t launch_propose(const Desc* d, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T, int PPT, bool HOPS>
+template <typename T, int PPT, bool HOPS, int BT>
 hipError_t launch_step_t(int ov, int nt, const Desc* d, const int* blkoff, int nact, int blocks,
                          int s, const int* act_end, hipStream_t st) {
-  const dim3 g(blocks), b(kStepThreads);
+  const dim3 g(blocks), b(BT);
   // round launches (act_end) never run step 1: it has a launch of its own
   const bool first = !act_end && s == 1;
   if (ov) {
-    if (first)
+    if constexpr (BT != kStepThreads) {
+      return hipErrorInvalidValue;   // the pair kernels run 256-thread blocks only
+    } else if (first) {
       hipLaunchKernelGGL((k_step_ov<T, true, PPT>), g, b, 0, st, d, blkoff, nact, s, act_end);
-    else
+    } else {
       hipLaunchKernelGGL((k_step_ov<T, false, PPT>), g, b, 0, st, d, blkoff, nact, s, act_end);
+    }
   } else if (first) {
-    hipLaunchKernelGGL((k_step<T, true, PPT, HOPS, false>), g, b, 0, st, d, blkoff, nact, s,
+    hipLaunchKernelGGL((k_step<T, true, PPT, HOPS, false, BT>), g, b, 0, st, d, blkoff, nact, s,
                        act_end);
   } else if (nt) {
-    hipLaunchKernelGGL((k_step<T, false, PPT, HOPS, true>), g, b, 0, st, d, blkoff, nact, s,
+    hipLaunchKernelGGL((k_step<T, false, PPT, HOPS, true, BT>), g, b, 0, st, d, blkoff, nact, s,
                        act_end);
   } else {
-    hipLaunchKernelGGL((k_step<T, false, PPT, HOPS, false>), g, b, 0, st, d, blkoff, nact, s,
+    hipLaunchKernelGGL((k_step<T, false, PPT, HOPS, false, BT>), g, b, 0, st, d, blkoff, nact, s,
                        act_end);
   }
   return hipGetLastError();
 }
 
-template <typename T, bool HOPS>
+template <typename T, bool HOPS, int BT>
 hipError_t launch_step_h(int ov, int nt, int ppt, const Desc* d, const int* blkoff, int nact,
                          int blocks, int s, const int* act_end, hipStream_t st) {
-  return ppt == 2 ? launch_step_t<T, 2, HOPS>(ov, nt, d, blkoff, nact, blocks, s, act_end, st)
-                  : launch_step_t<T, 1, HOPS>(ov, nt, d, blkoff, nact, blocks, s, act_end, st);
+  return ppt == 2 ? launch_step_t<T, 2, HOPS, BT>(ov, nt, d, blkoff, nact, blocks, s, act_end, st)
+                  : launch_step_t<T, 1, HOPS, BT>(ov, nt, d, blkoff, nact, blocks, s, act_end, st);
 }
 
+// bt: threads per block, 256 or (7-vector form, hoppings recomputed) 512
 hipError_t launch_step(int fp32, int ov, int hops, int ppt, const Desc* d, const int* blkoff,
-                       int nact, int blocks, int s, hipStream_t st, const int* act_end, int nt) {
+                       int nact, int blocks, int s, hipStream_t st, const int* act_end, int nt,
+                       int bt) {
+  if (bt == 512) {
+    if (ov || hops) return hipErrorInvalidValue;
+    return fp32 ? launch_step_h<float, false, 512>(0, nt, ppt, d, blkoff, nact, blocks, s,
+                                                   act_end, st)
+                : launch_step_h<double, false, 512>(0, nt, ppt, d, blkoff, nact, blocks, s,
+                                                    act_end, st);
+  }
+  if (bt != kStepThreads) return hipErrorInvalidValue;
   if (fp32)
-    return hops ? launch_step_h<float, true>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st)
-                : launch_step_h<float, false>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st);
-  return hops ? launch_step_h<double, true>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st)
-              : launch_step_h<double, false>(ov, nt, ppt, d, blkoff, nact, blocks, s, act_end, st);
+    return hops ? launch_step_h<float, true, kStepThreads>(ov, nt, ppt, d, blkoff, nact, blocks,
+                                                           s, act_end, st)
+                : launch_step_h<float, false, kStepThreads>(ov, nt, ppt, d, blkoff, nact, blocks,
+                                                            s, act_end, st);
+  return hops ? launch_step_h<double, true, kStepThreads>(ov, nt, ppt, d, blkoff, nact, blocks, s,
+                                                          act_end, st)
+              : launch_step_h<double, false, kStepThreads>(ov, nt, ppt, d, blkoff, nact, blocks,
+                                                           s, act_end, st);
 }
 
 // The two-step pair kernel takes up to kTileLds of dynamic LDS (set once per

@@ -167,3 +167,66 @@ def test_nontemporal_steps_do_not_change_results(g):
     assert r0 == r1
     for (a, b_), (c, d) in zip(s0, s1):
         assert np.array_equal(a, c) and np.array_equal(b_, d)
+
+
+@pytest.mark.parametrize("prec,ppt,lanes", [(0, 1, 1), (1, 2, 2), (1, 1, 2)])
+def test_512_thread_blocks_match_256(g, prec, ppt, lanes):
+    # The launched step kernel with 512-thread blocks forms the same vectors
+    # (same per-site arithmetic) and groups the block partial sums over twice
+    # the sites: decisions, sites and spins equal the 256-thread run's, Delta S
+    # agrees to rounding of the FP64 sums and matches the oracle.  12^3 and
+    # 10^3 leave a ragged last block.
+    import oracle
+    import synth
+    specs = [(12, 64, 10.0), (10, 128, 5.0), (16, 64, 20.0)]
+
+    def run(bt):
+        chs = []
+        for i, (L, M, beta) in enumerate(specs):
+            ch = g.Chain(g.Params(L=L, M=M, beta=beta, precision=prec, seed=41, chain_id=i))
+            th, ph = synth.random_angles(L ** 3, 70 + i)
+            ch.set_spins(th, ph)
+            chs.append(ch)
+        b = g.Batch(chs)
+        b.set_tuning(ppt)
+        b.set_lanes(lanes)
+        b.set_block_threads(bt)
+        assert b.block_threads() == bt and b.tuning() == (ppt, lanes)
+        spins0 = [c.get_spins() for c in chs]
+        recs = b.step(3, records=True)
+        b.close()
+        return recs, [c.get_spins() for c in chs], spins0
+    r256, s256, spins0 = run(256)
+    r512, s512, _ = run(512)
+    for q in range(3):
+        for i in range(len(specs)):
+            a, c = r256[q][i], r512[q][i]
+            assert (a.site, a.u, a.accepted) == (c.site, c.u, c.accepted)
+            assert abs(a.dseff - c.dseff) <= 1e-11 * max(1.0, abs(a.dseff))
+    for (t1, p1), (t2, p2) in zip(s256, s512):
+        assert np.array_equal(t1, t2) and np.array_equal(p1, p2)
+    tol = 1e-10 if prec == 0 else 2e-5
+    for i, (L, M, beta) in enumerate(specs):
+        m = oracle.Model(L=L, M=M, beta=beta, seed=41, chain_id=i)
+        th, ph = spins0[i]
+        r = r512[0][i]
+        ref = oracle.delta_seff(m, th, ph, r.site, r.theta_new, r.phi_new)
+        assert abs(r.dseff - ref) < tol
+
+
+def test_block_threads_validation(g):
+    ch = g.Chain(g.Params(L=12, M=64, precision=0, seed=1))
+    b = g.Batch([ch])
+    for bad in (0, 64, 128, 1024):
+        with pytest.raises(g.GfmcError) as e:
+            b.set_block_threads(bad)
+        assert e.value.status == g.GFMC_EINVAL
+    b.close()
+    for kw in ({"vectors": 1}, {"hoppings": 1}):
+        c = g.Chain(g.Params(L=12, M=64, precision=0, seed=1, **kw))
+        bb = g.Batch([c])
+        with pytest.raises(g.GfmcError) as e:
+            bb.set_block_threads(512)
+        assert e.value.status == g.GFMC_EINVAL
+        assert bb.block_threads() == 256
+        bb.close()
