@@ -35,11 +35,17 @@ HBM_PEAK_GBS = 8000.0
 # chains of 32^3, site pairs per thread, non-temporal access and threads per
 # block, and valid only for the kernel source they were taken with (sha256
 # below), else null.
-TRAFFIC_KERNEL_SHA256 = "30562cece4617dd4df64360d1cd24d97b0121f17c1259030182522f83062c2b0"
-TRAFFIC_BYTES = {("k_step<float>", 64, 2, 0, 256): 212672430,
-                 ("k_step_ov<float>", 64, 2, 0, 256): 84205319,
-                 ("k_step<float>", 128, 1, 1, 256): 422904346,
-                 ("k_step<double>", 64, 1, 1, 256): 421323085}
+TRAFFIC_KERNEL_SHA256 = "da041d79a8d069d2106b57b6678ff4c6f9a9fe187b0c9abad7d117d9231d6c22"
+TRAFFIC_BYTES = {("k_step<float>", 64, 2, 0, 256): 212712160,
+                 ("k_step_ov<float>", 64, 2, 0, 256): 84205242,
+                 ("k_step<float>", 64, 1, 0, 256): 211566603,
+                 ("k_step<float>", 64, 1, 0, 512): 210784778,
+                 ("k_step<float>", 64, 1, 1, 256): 211548171,
+                 ("k_step<float>", 64, 1, 1, 512): 210763787,
+                 ("k_step<float>", 128, 1, 1, 256): 422904090,
+                 ("k_step<float>", 128, 1, 1, 512): 421315354,
+                 ("k_step<double>", 64, 1, 1, 256): 421320538,
+                 ("k_step<double>", 64, 1, 1, 512): 420466715}
 
 
 def note(msg: str):
@@ -108,7 +114,7 @@ def tune(batch, fixed: str):
         if len(vals) > 2:
             batch.set_nontemporal(bool(vals[2]))
     else:
-        batch.autotune(64)
+        batch.autotune(256)   # 256 steps per trial: shapes within a few per cent apart
 
 
 def traffic_bytes(kernel: str, chains: int, ppt: int, nt: int = 0, bt: int = 256):
@@ -327,8 +333,9 @@ def mixed_batch(g, torch, dev, n_prop: int = 2, step_granular: bool = True):
     for ch in chs:
         ch.init_spins(g.INIT_RANDOM)
     b = g.Batch(chs)
-    b.autotune(32)
+    b.autotune(256)
     ppt, lanes = b.tuning()
+    nt, bt = b.form()["nontemporal"], b.block_threads()
     b.set_schedule(step_granular)
     b.step(1)
     torch.cuda.synchronize()
@@ -357,7 +364,7 @@ def mixed_batch(g, torch, dev, n_prop: int = 2, step_granular: bool = True):
            "windows": n_prop, "proposals": {"64^3": props[0], "32^3_each": props[1]},
            "ms_per_window": 1e3 * dt / n_prop,
            "svu_per_s": svu / dt, "mc_spin_updates_per_s": sum(props) / dt,
-           "pairs_per_thread": ppt, "lanes": lanes}
+           "pairs_per_thread": ppt, "lanes": lanes, "nontemporal": nt, "block_threads": bt}
     # step kernel: algorithmic bytes of every step taken over the step time
     # (step-granular: the whole window, reconstructions of the 32^3 chains
     # included; lock-step: the step launches)
