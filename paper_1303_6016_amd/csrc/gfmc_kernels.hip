@@ -602,6 +602,49 @@ __device__ __forceinline__ void gram_rows(const Desc& D, const int lb, const int
     D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo<NW>(gsum, gram_combo_index(t));
 }
 
+// The block's 49 Gram sums of step s from the 16 values of each thread's PPT
+// site pairs (the column form below; step_block forms the same sums inline):
+// v_mfma_f64_16x16x4 with A = B = 4 columns (site pairs) of 16
+// components on the FP64 matrix core; each wave stages 16 site pairs at a
+// time in LDS (4 rounds per pair slot), slot by slot.  Every thread of the
+// block must call it (it holds a block barrier).
+template <int PPT, int NW>
+__device__ __forceinline__ void gram_staged(const Desc& D, const int lb, const int s,
+                                            const double (&x)[PPT][16], double (*xs)[16][17],
+                                            double (*gsum)[256]) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  d4v acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      if ((lane >> 4) == rr) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) xs[w][lane & 15][i] = x[p][i];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double val = xs[w][4 * m + (lane >> 4)][lane & 15];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(val, val, acc, 0, 0, 0);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  // result layout of v_mfma_f64_16x16x4: lane l, register r holds entry
+  // (4r + l/16, l%16) of the 16x16 product
+#pragma unroll
+  for (int r = 0; r < 4; ++r) gsum[w][(4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[r];
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < kNP)
+    D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo<NW>(gsum, gram_combo_index(t));
+}
+
 template <typename T, bool FIRST, int PPT, bool HOPS, bool NT, bool COH = false,
           typename Arrive = NoArrive, int BT = kStepThreads>
 __device__ __forceinline__ void step_block(const Desc& D, const int lb, const int s,
@@ -911,10 +954,249 @@ __device__ __forceinline__ void step_block(const Desc& D, const int lb, const in
     D.part[((size_t)(s - 1) * kNP + t) * D.nblk + lb] = gram_combo<NW>(gsum, gram_combo_index(t));
 }
 
+// Step s with two site pairs of one y column per thread (7-vector form, FP32,
+// hoppings recomputed, launched kernels with two pairs per thread): thread j
+// of a chain takes half-row index k in rows 2 (j / (L/2)) and the next one of
+// one z-plane.  As in the pair kernel's column form, the y + 1 neighbour of
+// the first pair's o-site is the second pair's n-site and the y + 1
+// neighbour of its n-site is the second pair's o-site (and the same for
+// y - 1 from the second pair): those spinors, the n-site's a^o_{s-1} and the
+// o-site's six a^n_{s-1} come from the thread's own loads, so two pairs load
+// 68 values instead of 78.  Every site's sums run over the six directions in
+// the same order as in step_block, so the vector values agree with it bit
+// for bit; the n-site's loads are issued by direction group (x, y, z) for
+// both pairs together.
+template <typename T>
+__device__ inline six<T> pick6(bool c, const six<T>& a, const six<T>& b) {
+  six<T> r;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) r.v[e] = pick(c, a.v[e], b.v[e]);
+  return r;
+}
+
+template <typename T, bool FIRST, bool NT, int BT>
+__device__ __forceinline__ void step_block_col2(const Desc& D, const int lb, const int s,
+                                                double (*xs)[16][17], double (*gsum)[256]) {
+  constexpr int NW = BT / 64;
+  const int L = D.L, half = D.half, hx = L >> 1;
+  const Ctl* ctl = D.ctl;
+  const int pO = ctl->parity_o;
+  const int po = pO ^ (s & 1);          // parity of the sites that carry a^o_s
+  const int pn = po ^ 1;                // parity of the sites that carry a^n_s
+  const int o_half = ctl->o_half;
+  int sh[6];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) sh[e] = FIRST ? ctl->start_half[1 + e] : 0;
+  const double hsc = -D.t / D.a;        // Ht = -(t/a) t_ij
+  const T two = FIRST ? (T)1 : (T)2;     // |a_1> = Ht|a_0>, then 2 Ht|a_{s-1}> - |a_{s-2}>
+  const GLOBAL spn<T>* sp = (const GLOBAL spn<T>*)D.spin;            // [2][half]
+  GLOBAL cpx<T>* vo = (GLOBAL cpx<T>*)D.vec;                         // o-slots [2][half]
+  const Planes<T> vn = planes<T>((cpx<T>*)D.vec + D.N, D.N);        // n-slots [2][half]
+  const GLOBAL spn<T>* sp_o = sp + (size_t)po * half;
+  const GLOBAL spn<T>* sp_n = sp + (size_t)pn * half;
+  auto ind = [&](int hh) {   // a^o_0 = |o> at half-row index hh (o's parity)
+    cpx<T> r;
+    r.x = (hh == o_half) ? (T)1 : (T)0;
+    r.y = 0;
+    return r;
+  };
+  auto ind6 = [&](int hh) {   // a^{n_e}_0 = |n_e> at half-row index hh
+    six<T> r;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      r.v[e].x = (hh == sh[e]) ? (T)1 : (T)0;
+      r.v[e].y = 0;
+    }
+    return r;
+  };
+  double x[2][16];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[q][i] = 0.0;
+  const int j = lb * BT + (int)threadIdx.x;
+  if (j < half / 2) {
+    const int r = (int)fdiv((uint32_t)j, D.div_hx);
+    const int k = j - r * hx;
+    const int R = 2 * r;   // row index y + L z of the first pair
+    const int z = (int)fdiv((uint32_t)R, D.div_L);
+    const int y0 = R - z * L;
+    const int h0 = R * hx + k;
+    const int b0 = (y0 + z + po) & 1;   // x = 2k + b of the first pair's o-site
+    spn<T> so[2], sn[2];   // the pairs' own spinors
+    cpx<T> aop[2];         // a^o_{s-1} at the n-sites
+    {   // a^o_s on the o-sites
+      int nh[2][6];
+      spn<T> sjx[2], sj[2][6];
+      cpx<T> anx[2], an[2][6], pr[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int h = h0 + q * hx, bo = b0 ^ q;
+        nb6_half(h, k, bo, y0 + q, z, L, nh[q]);
+        const int nx = bo ? nh[q][0] : nh[q][1];   // the x neighbour that is another pair
+        so[q] = ld(sp_o + h);
+        sn[q] = ld(sp_n + h);
+        sjx[q] = ld(sp_n + nx);
+        if (FIRST) {
+          aop[q] = ind(h);
+          anx[q] = ind(nx);
+        } else {
+          aop[q] = ld(vo + (size_t)pn * half + h);
+          anx[q] = ld(vo + (size_t)pn * half + nx);
+        }
+#pragma unroll
+        for (int d = 2; d < 6; ++d) {
+          if ((d == 2 && q == 0) || (d == 3 && q == 1)) continue;   // inside the column
+          sj[q][d] = ld(sp_n + nh[q][d]);
+          an[q][d] = FIRST ? ind(nh[q][d]) : ld(vo + (size_t)pn * half + nh[q][d]);
+        }
+        pr[q].x = 0;
+        pr[q].y = 0;
+        if (!FIRST) pr[q] = NT ? ld_nt(vo + (size_t)po * half + h) : ld(vo + (size_t)po * half + h);
+      }
+      STEP_LOADS_ISSUED();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int h = h0 + q * hx, bo = b0 ^ q;
+        sj[q][0] = pick(bo != 0, sjx[q], sn[q]);
+        sj[q][1] = pick(bo != 0, sn[q], sjx[q]);
+        an[q][0] = pick(bo != 0, anx[q], aop[q]);
+        an[q][1] = pick(bo != 0, aop[q], anx[q]);
+        if (q == 0) {
+          sj[0][2] = sn[1];
+          an[0][2] = aop[1];
+        } else {
+          sj[1][3] = sn[0];
+          an[1][3] = aop[0];
+        }
+        T ar = 0, ai = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+          T hr, hi_;
+          hop_spinor(so[q], sj[q][d], hsc, hr, hi_);
+          cmac(hr, hi_, an[q][d], ar, ai);
+        }
+        cpx<T> ao;
+        ao.x = two * ar - pr[q].x;
+        ao.y = two * ai - pr[q].y;
+        if (NT) st_nt(vo + (size_t)po * half + h, ao);
+        else st(vo + (size_t)po * half + h, ao);
+        x[q][14] = (double)ao.x;
+        x[q][15] = (double)ao.y;
+      }
+    }
+    {   // a^{n_e}_s, e = 0..5, on the n-sites: x, y and z directions in turn
+      int nhn[2][6];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) nb6_half(h0 + q * hx, k, b0 ^ q ^ 1, y0 + q, z, L, nhn[q]);
+      T accr[2][6], acci[2][6];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          accr[q][e] = 0;
+          acci[q][e] = 0;
+        }
+      auto acc6 = [&](int q, const spn<T>& sj, const six<T>& a6) {
+        T hr, hi_;
+        hop_spinor(sn[q], sj, hsc, hr, hi_);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) cmac(hr, hi_, a6.v[e], accr[q][e], acci[q][e]);
+      };
+      six<T> own6[2];   // a^n_{s-1} at the pairs' own o-sites
+      {   // x: the pair's own o-site and the neighbour in the next or previous pair
+        spn<T> sjx[2];
+        six<T> anx6[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int h = h0 + q * hx, bn = b0 ^ q ^ 1;
+          const int nx = bn ? nhn[q][0] : nhn[q][1];
+          sjx[q] = ld(sp_o + nx);
+          own6[q] = FIRST ? ind6(h) : vn.ld((size_t)po * half + h);
+          anx6[q] = FIRST ? ind6(nx) : vn.ld((size_t)po * half + nx);
+        }
+        STEP_LOADS_ISSUED();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const bool bn = (b0 ^ q ^ 1) != 0;
+          acc6(q, pick(bn, sjx[q], so[q]), pick6(bn, anx6[q], own6[q]));   // x + 1
+          acc6(q, pick(bn, so[q], sjx[q]), pick6(bn, own6[q], anx6[q]));   // x - 1
+        }
+      }
+      {   // y: one neighbour is the other pair's o-site
+        spn<T> sjy[2];
+        six<T> any6[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int ny = nhn[q][q == 0 ? 3 : 2];   // the y neighbour outside the column
+          sjy[q] = ld(sp_o + ny);
+          any6[q] = FIRST ? ind6(ny) : vn.ld((size_t)po * half + ny);
+        }
+        STEP_LOADS_ISSUED();
+        acc6(0, so[1], own6[1]);     // y + 1
+        acc6(0, sjy[0], any6[0]);    // y - 1
+        acc6(1, sjy[1], any6[1]);    // y + 1
+        acc6(1, so[0], own6[0]);     // y - 1
+      }
+      six<T> prev[2];
+      {   // z, and the sites' own a^n_{s-2}
+        spn<T> sjz[2][2];
+        six<T> anz6[2][2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int h = h0 + q * hx;
+#pragma unroll
+          for (int g = 0; g < 2; ++g) {
+            sjz[q][g] = ld(sp_o + nhn[q][4 + g]);
+            anz6[q][g] = FIRST ? ind6(nhn[q][4 + g]) : vn.ld((size_t)po * half + nhn[q][4 + g]);
+          }
+          if (!FIRST)
+            prev[q] = NT ? vn.ld_nt((size_t)pn * half + h) : vn.ld((size_t)pn * half + h);
+        }
+        STEP_LOADS_ISSUED();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          acc6(q, sjz[q][0], anz6[q][0]);
+          acc6(q, sjz[q][1], anz6[q][1]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int h = h0 + q * hx;
+        six<T> out;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          out.v[e].x = two * accr[q][e];
+          out.v[e].y = two * acci[q][e];
+          if (!FIRST) {
+            out.v[e].x -= prev[q].v[e].x;
+            out.v[e].y -= prev[q].v[e].y;
+          }
+          x[q][2 * e] = (double)out.v[e].x;
+          x[q][2 * e + 1] = (double)out.v[e].y;
+        }
+        if (NT) vn.st_nt((size_t)pn * half + h, out);
+        else vn.st((size_t)pn * half + h, out);
+        if (FIRST) {   // store a_0 on the sites that hold it from now on
+          st(vo + (size_t)pn * half + h, aop[q]);
+          vn.st((size_t)po * half + h, ind6(h));
+        }
+        x[q][12] = (double)aop[q].x;
+        x[q][13] = (double)aop[q].y;
+      }
+    }
+  }
+  gram_staged<2, NW>(D, lb, s, x, xs, gsum);
+}
+
+// The column form (two site pairs per thread, FP32) is held to three waves per
+// SIMD (159 VGPRs; left to itself the compiler takes 172 and two waves, and
+// the 64 x 32^3 round takes 35.4 us instead of 32.1).
 template <typename T, bool FIRST, int PPT, bool HOPS, bool NT, int BT = kStepThreads>
-__global__ __launch_bounds__(BT) void k_step(const Desc* __restrict__ descs,
-                                             const int* __restrict__ blkoff, int nact, int s_arg,
-                                             const int* __restrict__ act_end) {
+__global__ __launch_bounds__(BT)
+__attribute__((amdgpu_waves_per_eu(PPT == 2 && !HOPS && sizeof(T) == 4 ? 3 : 1))) void k_step(
+    const Desc* __restrict__ descs, const int* __restrict__ blkoff, int nact, int s_arg,
+    const int* __restrict__ act_end) {
   __shared__ double xs[BT / 64][16][17];
   __shared__ double gsum[BT / 64][256];
   const int gb = xcd_remap(blockIdx.x, gridDim.x);
@@ -930,7 +1212,10 @@ __global__ __launch_bounds__(BT) void k_step(const Desc* __restrict__ descs,
   const Desc& D = descs[c];
   const int s = chain_step(s_arg, act_end, c, D.S);
   if (s == 0) return;   // uniform over the block: the chain does not step now
-  step_block<T, FIRST, PPT, HOPS, NT, false, NoArrive, BT>(D, gb - blkoff[c], s, xs, gsum);
+  if constexpr (PPT == 2 && !HOPS && sizeof(T) == 4)
+    step_block_col2<T, FIRST, NT, BT>(D, gb - blkoff[c], s, xs, gsum);
+  else
+    step_block<T, FIRST, PPT, HOPS, NT, false, NoArrive, BT>(D, gb - blkoff[c], s, xs, gsum);
 }
 
 // ------------------------------------------- persistent single chain ---
