@@ -35,17 +35,20 @@ HBM_PEAK_GBS = 8000.0
 # chains of 32^3, site pairs per thread, non-temporal access and threads per
 # block, and valid only for the kernel source they were taken with (sha256
 # below), else null.
-TRAFFIC_KERNEL_SHA256 = "da041d79a8d069d2106b57b6678ff4c6f9a9fe187b0c9abad7d117d9231d6c22"
-TRAFFIC_BYTES = {("k_step<float>", 64, 2, 0, 256): 212712160,
-                 ("k_step_ov<float>", 64, 2, 0, 256): 84205242,
-                 ("k_step<float>", 64, 1, 0, 256): 211566603,
-                 ("k_step<float>", 64, 1, 0, 512): 210784778,
-                 ("k_step<float>", 64, 1, 1, 256): 211548171,
-                 ("k_step<float>", 64, 1, 1, 512): 210763787,
-                 ("k_step<float>", 128, 1, 1, 256): 422904090,
-                 ("k_step<float>", 128, 1, 1, 512): 421315354,
-                 ("k_step<double>", 64, 1, 1, 256): 421320538,
-                 ("k_step<double>", 64, 1, 1, 512): 420466715}
+TRAFFIC_KERNEL_SHA256 = "cd724c4b8cd1d91da370ddf8b45a547aa759edef0ade26e74016a2ccc4ac84a6"
+TRAFFIC_BYTES = {("k_step<float>", 64, 2, 0, 256): 213828771,
+                 ("k_step_ov<float>", 64, 2, 0, 256): 84205354,
+                 ("k_step<float>", 64, 1, 0, 256): 211566567,
+                 ("k_step<float>", 64, 1, 0, 512): 210792422,
+                 ("k_step<float>", 64, 1, 1, 256): 211564647,
+                 ("k_step<float>", 64, 1, 1, 512): 210761703,
+                 ("k_step<float>", 64, 2, 1, 256): 211637203,
+                 ("k_step<float>", 128, 1, 1, 256): 422920466,
+                 ("k_step<float>", 128, 1, 1, 512): 421313234,
+                 ("k_step<float>", 128, 2, 1, 256): 422548855,
+                 ("k_step<double>", 64, 1, 1, 256): 421342034,
+                 ("k_step<double>", 64, 1, 1, 512): 420489682,
+                 ("k_step<double>", 64, 2, 1, 256): 423743754}
 
 
 def note(msg: str):
