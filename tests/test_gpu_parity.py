@@ -485,3 +485,44 @@ def test_zero_counts_change_nothing(g):
     b.close()
     th2, ph2 = ch.get_spins()
     assert np.array_equal(th, th2) and np.array_equal(ph, ph2) and ch.get_counter() == 0
+
+
+@pytest.mark.parametrize("nt", [False, True])
+def test_column_form_matches_one_pair_per_thread(g, nt):
+    # FP32 with two site pairs per thread takes them from one y column and
+    # shares the y neighbours' loads: the vectors equal those of one pair per
+    # thread bit for bit (same per-site arithmetic), the block sums group the
+    # sites differently.  L = 10 and 14 leave a ragged last block; 16 fills
+    # its blocks.  Decisions, sites and spins equal; Delta S to rounding of the
+    # FP64 sums and to the oracle.
+    specs = [(10, 64, 10.0), (14, 64, 5.0), (16, 128, 20.0)]
+
+    def run(ppt):
+        chs = []
+        for i, (L, M, beta) in enumerate(specs):
+            ch, _ = make(g, L, M, 1, seed=51, chain_id=i, beta=beta)
+            th, ph = synth.random_angles(L ** 3, 80 + i)
+            ch.set_spins(th, ph)
+            chs.append(ch)
+        b = g.Batch(chs)
+        b.set_lanes(1)
+        b.set_tuning(ppt)
+        b.set_nontemporal(nt)
+        spins0 = [c.get_spins() for c in chs]
+        recs = b.step(3, records=True)
+        b.close()
+        return recs, [c.get_spins() for c in chs], spins0
+    r1, s1, spins0 = run(1)
+    r2, s2, _ = run(2)
+    for q in range(3):
+        for i in range(len(specs)):
+            a, c = r1[q][i], r2[q][i]
+            assert (a.site, a.u, a.accepted) == (c.site, c.u, c.accepted)
+            assert abs(a.dseff - c.dseff) <= 1e-11 * max(1.0, abs(a.dseff))
+    for (t1, p1), (t2, p2) in zip(s1, s2):
+        assert np.array_equal(t1, t2) and np.array_equal(p1, p2)
+    for i, (L, M, beta) in enumerate(specs):
+        m = oracle.Model(L=L, M=M, beta=beta, seed=51, chain_id=i)
+        th, ph = spins0[i]
+        r = r2[0][i]
+        assert abs(r.dseff - oracle.delta_seff(m, th, ph, r.site, r.theta_new, r.phi_new)) < 2e-5
