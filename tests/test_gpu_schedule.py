@@ -121,7 +121,10 @@ def test_lone_chain_persistent_run_equals_step_launches(g, L, M, prec):
     p = g.Params(L=L, M=M, beta=20.0, precision=prec, seed=5, chain_id=2)
     probe = g.Chain(p)
     pb = g.Batch([probe])
-    assert pb.form()["persistent"] > 0   # the lone chain takes the persistent path
+    # the lone chain takes the persistent path, with blocks of 64 threads while
+    # that gives at most 16 blocks, else of 128 or 256 (at most 32 blocks)
+    expected_blocks = {10: 8, 12: 14, 16: 16, 24: 27}[L]
+    assert pb.form()["persistent"] == expected_blocks
     pb.close()
     lone = g.Chain(p)
     th, ph = synth.random_angles(L ** 3, 3)
