@@ -404,7 +404,10 @@ gfmc_status gfmc_chain_step_bytes(gfmc_chain* chain, double* bytes_per_step, int
 /* ----------------------------------------------------------------- serving --
  * An engine runs independent chain requests on one device with continuous
  * batching: a host worker thread admits queued requests whenever a slot and
- * enough of the HBM budget are free, and every iteration advances all
+ * enough of the HBM budget are free (in arrival order; a request whose
+ * workspace does not fit yet lets later ones that fit go first, until it has
+ * waited 10 s, after which the requests behind it wait for it), and every
+ * iteration advances all
  * admitted chains by one proposal in one batched launch sequence, so chains
  * of different L, M and temperature share the device and requests that
  * arrive while others run join at the next iteration.  Each request runs

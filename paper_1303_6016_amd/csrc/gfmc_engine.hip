@@ -9,7 +9,9 @@
 // the caller's stream a hardware queue of its own among the four a process
 // gets by default.  Each iteration the worker (1) admits queued
 // requests in arrival order while a slot and a large enough block of the HBM
-// budget are free, (2) retires cancelled requests, (3) re-uploads the plans
+// budget are free; a request that does not fit lets later ones that do in
+// ahead of it, until it has waited kHoldAfter seconds, after which admission
+// holds for it (no request is starved); (2) retires cancelled requests, (3) re-uploads the plans
 // when the set of running chains changed, (4) advances every group by a
 // number of proposals inversely proportional to the estimated device time of
 // one of its proposals (capped, and never past a member's sweep boundary),
@@ -41,6 +43,12 @@ struct Arena {
     used = 0;
     free_.clear();
     free_[0] = n;
+  }
+  bool fits(size_t n) const {
+    n = align256(n);
+    for (const auto& kv : free_)
+      if (kv.second >= n) return true;
+    return false;
   }
   bool alloc(size_t n, size_t& off) {
     n = align256(n);
@@ -321,6 +329,25 @@ static gfmc_status iterate(gfmc_engine* E) {
   return GFMC_OK;
 }
 
+// A queued request that has waited kHoldAfter seconds without fitting the
+// free budget holds admission: the requests behind it wait until it is in.
+constexpr double kHoldAfter = 10.0;
+static bool held(const gfmc_engine* E, const Request* r) {
+  return E->now() - r->t_submit >= kHoldAfter;
+}
+
+// Whether the admission pass would take a queued request now (caller holds
+// the engine's lock): a free slot and a request that fits, scanning in
+// arrival order up to the first held one.
+static bool admissible(const gfmc_engine* E) {
+  if ((int)E->running.size() >= E->max_slots) return false;
+  for (const Request* r : E->queue) {
+    if (E->arena.fits(r->bytes)) return true;
+    if (held(E, r)) return false;
+  }
+  return false;
+}
+
 static void worker_main(gfmc_engine* E) {
   (void)hipSetDevice(E->device);
   std::vector<Request*> admitted;
@@ -330,13 +357,19 @@ static void worker_main(gfmc_engine* E) {
     {
       std::unique_lock<std::mutex> lk(E->mu);
       if (E->stop) break;
-      while (!E->queue.empty() && (int)(E->running.size() + admitted.size()) < E->max_slots) {
-        Request* r = E->queue.front();
+      for (auto it = E->queue.begin();
+           it != E->queue.end() && (int)(E->running.size() + admitted.size()) < E->max_slots;) {
+        Request* r = *it;
         size_t off = 0;
-        if (!E->arena.alloc(r->bytes, off)) break;   // wait for memory (arrival order)
-        r->off = off;
-        E->queue.pop_front();
-        admitted.push_back(r);
+        if (E->arena.alloc(r->bytes, off)) {
+          r->off = off;
+          it = E->queue.erase(it);
+          admitted.push_back(r);
+        } else if (held(E, r)) {
+          break;   // later requests wait until this one is admitted
+        } else {
+          ++it;    // later, smaller requests may go first
+        }
       }
       if (E->running.empty() && admitted.empty()) {
         E->busy = false;
@@ -386,7 +419,7 @@ static void worker_main(gfmc_engine* E) {
       boundary_now |= r->step_props > 0 && ((r->done_props + r->step_props) % r->d.N == 0);
     {
       std::lock_guard<std::mutex> g(E->mu);
-      pending = !E->queue.empty();
+      pending = admissible(E);
       for (auto* r : E->running) pending |= r->cancel;
     }
     ++since_sync;

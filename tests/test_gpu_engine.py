@@ -88,6 +88,45 @@ def test_engine_budget_and_cancel(g):
     eng.close()
 
 
+
+def _wait_status(eng, pred, timeout=60.0):
+    deadline = time.monotonic() + timeout
+    st = eng.status()
+    while not pred(st) and time.monotonic() < deadline:
+        time.sleep(0.005)
+        st = eng.status()
+    return st
+
+
+def test_engine_admits_smaller_requests_past_one_that_does_not_fit(g):
+    # budget = A + B - 256 bytes: with A running, B (no larger than A) does
+    # not fit, C does; C goes in ahead of B, and B goes in once A has left
+    # (into A's place: the budget is carved first-fit)
+    pa = g.Params(L=16, M=1024, seed=1)
+    pb = g.Params(L=12, M=512, seed=2)
+    pc = g.Params(L=4, M=64, seed=3)
+    al = lambda n: (n + 255) // 256 * 256
+    wa, wb, wc = (al(g.gfmc_workspace_bytes(p)) for p in (pa, pb, pc))
+    assert wa >= wb > wc + 256
+    eng = g.Engine(0, hbm_budget_bytes=wa + wb - 256, max_slots=4)
+    ida = eng.submit(pa, nsweeps=100000)
+    st = _wait_status(eng, lambda st: st["running"] == 1)
+    assert st["running"] == 1, st
+    idb = eng.submit(pb, nsweeps=100000)
+    idc = eng.submit(pc, nsweeps=100000)
+    st = _wait_status(eng, lambda st: st["running"] == 2)
+    assert st["running"] == 2 and st["queued"] == 1, st   # A and C run, B waits
+    eng.cancel(ida)
+    st = _wait_status(eng, lambda st: st["queued"] == 0 and st["running"] == 2)
+    assert st["running"] == 2 and st["queued"] == 0, st   # B took A's place
+    eng.cancel(idb)
+    eng.cancel(idc)
+    eng.drain(120)
+    res = {r.request_id: r for r in eng.poll()}
+    assert all(res[i].status == g.GFMC_ECANCELED for i in (ida, idb, idc))
+    assert res[idc].t_admit < res[idb].t_admit   # C was admitted before B
+    eng.close()
+
 MIXED = [  # L, M, T, precision: LDS-resident (L <= 10 FP32, L <= 8 FP64) and multi-block chains
     (4, 128, 0.05, 1),
     (10, 64, 0.1, 0),
