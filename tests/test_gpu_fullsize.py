@@ -144,13 +144,17 @@ def test_64cubed_with_eight_32cubed_chains_in_one_batch(g):
         assert r.dseff == a.dseff
 
 
-@pytest.mark.parametrize("vectors", [0, 1])
-def test_benchmark_batch_sampled_against_oracle(g, vectors):
-    # The benchmark's launch configuration: 64 chains of 32^3, M = 2048, FP32
-    # recursion, T = 0.02..0.2 t, uniform-sphere starts drawn on the device
-    # (seed 7, chain_id = chain index), autotuned launch shape.  One batched
-    # proposal; sampled chains are checked against the oracle one proposal at
-    # a time, the decisions of the sampled chains taken from the oracle.
+@pytest.mark.parametrize("vectors,tuning", [(0, None), (0, (2, 2, 256)), (0, (1, 2, 512)),
+                                            (1, None)])
+def test_benchmark_batch_sampled_against_oracle(g, vectors, tuning):
+    # The benchmark's workload: 64 chains of 32^3, M = 2048, FP32 recursion,
+    # T = 0.02..0.2 t, uniform-sphere starts drawn on the device (seed 7,
+    # chain_id = chain index), with the autotuned launch shape and with the
+    # two shapes the benchmark's autotuner picks for it (two site pairs of a
+    # y column per thread, or one with 512-thread blocks; two lanes).  One
+    # batched proposal; sampled chains are checked against the oracle one
+    # proposal at a time, the decisions of the sampled chains taken from the
+    # oracle.
     import synth
     L, M, n = 32, 2048, 64
     temps = synth.temperature_ladder(n, 0.02, 0.2)
@@ -160,7 +164,13 @@ def test_benchmark_batch_sampled_against_oracle(g, vectors):
     for ch in chs:
         ch.init_spins(g.INIT_RANDOM)
     b = g.Batch(chs)
-    ppt = b.autotune(16)
+    if tuning is None:
+        ppt = b.autotune(16)
+    else:
+        ppt, lanes, bt = tuning
+        b.set_lanes(lanes)
+        b.set_block_threads(bt)
+        b.set_tuning(ppt)
     sample = [0, 37, 63] if vectors == 0 else [11, 50]
     force = np.full(n, -1, dtype=np.int32)
     ref = {}
