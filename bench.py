@@ -384,8 +384,8 @@ SERVING_MIXES = {
     "small": ((4, 6, 8, 12, 16), (0.3, 0.25, 0.25, 0.15, 0.05), 6.0),
     # the serving workload's sizes whose sweeps finish within minutes on one GPU
     "large": ((8, 16, 24, 32), (0.4, 0.3, 0.2, 0.1), 0.3),
-    # the serving workload as specified: L uniform in {8, 16, 24, 32, 48}
-    "survey": ((8, 16, 24, 32, 48), (0.2, 0.2, 0.2, 0.2, 0.2), None),
+    # the full serving workload: L uniform in {8, 16, 24, 32, 48}
+    "full": ((8, 16, 24, 32, 48), (0.2, 0.2, 0.2, 0.2, 0.2), None),
 }
 
 

@@ -301,7 +301,9 @@ gfmc_status gfmc_batch_sweep(gfmc_batch* batch, int32_t nsweeps, double* magneti
 gfmc_status gfmc_batch_use_graph(gfmc_batch* batch, int32_t enable);
 
 /* Launch shape of the Chebyshev steps: 1 or 2 site pairs per thread of the
- * multi-block step kernel (one launch per step), or 0 for one LDS-resident
+ * multi-block step kernel (one launch per step; with 2, the pair form and the
+ * FP32 7-vector form take the two pairs from one y column of a z-plane and
+ * share their y neighbours' loads), or 0 for one LDS-resident
  * workgroup per chain that runs all M/2 steps in a single launch (every
  * chain must fit: 128 B/site FP32, 232 B/site FP64 within 140 KB, i.e. up
  * to 10^3 FP32 / 8^3 FP64, 7 site start vectors, recomputed hoppings).
