@@ -107,7 +107,8 @@ def test_step_granular_uneven_counts_and_validation(g):
         assert np.array_equal(gth, th) and np.array_equal(gph, ph)
 
 
-@pytest.mark.parametrize("L,M,prec", [(16, 256, 0), (12, 128, 1), (10, 64, 0), (24, 64, 1)])
+@pytest.mark.parametrize("L,M,prec", [(16, 256, 0), (12, 128, 1), (10, 64, 0), (24, 64, 1),
+                                      (14, 128, 1), (20, 64, 0)])
 def test_lone_chain_persistent_run_equals_step_launches(g, L, M, prec):
     # A lone chain that fits one compute die runs all M/2 steps of a proposal
     # in one persistent launch; the same chain beside another one in a batch
@@ -123,7 +124,7 @@ def test_lone_chain_persistent_run_equals_step_launches(g, L, M, prec):
     pb = g.Batch([probe])
     # the lone chain takes the persistent path, with blocks of 64 threads while
     # that gives at most 16 blocks, else of 128 or 256 (at most 32 blocks)
-    expected_blocks = {10: 8, 12: 14, 16: 16, 24: 27}[L]
+    expected_blocks = {10: 8, 12: 14, 14: 11, 16: 16, 20: 32, 24: 27}[L]
     assert pb.form()["persistent"] == expected_blocks
     pb.close()
     lone = g.Chain(p)
