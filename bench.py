@@ -632,8 +632,9 @@ def fp32_accuracy(g, sites: int = 16, sizes=(2, 4, 6, 8, 10, 12, 16, 24, 32, 48,
 
 def chain_sweep(g, torch):
     """Step-kernel time and algorithmic bandwidth of 32^3, M = 2048 batches of
-    8..128 chains (FP32 and FP64), both launch shapes: shows where the chains'
-    data stops fitting the 256 MB last-level cache."""
+    8..128 chains (FP32 and FP64), both launch shapes, one or two lanes, 256-
+    or 512-thread blocks: shows where the chains' data stops fitting the 256 MB
+    last-level cache."""
     for prec in (g.FP32_ACC64, g.FP64):
         for nch in (8, 16, 32, 64, 128):
             chs = [g.Chain(g.Params(L=L, M=M, beta=20.0, precision=prec, seed=SEED, chain_id=c))
@@ -642,15 +643,17 @@ def chain_sweep(g, torch):
                 c.init_spins(g.INIT_RANDOM)
             b = g.Batch(chs)
             bps, _ = chs[0].step_bytes()
-            for ppt, lanes in ((1, 1), (2, 1), (1, 2), (2, 2)):
+            for bt, ppt, lanes in ((256, 1, 1), (256, 2, 1), (256, 1, 2), (256, 2, 2),
+                                   (512, 1, 1), (512, 1, 2)):
                 b.set_lanes(lanes)
+                b.set_block_threads(bt)
                 b.set_tuning(ppt)
                 b.step(1)
                 b.step(2)
                 ms, nl = b.step_timing()
                 us = ms * 1e3 / nl
                 print(json.dumps({"mode": "chain_sweep", "precision": "f32" if prec else "f64",
-                                  "chains": nch, "pairs_per_thread": ppt,
+                                  "chains": nch, "pairs_per_thread": ppt, "block_threads": bt,
                                   "lanes": b.tuning()[1], "avg_round_us": us,
                                   "achieved_GBs": nch * bps / (us * 1e-6) / 1e9,
                                   "bytes_per_round": nch * bps}), flush=True)
