@@ -127,6 +127,36 @@ def test_engine_admits_smaller_requests_past_one_that_does_not_fit(g):
     assert res[idc].t_admit < res[idb].t_admit   # C was admitted before B
     eng.close()
 
+
+def test_engine_holds_admission_for_a_request_that_waited(g):
+    # A request that has waited 10 s without fitting holds admission: a small
+    # request submitted after that waits behind it (no starvation of large
+    # requests by a stream of small ones).  Same sizes as above.
+    pa = g.Params(L=16, M=1024, seed=1)
+    pb = g.Params(L=12, M=512, seed=2)
+    pc = g.Params(L=4, M=64, seed=3)
+    al = lambda n: (n + 255) // 256 * 256
+    wa, wb, wc = (al(g.gfmc_workspace_bytes(p)) for p in (pa, pb, pc))
+    eng = g.Engine(0, hbm_budget_bytes=wa + wb - 256, max_slots=4)
+    ida = eng.submit(pa, nsweeps=100000)
+    st = _wait_status(eng, lambda st: st["running"] == 1)
+    assert st["running"] == 1, st
+    idb = eng.submit(pb, nsweeps=100000)
+    time.sleep(10.5)
+    idc = eng.submit(pc, nsweeps=100000)
+    time.sleep(1.0)
+    st = eng.status()
+    assert st["running"] == 1 and st["queued"] == 2, st   # C waits behind B
+    eng.cancel(ida)   # B goes in, then C
+    st = _wait_status(eng, lambda st: st["running"] == 3 or (st["running"] == 2 and st["queued"] == 0))
+    assert st["queued"] == 0, st
+    for i in (idb, idc):
+        eng.cancel(i)
+    eng.drain(120)
+    res = {r.request_id: r for r in eng.poll()}
+    assert res[idb].t_admit <= res[idc].t_admit
+    eng.close()
+
 MIXED = [  # L, M, T, precision: LDS-resident (L <= 10 FP32, L <= 8 FP64) and multi-block chains
     (4, 128, 0.05, 1),
     (10, 64, 0.1, 0),
