@@ -144,6 +144,81 @@ def test_64cubed_with_eight_32cubed_chains_in_one_batch(g):
         assert r.dseff == a.dseff
 
 
+@pytest.mark.parametrize("tuning", [(1, 2, 512), (2, 2, 256)])
+def test_mixed_benchmark_batch_against_oracle(g, tuning):
+    # The mixed benchmark's workload: one 64^3 chain (M = 4096, chain_id 0)
+    # and eight 32^3 chains (M = 2048, chain_id 1..8), FP32 recursion,
+    # beta = 20, seed 11, uniform-sphere starts drawn on the device, in the
+    # launch shapes its autotuner picks (one site pair per thread in
+    # 512-thread blocks, or two pairs of a y column; two lanes).
+    # A lock-step proposal with forced decisions: the 64^3 chain's against the
+    # oracle's stored first proposal, two 32^3 chains against the oracle.
+    # Then one step-granular window (2048 rounds) from there: the 32^3 chains
+    # make two proposals, the 64^3 chain one, and each chain ends where it
+    # ends alone (a batch of its own with the same launch shape): spins bit
+    # for bit.
+    import json
+    import os
+    ppt, lanes, bt = tuning
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_dseff_64cubed.json")
+    gold = json.load(open(path))["proposals"][0]
+    specs = [(64, 4096, 0)] + [(32, 2048, 1 + c) for c in range(8)]
+
+    def chain(L, M, cid):
+        ch = g.Chain(g.Params(L=L, M=M, beta=20.0, precision=1, seed=11, chain_id=cid))
+        ch.init_spins(g.INIT_RANDOM)
+        return ch
+
+    def shape(b, nl):
+        b.set_tuning(ppt)
+        b.set_lanes(nl)
+        b.set_block_threads(bt)
+
+    sample = [2, 7]
+    force = np.full(len(specs), -1, dtype=np.int32)
+    force[0] = gold["accepted"]
+    ref = {}
+    for i in sample:
+        L, M, cid = specs[i]
+        m = oracle.Model(L=L, M=M, beta=20.0, seed=11, chain_id=cid)
+        th, ph = oracle.init_spins(m, 0)
+        ref[i] = oracle.step(m, th, ph, 0)
+        force[i] = ref[i].accepted
+    chs = [chain(*s) for s in specs]
+    b = g.Batch(chs)
+    shape(b, lanes)
+    recs = b.step(1, force=force, records=True)[0]
+    r = recs[0]
+    print(f"mixed shape={tuning} 64^3: dS={gold['dseff']:.9f} err={r.dseff - gold['dseff']:.2e}",
+          flush=True)
+    assert (r.index, r.site, r.u, r.accepted) == (gold["index"], gold["site"], gold["u"],
+                                                  gold["accepted"])
+    assert abs(r.dseff - gold["dseff"]) < 2e-5
+    for i in sample:
+        a, o = recs[i], ref[i]
+        print(f"mixed shape={tuning} 32^3 chain {i}: dS={o.dseff:.9f} err={a.dseff - o.dseff:.2e}",
+              flush=True)
+        assert (a.site, a.u, a.accepted) == (o.site, o.u, o.accepted)
+        assert abs(a.dseff - o.dseff) < 2e-5
+    b.set_schedule(True)
+    b.step(1)
+    counters = [c.get_counter() for c in chs]
+    assert counters == [2] + [3] * 8
+    got = [c.get_spins() for c in chs]
+    b.close()
+    for i, (L, M, cid) in enumerate(specs):
+        ch = chain(L, M, cid)
+        bb = g.Batch([ch])
+        shape(bb, 1)
+        assert bb.form()["persistent"] == 0 and bb.form()["resident"] == 0
+        bb.step(1, force=force[i:i + 1])
+        bb.step(counters[i] - 1)
+        bb.close()
+        th, ph = ch.get_spins()
+        assert ch.get_counter() == counters[i]
+        assert np.array_equal(th, got[i][0]) and np.array_equal(ph, got[i][1])
+
+
 @pytest.mark.parametrize("vectors,tuning", [(0, None), (0, (2, 2, 256)), (0, (1, 2, 512)),
                                             (1, None)])
 def test_benchmark_batch_sampled_against_oracle(g, vectors, tuning):
