@@ -495,7 +495,7 @@ gfmc_status gfmc_stream_bandwidth(int32_t mode, const void* a, const void* b, vo
                                   size_t bytes, int32_t reps, void* stream, double* gbs);
 
 /* ------------------------------------------------------------------ misc -- */
-const char* gfmc_status_string(gfmc_status status);
+const char* gfmc_status_string(int32_t status);   /* any value: unknown ones named so */
 const char* gfmc_last_error(void);
 const char* gfmc_version(void);
 

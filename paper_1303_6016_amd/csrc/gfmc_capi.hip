@@ -61,20 +61,21 @@ gfmc_status derive(const gfmc_chain_params* p, Derived& d) {
     return fail(GFMC_EINVAL, "K must be a power of two with M <= K <= 8192");
   if (p->scale_b != 0.0) return fail(GFMC_EINVAL, "scale_b must be 0 on the device path");
   if (p->scale_a < 0 || !std::isfinite(p->scale_a)) return fail(GFMC_EINVAL, "scale_a must be >= 0");
-  if (p->kernel != GFMC_JACKSON && p->kernel != GFMC_LORENTZ)
-    return fail(GFMC_EINVAL, "unknown kernel");
-  if (p->precision != GFMC_FP64 && p->precision != GFMC_FP32_ACC64)
+  const int32_t kernel = gfmc_enum_value(p->kernel), precision = gfmc_enum_value(p->precision);
+  const int32_t proposal = gfmc_enum_value(p->proposal), vectors = gfmc_enum_value(p->vectors);
+  const int32_t hoppings = gfmc_enum_value(p->hoppings);
+  if (kernel != GFMC_JACKSON && kernel != GFMC_LORENTZ) return fail(GFMC_EINVAL, "unknown kernel");
+  if (precision != GFMC_FP64 && precision != GFMC_FP32_ACC64)
     return fail(GFMC_EINVAL, "unknown precision");
-  if (p->proposal != GFMC_PROPOSE_SPHERE && p->proposal != GFMC_PROPOSE_CONE)
+  if (proposal != GFMC_PROPOSE_SPHERE && proposal != GFMC_PROPOSE_CONE)
     return fail(GFMC_EINVAL, "unknown proposal");
+  if (vectors != GFMC_VECTORS_SITES && vectors != GFMC_VECTORS_OV && vectors != GFMC_VECTORS_MIXED)
+    return fail(GFMC_EINVAL, "unknown start-vector form");
+  if (hoppings != GFMC_HOP_RECOMPUTE && hoppings != GFMC_HOP_STORED)
+    return fail(GFMC_EINVAL, "unknown hopping mode");
   if (p->proposal == GFMC_PROPOSE_CONE && !(p->cone_angle > 0 && p->cone_angle <= M_PI))
     return fail(GFMC_EINVAL, "cone_angle must be in (0, pi]");
   if (p->kernel == GFMC_LORENTZ && p->lorentz_lambda < 0) return fail(GFMC_EINVAL, "lambda < 0");
-  if (p->vectors != GFMC_VECTORS_SITES && p->vectors != GFMC_VECTORS_OV &&
-      p->vectors != GFMC_VECTORS_MIXED)
-    return fail(GFMC_EINVAL, "unknown start-vector form");
-  if (p->hoppings != GFMC_HOP_RECOMPUTE && p->hoppings != GFMC_HOP_STORED)
-    return fail(GFMC_EINVAL, "unknown hopping mode");
   if (p->hoppings == GFMC_HOP_STORED && p->vectors != GFMC_VECTORS_SITES)
     return fail(GFMC_EINVAL, "stored hoppings need the 7 site start vectors");
   if (p->fp32_unvalidated != 0 && p->fp32_unvalidated != 1)
@@ -682,7 +683,7 @@ gfmc_status chain_init_spins(gfmc_chain* c, int mode, double frac) {
 // ====================================================================== ABI
 extern "C" {
 
-const char* gfmc_status_string(gfmc_status s) {
+const char* gfmc_status_string(int32_t s) {
   switch (s) {
     case GFMC_OK: return "ok";
     case GFMC_EINVAL: return "invalid argument";
@@ -753,7 +754,8 @@ gfmc_status gfmc_set_params(gfmc_chain* c, double t, double beta, double mu) {
 
 gfmc_status gfmc_init_spins(gfmc_chain* c, gfmc_init mode, double frac) {
   CHK(check_chain(c));
-  if (mode != GFMC_INIT_RANDOM && mode != GFMC_INIT_FM && mode != GFMC_INIT_FM_PLUS_RANDOM)
+  const int32_t m = gfmc_enum_value(mode);
+  if (m != GFMC_INIT_RANDOM && m != GFMC_INIT_FM && m != GFMC_INIT_FM_PLUS_RANDOM)
     return fail(GFMC_EINVAL, "unknown init mode");
   if (mode == GFMC_INIT_FM_PLUS_RANDOM && !(frac >= 0 && frac <= 1))
     return fail(GFMC_EINVAL, "random_fraction must be in [0, 1]");

@@ -536,7 +536,8 @@ gfmc_status gfmc_engine_submit(gfmc_engine* E, const gfmc_chain_params* p, gfmc_
   Derived d;
   CHK(derive(p, d));
   if (nsweeps < 1) return gfmc_fail(GFMC_EINVAL, "nsweeps must be >= 1");
-  if (init != GFMC_INIT_RANDOM && init != GFMC_INIT_FM && init != GFMC_INIT_FM_PLUS_RANDOM)
+  const int32_t im = gfmc_enum_value(init);
+  if (im != GFMC_INIT_RANDOM && im != GFMC_INIT_FM && im != GFMC_INIT_FM_PLUS_RANDOM)
     return gfmc_fail(GFMC_EINVAL, "unknown init mode");
   if (init == GFMC_INIT_FM_PLUS_RANDOM && !(frac >= 0 && frac <= 1))
     return gfmc_fail(GFMC_EINVAL, "random_fraction must be in [0, 1]");

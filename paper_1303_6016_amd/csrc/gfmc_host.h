@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -43,6 +45,17 @@ hipError_t launch_mixed_series(const Desc* d, int M, double* out, hipStream_t st
 using namespace gfmc;
 
 gfmc_status gfmc_fail(gfmc_status s, const std::string& msg);
+
+// Enum-typed arguments and fields arrive from C callers and language bindings
+// as 32-bit integers of any value; they are validated as integers, read from
+// their bytes, before anything reads them as their enum type.
+template <typename E>
+inline int32_t gfmc_enum_value(const E& v) {
+  static_assert(sizeof(E) == sizeof(int32_t), "enums of the C ABI are 32-bit");
+  int32_t r;
+  std::memcpy(&r, &v, sizeof r);
+  return r;
+}
 
 #define HIPCHK(expr)                                                                       \
   do {                                                                                     \
