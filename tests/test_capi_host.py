@@ -37,7 +37,8 @@ def _bytes(**kw):
                                 dict(L=4, proposal=1, cone_angle=0.0), dict(L=4, precision=5),
                                 dict(L=4, M=16384), dict(L=4, vectors=1, hoppings=1),
                                 dict(L=4, vectors=3), dict(L=4, vectors=2, hoppings=1),
-                                dict(L=4, hoppings=3)])
+                                dict(L=4, hoppings=3), dict(L=4, kernel=-1),
+                                dict(L=4, proposal=7), dict(L=4, precision=-2**31)])
 def test_invalid_parameters_are_rejected(kw):
     import paper_1303_6016_amd as g
     with pytest.raises(g.GfmcError) as e:
@@ -78,6 +79,10 @@ def test_null_handles_and_bad_arguments_are_rejected_on_the_host():
     assert e.value.status == EINVAL
     assert L.gfmc_chain_destroy(None) == g.GFMC_OK and L.gfmc_batch_destroy(None) == g.GFMC_OK
     assert L.gfmc_last_error()
+    # status codes are taken as plain integers: any value has a text
+    assert L.gfmc_status_string(EINVAL) == b"invalid argument"
+    for v in (1, 7, -7, 2 ** 31 - 1, -2 ** 31):
+        assert L.gfmc_status_string(v) == b"unknown status"
 
 
 # The validated range of the FP32 recursion (include/gfmc.h, gfmc_precision):
